@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only draws point sets (numpy ``default_rng``); it holds none of
+the method's arithmetic. Shapes and value distributions follow the paper's
+workloads (Sec. 4: clustered Gaussian data, image-shaped 784-d data standing
+in for MNIST, large low-d clustered data), none of which ships with the paper.
+
+Every generator returns float32 ``X[N, d]`` plus a dict of the parameters the
+method runs with (K, rho, delta, max_iters, seed).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = ["config", "CONFIGS", "gaussian_mixture", "integer_points", "image_like",
+           "lowd_blobs", "anisotropic_clusters", "batched_datasets", "clustered_labels"]
+
+
+def gaussian_mixture(N: int, d: int, n_centres: int, seed: int, lo: float = -10.0,
+                     hi: float = 10.0, sigma: float = 1.0, return_labels: bool = False):
+    """Isotropic Gaussian mixture: centres U[lo,hi]^d, uniform labels, x = c + sigma*N(0,I)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(lo, hi, (n_centres, d))
+    labels = rng.integers(0, n_centres, N)
+    X = (centres[labels] + sigma * rng.standard_normal((N, d))).astype(np.float32)
+    return (X, labels) if return_labels else X
+
+
+def integer_points(N: int, d: int, hi: int, seed: int) -> np.ndarray:
+    """Small non-negative integer coordinates in [0, hi]: every FP32 sum below 2^24
+    is exact, so FP32 and FP64 distances agree bit for bit."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, hi + 1, (N, d)).astype(np.float32)
+
+
+def clustered_labels(N: int, d: int, n_clusters: int, seed: int, spread: float = 0.5):
+    """Clustered dataset in the sense of Sec. 3.2 (every point's nearest
+    neighbours lie in its own cluster): well separated centres."""
+    return gaussian_mixture(N, d, n_clusters, seed, -10.0, 10.0, spread, return_labels=True)
+
+
+def _bump_field(rng, side: int, n_bumps: int) -> np.ndarray:
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
+    f = np.zeros((side, side))
+    for _ in range(n_bumps):
+        cy, cx = rng.uniform(6, side - 6, 2)
+        sy, sx = rng.uniform(1.5, 4.0, 2)
+        f += rng.uniform(0.6, 1.0) * np.exp(-0.5 * (((yy - cy) / sy) ** 2 + ((xx - cx) / sx) ** 2))
+    return f / f.max()
+
+
+def image_like(N: int = 60000, seed: int = 1, side: int = 28, n_protos: int = 10,
+               on_frac: float = 0.2, drop: float = 0.1, noise: float = 0.03,
+               return_labels: bool = False):
+    """784-d image-shaped integers in [0, 255], ~80% zeros (stand-in for MNIST, Sec. 4).
+
+    10 prototypes are smooth fields (sums of Gaussian bumps) thresholded to the
+    top ``on_frac`` pixels; a point picks a prototype, scales its intensities by
+    U(0.6, 1), drops each on-pixel with probability ``drop`` and sets each pixel
+    with probability ``noise`` to U{1..255}; values are rounded and clipped.
+    Squared norms stay below 2^23, so all pair distances are exact in FP32.
+    """
+    rng = np.random.default_rng(seed)
+    protos = []
+    for _ in range(n_protos):
+        f = _bump_field(rng, side, int(rng.integers(3, 7)))
+        thr = np.quantile(f, 1.0 - on_frac)
+        p = np.where(f >= thr, 90.0 + 165.0 * (f - thr) / max(1e-12, 1.0 - thr), 0.0)
+        protos.append(p.reshape(-1))
+    protos = np.stack(protos)
+    d = side * side
+    labels = rng.integers(0, n_protos, N)
+    X = np.empty((N, d), np.float32)
+    for s in range(0, N, 8192):
+        n = min(8192, N - s)
+        base = protos[labels[s:s + n]] * rng.uniform(0.6, 1.0, (n, 1))
+        keep = rng.random((n, d)) >= drop
+        v = base * keep
+        nz = rng.random((n, d)) < noise
+        v = np.where(nz, rng.integers(1, 256, (n, d)).astype(np.float64), v)
+        X[s:s + n] = np.clip(np.rint(v), 0, 255)
+    return (X, labels) if return_labels else X
+
+
+def lowd_blobs(N: int = 4_000_000, seed: int = 2, n_blobs: int = 1000, sigma: float = 0.01,
+               background: float = 0.1, return_labels: bool = False):
+    """3-d: Gaussian blobs (sigma) around U[0,1]^3 centres plus uniform background,
+    rows shuffled into random memory order. Label -1 marks background."""
+    rng = np.random.default_rng(seed)
+    nb = int(round(N * background))
+    nc = N - nb
+    centres = rng.uniform(0.0, 1.0, (n_blobs, 3))
+    lab = rng.integers(0, n_blobs, nc)
+    X = np.empty((N, 3), np.float32)
+    X[:nc] = centres[lab] + sigma * rng.standard_normal((nc, 3))
+    X[nc:] = rng.uniform(0.0, 1.0, (nb, 3))
+    labels = np.concatenate([lab, -np.ones(nb, np.int64)])
+    perm = rng.permutation(N)
+    X = X[perm]
+    labels = labels[perm]
+    return (X, labels) if return_labels else X
+
+
+def anisotropic_clusters(N: int = 200_000, d: int = 960, seed: int = 3, n_clusters: int = 100):
+    """Centres U[-1,1]^d; per-cluster per-dimension sigma = 10^U(-1,0); x = c + sigma*N(0,I)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-1.0, 1.0, (n_clusters, d)).astype(np.float32)
+    sig = (10.0 ** rng.uniform(-1.0, 0.0, (n_clusters, d))).astype(np.float32)
+    lab = rng.integers(0, n_clusters, N)
+    X = np.empty((N, d), np.float32)
+    for s in range(0, N, 16384):
+        n = min(16384, N - s)
+        l = lab[s:s + n]
+        X[s:s + n] = centres[l] + sig[l] * rng.standard_normal((n, d), dtype=np.float32)
+    return X
+
+
+def batched_datasets(count: int = 512, seed: int = 4, n_lo: int = 500, n_hi: int = 20000,
+                     dims=(16, 64, 128)):
+    """Independent Gaussian-mixture datasets of uneven N and d.
+
+    N_i = round(exp(U(ln n_lo, ln n_hi))), d_i uniform over ``dims``, 5..20
+    components with centres U[-10,10]^d and sigma 1, per-dataset seeds drawn
+    from the master generator. Returns a list of (X_i, seed_i)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        d = int(dims[int(rng.integers(0, len(dims)))])
+        comps = int(rng.integers(5, 21))
+        s = int(rng.integers(0, 2**31 - 1))
+        out.append((gaussian_mixture(n, d, comps, s), s))
+    return out
+
+
+# Method parameters per workload. max_iters for the large cases and the seeds
+# of configs 3 and 4 are readings (the workload text leaves them open).
+CONFIGS = {
+    1: dict(name="gauss2k_d8", K=10, rho=1.0, delta=0.001, max_iters=20, seed=0),
+    2: dict(name="image60k_d784", K=20, rho=1.0, delta=0.001, max_iters=30, seed=1),
+    3: dict(name="blobs4m_d3", K=15, rho=0.5, delta=0.001, max_iters=30, seed=2),
+    4: dict(name="aniso200k_d960", K=20, rho=0.5, delta=0.001, max_iters=30, seed=3),
+    5: dict(name="batch512", K=15, rho=1.0, delta=0.001, max_iters=30, seed=4),
+}
+
+
+def config(i: int, N: int | None = None):
+    """(X, params) for workload i (1..4). ``N`` shrinks the point count (tests)."""
+    p = dict(CONFIGS[i])
+    if i == 1:
+        X = gaussian_mixture(N or 2000, 8, 10, 0)
+    elif i == 2:
+        X = image_like(N or 60000, 1)
+    elif i == 3:
+        X = lowd_blobs(N or 4_000_000, 2)
+    elif i == 4:
+        X = anisotropic_clusters(N or 200_000, 960, 3)
+    else:
+        raise ValueError("config 5 is a batch: use batched_datasets()")
+    return X, p

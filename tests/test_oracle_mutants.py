@@ -1,0 +1,49 @@
+"""Planted mistakes in the oracle (CPU only) must each fail at least one pin.
+
+Each mutant is a one-line textual change of oracle/knng_oracle.c, compiled to
+a temporary library and run against tests/test_oracle_pins.py in a child
+process. A mutant that passes every pin would show a gap in the pins.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "knng_oracle.c")
+
+MUTANTS = {
+    "reverse_neighbours_dropped": ("for (int64_t r = roff[u]; r < roff[u + 1]; ++r) {",
+                                   "for (int64_t r = roff[u]; r < roff[u]; ++r) {"),
+    "tie_break_reversed": ("return da < db || (da == db && ia < ib);",
+                           "return da < db || (da == db && ia > ib);"),
+    "no_new_to_old_flip": ("if (f == ORC_NEW) {", "if (0) {"),
+    "distance_drops_last_dim": ("for (int64_t j = 0; j < d; ++j) {", "for (int64_t j = 0; j + 1 < d; ++j) {"),
+    "old_keeps_new_members": ("if (!in_new) old_raw[co++] = old_raw[i];", "old_raw[co++] = old_raw[i];"),
+    "duplicate_tuples_kept": ("if (i > 0 && cmp_cand(&pool[i - 1], &pool[i]) == 0) continue;", ";"),
+    "new_new_pairs_skipped": ("for (int32_t j = i + 1; j < nnew[u]; ++j) {", "for (int32_t j = i + 1; j < 0; ++j) {"),
+    "hash_constant_typo": ("0x94D049BB133111EBULL", "0x94D049BB133111EAULL"),
+    "init_allows_self": ("if ((int64_t)c >= u) c += 1;", ";"),
+    "merge_readds_listed_ids": ("if (!in_list) all[n++] = cand[i];", "all[n++] = cand[i];"),
+    "weight_not_symmetric": ("uint32_t a = (uint32_t)(u < x ? u : x), b = (uint32_t)(u < x ? x : u);",
+                             "uint32_t a = (uint32_t)x, b = (uint32_t)u;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation anchor not found: " + old
+    with tempfile.TemporaryDirectory() as tmp:
+        c = os.path.join(tmp, "mut.c")
+        so = os.path.join(tmp, "libmut.so")
+        open(c, "w").write(src.replace(old, new, 1))
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", so, c, "-lm"])
+        env = dict(os.environ, KNNG_ORACLE_LIB=so, OMP_NUM_THREADS="4")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"

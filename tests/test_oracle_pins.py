@@ -1,0 +1,292 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a published reference output,
+a closed form, a textbook routine (numpy sort / brute force), an invariant of
+the method, or a statistical property stated in the paper. Paper citations are
+to Kluser et al., arXiv 2112.06630.
+"""
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------- hash
+
+def test_mix64_matches_splitmix64_reference_outputs(oracle_lib):
+    """SplitMix64 (seed 0) reference outputs pin the mix64 output function."""
+    vals = [int(l, 16) for l in open(os.path.join(HERE, "golden", "splitmix64_seed0.txt"))
+            if l.startswith("0x")]
+    state = 0
+    for v in vals:
+        state = (state + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+        assert oracle.mix64(state) == v
+
+
+def test_hash_weights_are_uniform(oracle_lib):
+    """Sampling weights must be uniform in [0, 2^32) (Sec. 3.1 draws them u.a.r.):
+    chi-square over 64 bins, and distinct (t, pair) inputs decorrelate."""
+    w = np.array([oracle.hash64(7, 2, t, a, a + 1 + b) >> 32
+                  for t in range(1, 5) for a in range(60) for b in range(60)], np.float64)
+    hist, _ = np.histogram(w, bins=64, range=(0, 2.0**32))
+    exp = len(w) / 64
+    chi2 = ((hist - exp) ** 2 / exp).sum()
+    assert chi2 < 120  # 63 dof, p ~ 1e-5
+    assert len(np.unique(w)) == len(w)
+
+
+# --------------------------------------------------------------------------- distances / brute force
+
+def test_dist_matches_numpy_on_integer_points(oracle_lib):
+    X = synth.integer_points(50, 7, 30, 1)
+    ids = np.tile(np.arange(50, dtype=np.int32), (50, 1))
+    D = oracle.list_dists(X, ids)
+    ref = ((X.astype(np.float64)[:, None, :] - X.astype(np.float64)[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(D, ref)
+
+
+@pytest.mark.parametrize("N,d,K,seed", [(60, 3, 5, 0), (100, 8, 10, 1), (37, 1, 36, 2)])
+def test_bruteforce_matches_numpy_lexsort(oracle_lib, N, d, K, seed):
+    """Sec. 2: the exact K-NNG keeps the k nearest others; (dist, id) tie-break.
+    Integer data makes ties frequent, so the tie-break is exercised."""
+    X = synth.integer_points(N, d, 4, seed)
+    ids, dists = oracle.bruteforce(X, K)
+    Xd = X.astype(np.float64)
+    D = ((Xd[:, None, :] - Xd[None, :, :]) ** 2).sum(-1)
+    for p in range(N):
+        order = np.lexsort((np.arange(N), D[p]))
+        order = order[order != p][:K]
+        assert np.array_equal(ids[p], order)
+        assert np.array_equal(dists[p], D[p, order])
+
+
+# --------------------------------------------------------------------------- init
+
+def test_init_rows_are_distinct_nonself_sorted(oracle_lib):
+    X = synth.integer_points(300, 4, 5, 3)
+    st = oracle.init(X, 12, 99)
+    D = oracle.list_dists(X, st.ids)
+    for u in range(300):
+        row = st.ids[u]
+        assert len(set(row.tolist())) == 12 and u not in row
+        keys = list(zip(st.dists[u], row))
+        assert keys == sorted(keys)
+    assert np.array_equal(D, st.dists)
+    assert (st.flags == oracle.NEW).all()
+
+
+def test_init_complete_graph_when_N_is_K_plus_1(oracle_lib):
+    """N = K + 1 leaves no choice: every list holds all other points, in (dist, id) order."""
+    X = synth.integer_points(11, 2, 3, 5)
+    st = oracle.init(X, 10, 1234)
+    ids, dists = oracle.bruteforce(X, 10)
+    assert np.array_equal(st.ids, ids) and np.array_equal(st.dists, dists)
+
+
+def test_init_ids_uniform(oracle_lib):
+    """Sec. 2: initial neighbours are drawn uniformly from V (chi-square on frequencies)."""
+    N, K = 400, 10
+    X = np.zeros((N, 1), np.float32)
+    cnt = np.zeros(N)
+    for s in range(10):
+        st = oracle.init(X, K, s)
+        np.add.at(cnt, st.ids.reshape(-1), 1)
+    exp = cnt.sum() / N
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < N + 5 * math.sqrt(2 * N)
+
+
+def test_init_cluster_miss_rate_bound(oracle_lib):
+    """Sec. 3.2: Pr[none of k random neighbours in the own cluster] <= ((c-1)/c)^k.
+    Sampling without replacement makes the rate slightly lower than the bound."""
+    N, K, c = 4000, 10, 10
+    X, lab = synth.clustered_labels(N, 4, c, 11)
+    st = oracle.init(X, K, 5)
+    miss = np.mean([(lab[st.ids[u]] != lab[u]).all() for u in range(N)])
+    bound = ((c - 1) / c) ** K
+    assert miss <= bound + 3 * math.sqrt(bound * (1 - bound) / N)
+    assert miss >= 0.75 * bound
+
+
+# --------------------------------------------------------------------------- sample
+
+def _rev(st):
+    N = st.ids.shape[0]
+    rev = [set() for _ in range(N)]
+    for u in range(N):
+        for v in st.ids[u]:
+            rev[v].add(u)
+    return rev
+
+
+def test_sample_bounds_and_membership(oracle_lib):
+    """Sec. 3.1: N(u) draws from forward and reverse neighbours, bounded by rho*k per flag."""
+    X, p = synth.config(1, N=600)
+    K, C = 10, oracle.cap(10, 0.5)
+    r = oracle.build_graph(X, K, 0.5, 0.0, 2, 3)
+    st = oracle.State(r.ids, r.dists, r.flags, 2)
+    sm = oracle.sample(st, K, C, 3, 3)
+    rev = _rev(st)
+    for u in range(600):
+        nw, od = set(sm.cnew[u].tolist()), set(sm.cold[u].tolist())
+        assert len(nw) == len(sm.cnew[u]) <= C and len(od) == len(sm.cold[u]) <= C
+        assert not (nw & od)
+        assert (nw | od) <= (set(st.ids[u].tolist()) | rev[u])
+        assert u not in nw | od
+
+
+def test_sample_complete_graph_selects_everyone_and_flips(oracle_lib):
+    """N = K + 1 with C = K: the pool is every other point (forward and reverse
+    routes give the identical tuple, counted once), so all are sampled new, all
+    forward entries flip to OLD, e_1 = N*K(K-1)/2, nothing changes, and a second
+    iteration has no new member left (e_2 = 0)."""
+    N, K = 9, 8
+    X = synth.integer_points(N, 3, 10, 2)
+    st = oracle.init(X, K, 4)
+    sm = oracle.sample(st, K, K, 4, 1)
+    for u in range(N):
+        assert sorted(sm.cnew[u].tolist()) == [v for v in range(N) if v != u]
+        assert len(sm.cold[u]) == 0
+    assert (sm.flags == oracle.OLD).all()
+    s1, e1, c1 = oracle.iterate(X, st, K, K, 4)
+    assert e1 == N * K * (K - 1) // 2 and c1 == 0
+    assert np.array_equal(s1.ids, st.ids)
+    s2, e2, c2 = oracle.iterate(X, s1, K, K, 4)
+    assert e2 == 0 and c2 == 0
+
+
+def test_sample_selection_is_uniform(oracle_lib):
+    """Sec. 3.1: keeping the rho*k smallest u.a.r. weights is a uniform subset.
+    Over many iterations t (fresh weights), every pool member of a fixed node is
+    chosen with frequency C/|pool|."""
+    N, K, C = 200, 10, 3
+    X = np.zeros((N, 1), np.float32)
+    st = oracle.init(X, K, 21)
+    rev = _rev(st)
+    T = 400
+    counts = [dict() for _ in range(N)]
+    for t in range(1, T + 1):
+        sm = oracle.sample(st, K, C, 21, t)
+        for u in range(0, N, 10):
+            for v in sm.cnew[u]:
+                counts[u][int(v)] = counts[u].get(int(v), 0) + 1
+    chi2, dof = 0.0, 0
+    for u in range(0, N, 10):
+        pool = set(st.ids[u].tolist()) | rev[u]
+        exp = T * C / len(pool)
+        for v in pool:
+            chi2 += (counts[u].get(v, 0) - exp) ** 2 / exp
+            dof += 1
+        assert set(counts[u]) <= pool
+    assert chi2 < dof + 5 * math.sqrt(2 * dof)
+
+
+def test_evals_count_closed_form(oracle_lib):
+    """e_t = sum_u [n_new(n_new-1)/2 + n_new*n_old] (new x new and new x old pairs)."""
+    X, _ = synth.config(1, N=500)
+    K, C = 10, 7
+    st = oracle.init(X, K, 8)
+    sm = oracle.sample(st, K, C, 8, 1)
+    exp = sum(len(a) * (len(a) - 1) // 2 + len(a) * len(b) for a, b in zip(sm.cnew, sm.cold))
+    _, e, _ = oracle.iterate(X, st, K, C, 8)
+    assert e == exp
+
+
+# --------------------------------------------------------------------------- join + merge
+
+def test_exact_knn_is_a_fixed_point(oracle_lib):
+    """Feeding the exact K-NNG (all NEW) changes nothing: no proposal can beat it."""
+    X, _ = synth.config(1, N=400)
+    K = 10
+    ids, dists = oracle.bruteforce(X, K)
+    st = oracle.State(ids, dists, np.ones_like(ids, dtype=np.uint8), 0)
+    s1, e, c = oracle.iterate(X, st, K, K, 5)
+    assert c == 0 and e > 0
+    assert np.array_equal(s1.ids, ids) and np.array_equal(s1.dists, dists)
+
+
+def test_iteration_invariants_and_monotone_keys(oracle_lib):
+    """Rows: K distinct non-self ids sorted by (dist, id), stored D = recomputed D;
+    the i-th key of every row never increases, so sum of list distances never increases."""
+    X, p = synth.config(1, N=800)
+    K, C = 10, 10
+    st = oracle.init(X, K, 2)
+    prev_sum = st.dists.sum()
+    for t in range(1, 7):
+        nxt, e, c = oracle.iterate(X, st, K, C, 2)
+        assert np.array_equal(oracle.list_dists(X, nxt.ids), nxt.dists)
+        for u in range(800):
+            assert len(set(nxt.ids[u].tolist())) == K and u not in nxt.ids[u]
+            keys = list(zip(nxt.dists[u], nxt.ids[u]))
+            assert keys == sorted(keys)
+            old = list(zip(st.dists[u], st.ids[u]))
+            assert all(a <= b for a, b in zip(keys, old))
+        s = nxt.dists.sum()
+        assert s <= prev_sum
+        changed = sum(len(set(nxt.ids[u]) - set(st.ids[u])) for u in range(800))
+        assert changed == c
+        prev_sum, st = s, nxt
+
+
+def test_build_reaches_exact_knn_on_small_inputs(oracle_lib):
+    """Sec. 2: NN-Descent approximates the exact K-NNG; the paper reports recall
+    above 99% (Sec. 2). On small clustered inputs the oracle must get there."""
+    X, p = synth.config(1)
+    r = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
+    ei, ed = oracle.bruteforce(X, p["K"])
+    assert oracle.recall(X, r.ids, ed) >= 0.99
+    assert oracle.plain_recall(r.ids, ei) >= 0.99
+    assert r.changes[-1] < p["delta"] * X.shape[0] * p["K"] or r.iters == p["max_iters"]
+
+
+def test_identical_points_pure_id_tiebreak(oracle_lib):
+    """All points equal: every distance is 0 and only ids order the lists."""
+    N, K = 40, 6
+    X = np.full((N, 3), 2.5, np.float32)
+    r = oracle.build_graph(X, K, 1.0, 0.0, 15, 3)
+    for u in range(N):
+        assert (r.dists[u] == 0).all()
+        assert list(r.ids[u]) == sorted(r.ids[u])
+    exact = np.array([[v for v in range(N) if v != u][:K] for u in range(N)])
+    assert oracle.plain_recall(r.ids, exact) >= 0.95
+
+
+def test_stop_rule(oracle_lib):
+    """Sec. 2: iterate until the number of changes falls below the threshold."""
+    X, p = synth.config(1, N=1000)
+    r = oracle.build_graph(X, 10, 1.0, 0.01, 50, 0)
+    thr = 0.01 * 1000 * 10
+    assert r.changes[-1] < thr and (r.changes[:-1] >= thr).all()
+    r0 = oracle.build_graph(X, 10, 1.0, 0.01, 0, 0)
+    assert r0.iters == 0
+
+
+def test_c_build_equals_stepwise_build(oracle_lib):
+    X, p = synth.config(1, N=700)
+    a = oracle.build_graph(X, 10, 0.7, 0.001, 12, 9)
+    b = oracle.build_graph_c(X, 10, 0.7, 0.001, 12, 9)
+    assert a.iters == b.iters
+    assert np.array_equal(a.ids, b.ids) and np.array_equal(a.dists, b.dists)
+    assert np.array_equal(a.evals, b.evals) and np.array_equal(a.changes, b.changes)
+
+
+def test_thread_count_independence(oracle_lib):
+    """Results must not depend on the OpenMP thread count."""
+    code = ("import numpy as np, oracle, synth, sys\n"
+            "X,p=synth.config(1, N=900)\n"
+            "r=oracle.build_graph_c(X,10,0.8,0.001,10,4)\n"
+            "sys.stdout.write(str(hash(r.ids.tobytes()+r.dists.tobytes()+r.evals.tobytes())))\n")
+    outs = []
+    for n in ("1", "5"):
+        env = dict(os.environ, OMP_NUM_THREADS=n, PYTHONHASHSEED="0")
+        outs.append(subprocess.check_output([sys.executable, "-c", code], env=env,
+                                            cwd=os.path.dirname(HERE)))
+    assert outs[0] == outs[1]

@@ -1,0 +1,159 @@
+/*
+ * knng.h — C ABI of the MI355X (gfx950) NN-Descent library, squared-l2 metric.
+ *
+ * Method: Kluser, Bokstaller, Rutz, Buner, "Fast single-core K-Nearest Neighbor
+ * Graph computation" (arXiv 2112.06630). The problem (Sec. 2): for points
+ * X[N,d] in R^d, find for every point u the K nearest other points adj_G(u).
+ * NN-Descent (Sec. 2) starts from a random graph and repeats a selection step
+ * (Sec. 3.1: sample new/old forward and reverse neighbours) and a calculation
+ * step (Sec. 2, Sec. 3.3: squared-l2 distances of the sampled pairs, update the
+ * lists) until the number of changes falls below a threshold.
+ *
+ * The iteration here is synchronous and seeded: every sampling weight is a
+ * counter-based hash of (seed, t, pair) and every list is ordered by the key
+ * (squared distance, original id), so the result does not depend on thread or
+ * update order, and does not depend on the graph-ordered point permutation
+ * (Sec. 3.2) either.
+ *
+ * Memory and ownership. Every pointer named d_* is device memory on the
+ * current HIP device, owned by the caller. The library never allocates device
+ * memory: all scratch lives in the caller's workspace (d_ws, ws_bytes, at
+ * least knng_workspace_bytes()). `stream` is a hipStream_t (NULL = legacy
+ * default stream); all work is ordered on it. Host pointers may be NULL where
+ * marked nullable.
+ *
+ * Errors. Functions return a knng_status. On any status other than KNNG_OK
+ * and KNNG_ENOTCONV the outputs are undefined and knng_last_error() holds a
+ * message (thread-local, valid until the next call on the same thread).
+ *
+ * Thread safety. Calls on different contexts may run concurrently on
+ * different streams; calls on one context must be serialised by the caller.
+ */
+#ifndef KNNG_H
+#define KNNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KNNG_OK = 0,
+    KNNG_EINVAL = 1,     /* invalid argument (bad size, null pointer, non-finite X) */
+    KNNG_ENOMEM = 2,     /* workspace smaller than knng_workspace_bytes() */
+    KNNG_EDEVICE = 3,    /* a HIP runtime call failed */
+    KNNG_ENOTCONV = 4    /* max_iters reached before the stop rule held; results valid */
+} knng_status;
+
+typedef enum {
+    KNNG_FP32 = 0,        /* distances in FP32 */
+    KNNG_BF16_SCREEN = 1  /* reserved: BF16 screening with FP32 rescore */
+} knng_precision;
+
+typedef enum {
+    KNNG_PATH_AUTO = 0,   /* VALU direct form at low d, MFMA Gram tiles at high d */
+    KNNG_PATH_VALU = 1,   /* sum_j (x_j - y_j)^2 on the vector ALUs */
+    KNNG_PATH_MFMA = 2    /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
+} knng_path;
+
+typedef struct {
+    int32_t K;          /* list length, 1 <= K <= 64 and K <= N-1 (Sec. 2: k) */
+    double rho;         /* sample rate, 0 < rho <= 1 (Sec. 3.1: rho*k per neighbourhood) */
+    double delta;       /* stop when changes < delta*N*K (Sec. 2: threshold), delta >= 0 */
+    int32_t max_iters;  /* iteration cap T_max >= 0; 0 returns the random initial graph */
+    uint64_t seed;      /* seed of the counter-based hash */
+    int32_t precision;  /* knng_precision */
+    int32_t reorder;    /* 1: graph-ordered point permutation after iteration 1 (Sec. 3.2) */
+    int32_t path;       /* knng_path */
+} knng_params;
+
+#define KNNG_MAX_ITERS 64
+
+/* Per-build statistics, written to host memory when the pointer is non-NULL.
+ * Times are device times from HIP events on the build's stream. */
+typedef struct {
+    int32_t iters;                        /* iterations run */
+    int32_t converged;                    /* 1 if the stop rule held */
+    int32_t path;                         /* path used (knng_path, resolved) */
+    int32_t dpad;                         /* padded row length in floats */
+    int64_t evals[KNNG_MAX_ITERS];        /* e_t: distance evaluations of iteration t */
+    int64_t changes[KNNG_MAX_ITERS];      /* c_t: ids that entered a list */
+    int64_t proposals[KNNG_MAX_ITERS];    /* proposals that passed the snapshot filter */
+    float iter_ms[KNNG_MAX_ITERS];        /* whole iteration */
+    float sample_ms[KNNG_MAX_ITERS];      /* reverse bucketing + selection */
+    float join_ms[KNNG_MAX_ITERS];        /* local join (pairs, distances, proposals) */
+    float merge_ms[KNNG_MAX_ITERS];       /* top-K merge */
+    float init_ms;                        /* row padding + random initial graph */
+    float reorder_ms;                     /* graph-ordered permutation (0 if off) */
+    float finalize_ms;                    /* write-out in original order */
+    float total_ms;                       /* init .. finalize */
+} knng_stats;
+
+typedef struct knng_ctx knng_ctx;
+
+/* Bytes of device workspace a build of N points of dimension d needs. Returns
+ * 0 if the sizes or params are invalid (see knng_last_error()). */
+size_t knng_workspace_bytes(int64_t N, int32_t d, const knng_params* params);
+
+/* One-shot build (Sec. 2): init, iterate until c_t < delta*N*K or max_iters,
+ * write d_ids[N*K] (original row indices, int32) and d_dists[N*K] (squared l2,
+ * FP32), each row sorted ascending by (distance, id).
+ * dX: device, row-major float32 [N, d], finite. Synchronises `stream` once
+ * per iteration (to read c_t for the stop rule). Returns KNNG_ENOTCONV when
+ * max_iters was reached first. `stats` (host) may be NULL. */
+knng_status knng_build(const float* dX, int64_t N, int32_t d, const knng_params* params,
+                       int32_t* d_ids, float* d_dists, void* d_ws, size_t ws_bytes,
+                       void* stream, knng_stats* stats);
+
+/* ---- step API: one context per build, the state lives in the workspace ---- */
+
+/* Bind a context to (dX, N, d, params, workspace, stream); pads the rows and
+ * checks X is finite (one synchronisation). dX and the workspace must stay
+ * valid until knng_destroy. *out receives a host-allocated handle. */
+knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d,
+                        const knng_params* params, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Random initial graph G_0 (Sec. 2): K distinct non-self ids per point from
+ * the hash, all flagged new, rows sorted by (distance, id). Sets t = 0. */
+knng_status knng_init_graph(knng_ctx* ctx);
+
+/* Load a graph state: d_ids[N*K] int32 original ids (row u = point u) and
+ * d_flags[N*K] uint8 (1 = new, 0 = old); distances are recomputed on the
+ * device and rows re-sorted by (distance, id). Sets the iteration counter to
+ * t (the next iterate runs t+1). Only valid before any permutation. */
+knng_status knng_load_graph(knng_ctx* ctx, const int32_t* d_ids, const uint8_t* d_flags, int32_t t);
+
+/* One synchronous iteration t+1: sample (Sec. 3.1), local join (Sec. 2,
+ * Sec. 3.3), merge. Applies the permutation after iteration 1 when
+ * params.reorder is set. Synchronises `stream` once. Writes e_t and c_t
+ * (host, nullable). */
+knng_status knng_iterate(knng_ctx* ctx, int64_t* evals, int64_t* changes);
+
+/* Current graph in original order: d_ids[N*K], d_dists[N*K], d_flags[N*K]
+ * (nullable), rows sorted by (distance, id). */
+knng_status knng_export(knng_ctx* ctx, int32_t* d_ids, float* d_dists, uint8_t* d_flags);
+
+/* Sampled sets of the last iteration in original order: d_new[N*C],
+ * d_old[N*C] (int32 original ids; new sorted by (weight, id)), d_counts[2*N]
+ * (n_new, n_old per point). C = min(K, max(1, ceil(rho*K))). */
+knng_status knng_export_samples(knng_ctx* ctx, int32_t* d_new, int32_t* d_old, int32_t* d_counts);
+
+/* Statistics accumulated by the context so far (host). */
+knng_status knng_get_stats(const knng_ctx* ctx, knng_stats* stats);
+
+/* Free the host handle (no device memory is owned). */
+void knng_destroy(knng_ctx* ctx);
+
+/* Per-flag sample cap C for (K, rho). */
+int32_t knng_sample_cap(int32_t K, double rho);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* knng_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNG_H */

@@ -1,0 +1,236 @@
+"""MI355X (gfx950) NN-Descent K-NN graph construction, squared-l2 metric.
+
+Thin ctypes binding of ``libknng.so`` (C ABI in ``include/knng.h``). It only
+marshals arguments: torch provides the device memory (inputs, outputs and the
+workspace) and the stream; every step of the method runs in the HIP kernels.
+There is no CPU fallback: if the library is missing or fails to load, this
+module raises on import.
+
+Method: Kluser et al., "Fast single-core K-Nearest Neighbor Graph
+computation" (arXiv 2112.06630), Sec. 2 (K-NNG, NN-Descent), Sec. 3.1
+(sampling), Sec. 3.2 (reordering), Sec. 3.3 (squared-l2 distances).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = ["build", "Context", "Params", "workspace_bytes", "sample_cap", "KnngError", "LIB_PATH",
+           "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "MAX_ITERS", "lib"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknng.so")
+
+PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
+_PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA}
+MAX_ITERS = 64
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV = 0, 1, 2, 3, 4
+
+
+class KnngError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"knng status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("rho", ctypes.c_double), ("delta", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("path", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("dpad", ctypes.c_int32),
+                ("evals", ctypes.c_int64 * MAX_ITERS), ("changes", ctypes.c_int64 * MAX_ITERS),
+                ("proposals", ctypes.c_int64 * MAX_ITERS),
+                ("iter_ms", ctypes.c_float * MAX_ITERS), ("sample_ms", ctypes.c_float * MAX_ITERS),
+                ("join_ms", ctypes.c_float * MAX_ITERS), ("merge_ms", ctypes.c_float * MAX_ITERS),
+                ("init_ms", ctypes.c_float), ("reorder_ms", ctypes.c_float),
+                ("finalize_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    PP = ctypes.POINTER(Params)
+    L.knng_workspace_bytes.argtypes = [i64, i32, PP]
+    L.knng_workspace_bytes.restype = sz
+    L.knng_build.argtypes = [P, i64, i32, PP, P, P, P, sz, P, ctypes.POINTER(_Stats)]
+    L.knng_create.argtypes = [ctypes.POINTER(P), P, i64, i32, PP, P, sz, P]
+    L.knng_init_graph.argtypes = [P]
+    L.knng_load_graph.argtypes = [P, P, P, i32]
+    L.knng_iterate.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.knng_export.argtypes = [P, P, P, P]
+    L.knng_export_samples.argtypes = [P, P, P, P]
+    L.knng_get_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    L.knng_destroy.argtypes = [P]
+    L.knng_destroy.restype = None
+    L.knng_sample_cap.argtypes = [i32, ctypes.c_double]
+    L.knng_sample_cap.restype = i32
+    L.knng_last_error.restype = ctypes.c_char_p
+    for n in ("knng_build", "knng_create", "knng_init_graph", "knng_load_graph", "knng_iterate",
+              "knng_export", "knng_export_samples", "knng_get_stats"):
+        getattr(L, n).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _err() -> str:
+    return (lib.knng_last_error() or b"").decode()
+
+
+def _check(st: int, allow=(OK,)):
+    if st not in allow:
+        raise KnngError(st, _err())
+    return st
+
+
+def make_params(K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
+                reorder: bool = False, path: str | int = "auto") -> Params:
+    pth = _PATHS[path] if isinstance(path, str) else int(path)
+    return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, 0,
+                  1 if reorder else 0, pth)
+
+
+def sample_cap(K: int, rho: float) -> int:
+    return int(lib.knng_sample_cap(K, rho))
+
+
+def workspace_bytes(N: int, d: int, params: Params) -> int:
+    n = int(lib.knng_workspace_bytes(N, d, ctypes.byref(params)))
+    if n == 0:
+        raise KnngError(EINVAL, _err())
+    return n
+
+
+def _stream_ptr(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _check_x(X: torch.Tensor):
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+        raise ValueError("X must be a device tensor (ROCm)")
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float32 [N, d] tensor")
+
+
+def _stats_dict(s: _Stats) -> dict:
+    it = s.iters
+    return dict(iters=it, converged=bool(s.converged), path=s.path, dpad=s.dpad,
+                evals=list(s.evals[:it]), changes=list(s.changes[:it]), proposals=list(s.proposals[:it]),
+                iter_ms=list(s.iter_ms[:it]), sample_ms=list(s.sample_ms[:it]), join_ms=list(s.join_ms[:it]),
+                merge_ms=list(s.merge_ms[:it]), init_ms=s.init_ms, reorder_ms=s.reorder_ms,
+                finalize_ms=s.finalize_ms, total_ms=s.total_ms)
+
+
+def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
+          reorder: bool = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
+          out: tuple | None = None):
+    """K-NN graph of the rows of X (device float32 [N, d]).
+
+    Returns (ids int32 [N, K], dists float32 [N, K] squared l2, stats dict);
+    rows sorted by (distance, id). ``workspace`` (uint8 device tensor of at
+    least ``workspace_bytes``) and ``out`` may be passed to reuse memory.
+    """
+    _check_x(X)
+    N, d = X.shape
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path)
+    ws = workspace_bytes(N, d, p)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(ws, dtype=torch.uint8, device=X.device)
+    if out is None:
+        ids = torch.empty((N, K), dtype=torch.int32, device=X.device)
+        dists = torch.empty((N, K), dtype=torch.float32, device=X.device)
+    else:
+        ids, dists = out
+    st = _Stats()
+    _check(lib.knng_build(ctypes.c_void_p(X.data_ptr()), N, d, ctypes.byref(p), ctypes.c_void_p(ids.data_ptr()),
+                          ctypes.c_void_p(dists.data_ptr()), ctypes.c_void_p(workspace.data_ptr()), ws,
+                          ctypes.c_void_p(_stream_ptr(X.device)), ctypes.byref(st)), allow=(OK, ENOTCONV))
+    return ids, dists, _stats_dict(st)
+
+
+@dataclass
+class Graph:
+    ids: torch.Tensor
+    dists: torch.Tensor
+    flags: torch.Tensor
+
+
+class Context:
+    """Step API: one build whose state lives in a caller-held workspace."""
+
+    def __init__(self, X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
+                 seed: int = 0, reorder: bool = False, path: str | int = "auto"):
+        _check_x(X)
+        self.X = X
+        self.N, self.d = X.shape
+        self.K = K
+        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path)
+        self.C = sample_cap(K, rho)
+        self.ws_bytes = workspace_bytes(self.N, self.d, self.params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=X.device)
+        h = ctypes.c_void_p()
+        _check(lib.knng_create(ctypes.byref(h), ctypes.c_void_p(X.data_ptr()), self.N, self.d,
+                               ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                               ctypes.c_void_p(_stream_ptr(X.device))))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.knng_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self):
+        _check(lib.knng_init_graph(self._h))
+
+    def load(self, ids: torch.Tensor, flags: torch.Tensor, t: int):
+        ids = ids.to(device=self.X.device, dtype=torch.int32).contiguous()
+        flags = flags.to(device=self.X.device, dtype=torch.uint8).contiguous()
+        _check(lib.knng_load_graph(self._h, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(flags.data_ptr()), t))
+        torch.cuda.current_stream(self.X.device).synchronize()
+
+    def iterate(self) -> tuple[int, int]:
+        e, c = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib.knng_iterate(self._h, ctypes.byref(e), ctypes.byref(c)))
+        return int(e.value), int(c.value)
+
+    def export(self) -> Graph:
+        dev = self.X.device
+        ids = torch.empty((self.N, self.K), dtype=torch.int32, device=dev)
+        dists = torch.empty((self.N, self.K), dtype=torch.float32, device=dev)
+        flags = torch.empty((self.N, self.K), dtype=torch.uint8, device=dev)
+        _check(lib.knng_export(self._h, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dists.data_ptr()),
+                               ctypes.c_void_p(flags.data_ptr())))
+        return Graph(ids, dists, flags)
+
+    def samples(self):
+        dev = self.X.device
+        C = self.C
+        nw = torch.empty((self.N, C), dtype=torch.int32, device=dev)
+        od = torch.empty((self.N, C), dtype=torch.int32, device=dev)
+        cnt = torch.empty((self.N, 2), dtype=torch.int32, device=dev)
+        _check(lib.knng_export_samples(self._h, ctypes.c_void_p(nw.data_ptr()), ctypes.c_void_p(od.data_ptr()),
+                                       ctypes.c_void_p(cnt.data_ptr())))
+        return nw, od, cnt
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib.knng_get_stats(self._h, ctypes.byref(s)))
+        return _stats_dict(s)

@@ -1,0 +1,82 @@
+// Internal interface between the host orchestrator (knng_api.hip) and the
+// device kernels (knng_kernels.hip). Not installed; the public ABI is knng.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knng {
+
+constexpr uint32_t kNewBit = 0x80000000u;   // flag bit in a list entry's position word
+constexpr uint32_t kPosMask = 0x7fffffffu;
+constexpr int kWave = 64;
+constexpr int kSelectStage = 512;           // pool entries a select wave stages in LDS
+
+// Device counters of one iteration (uint64 slots).
+enum Counter : int {
+    kCntChanges = 0,     // c_t
+    kCntProposals = 1,   // proposals that passed the snapshot filter
+    kCntPairs2 = 2,      // 2 * e_t (sum of per-target proposal capacities)
+    kCntError = 3,       // nonzero: a device-side invariant failed
+    kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
+    kNumCounters = 8
+};
+
+// Views of the caller's workspace, carved by the host.
+struct Views {
+    int N, d, dp, K, C;
+    float* Xp;          // [N, dp] rows in position order, zero padded
+    float* nrm;         // [N] squared norms (Gram path)
+    int32_t* orig;      // [N] position -> original id
+    int32_t* posof;     // [N] original id -> position
+    uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
+    uint32_t* lpos;     // [N, K] position of the neighbour | kNewBit
+    uint32_t* rdeg;     // [N] reverse in-degree
+    uint32_t* roff;     // [N + 1] reverse bucket offsets
+    uint32_t* rcur;     // [N] reverse bucket cursors
+    uint4* rev;         // [N * K] reverse entries {w, orig src, pos src | flag, 0}
+    uint2* cand;        // [N, 2C] sampled members {orig, pos}: new then old
+    uint32_t* nn;       // [N] n_new | n_old << 16
+    uint32_t* cap;      // [N] upper bound of proposals per target
+    uint32_t* poff;     // [N + 1] proposal bucket offsets
+    uint32_t* pcnt;     // [N] proposal bucket cursors
+    uint64_t* pkey;     // [Pmax] proposal keys
+    uint32_t* ppos;     // [Pmax] proposal source positions
+    uint32_t* scan_tmp; // scan scratch
+    uint64_t* counters; // [kNumCounters]
+    // permutation scratch
+    int32_t* comp;      // [N]
+    int32_t* comp2;     // [N]
+    uint64_t* best;     // [N]
+    uint32_t* size;     // [N]
+    uint32_t* offs;     // [N]
+    int32_t* newpos;    // [N]
+    uint64_t* lkey2;    // [N, K] permute staging
+    uint32_t* lpos2;    // [N, K]
+    float* Xp2;         // [N, dp]
+    int32_t* orig2;     // [N]
+    uint32_t* flag;     // small device flags
+};
+
+size_t scan_tmp_words(int n);
+
+// kernels (launchers; all enqueue on `s`)
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
+void launch_norms(const Views& v, hipStream_t s);
+void launch_init(const Views& v, uint64_t st_init, int gram, hipStream_t s);
+void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int gram, hipStream_t s);
+void launch_rev_hist(const Views& v, hipStream_t s);
+void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
+void launch_rev_scatter(const Views& v, uint64_t st_sample, hipStream_t s);
+void launch_select(const Views& v, uint64_t st_sample, hipStream_t s);
+void launch_join_valu(const Views& v, hipStream_t s);
+void launch_join_mfma(const Views& v, hipStream_t s);
+void launch_merge(const Views& v, hipStream_t s);
+void launch_finish_counters(const Views& v, hipStream_t s);
+void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);
+void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t* counts, hipStream_t s);
+void launch_permute(const Views& v, hipStream_t s);
+bool join_valu_fits(const Views& v);
+
+}  // namespace knng

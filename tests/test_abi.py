@@ -1,0 +1,97 @@
+"""The C-ABI library loads and exports every symbol its header declares;
+host-side validation rejects bad arguments without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2112_06630_amd", "libknng.so")
+HDR = os.path.join(ROOT, "include", "knng.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libknng.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(knng_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_package_binding_loads():
+    import paper_2112_06630_amd as knng
+    assert knng.lib is not None
+    assert os.path.samefile(knng.LIB_PATH, LIB)
+
+
+def _params(**kw):
+    import paper_2112_06630_amd as knng
+    base = dict(K=10, rho=1.0, delta=0.001, max_iters=10, seed=0)
+    base.update(kw)
+    return knng.make_params(**base)
+
+
+@pytest.mark.parametrize("N,d,kw,msg", [
+    (100, 8, dict(K=0), "K must"),
+    (100, 8, dict(K=65), "K must"),
+    (10, 8, dict(K=10), "N - 1"),
+    (100, 0, dict(), "d must"),
+    (1, 8, dict(K=1), "N must"),
+    (100, 8, dict(rho=0.0), "rho"),
+    (100, 8, dict(rho=1.5), "rho"),
+    (100, 8, dict(delta=-1.0), "delta"),
+    (100, 8, dict(max_iters=-1), "max_iters"),
+    (100, 8, dict(max_iters=65), "max_iters"),
+    (100, 784, dict(K=64, rho=1.0, path="mfma"), "MFMA"),
+])
+def test_workspace_query_rejects(N, d, kw, msg):
+    import paper_2112_06630_amd as knng
+    with pytest.raises(knng.KnngError) as e:
+        knng.workspace_bytes(N, d, _params(**kw))
+    assert msg in str(e.value)
+
+
+def test_create_rejects_before_device_work():
+    """Invalid params or a short workspace fail before any HIP call."""
+    import paper_2112_06630_amd as knng
+    L = knng.lib
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    p = _params(K=0)
+    assert L.knng_create(ctypes.byref(h), fake, 100, 8, ctypes.byref(p), fake, 1 << 30, None) == knng.EINVAL
+    p = _params()
+    need = knng.workspace_bytes(100, 8, p)
+    assert L.knng_create(ctypes.byref(h), fake, 100, 8, ctypes.byref(p), fake, need - 1, None) == knng.ENOMEM
+    assert b"workspace too small" in L.knng_last_error()
+    assert L.knng_create(ctypes.byref(h), None, 100, 8, ctypes.byref(p), fake, need, None) == knng.EINVAL
+    assert L.knng_build(fake, 100, 8, ctypes.byref(p), None, None, fake, need, None, None) == knng.EINVAL
+
+
+def test_sample_cap_matches_oracle(oracle_lib):
+    import paper_2112_06630_amd as knng
+    for K in (1, 2, 7, 10, 15, 20, 64):
+        for rho in (0.01, 0.3, 0.5, 0.77, 1.0):
+            assert knng.sample_cap(K, rho) == oracle.cap(K, rho)
+
+
+def test_workspace_grows_with_size():
+    import paper_2112_06630_amd as knng
+    a = knng.workspace_bytes(1000, 8, _params())
+    b = knng.workspace_bytes(2000, 8, _params())
+    c = knng.workspace_bytes(2000, 784, _params(K=20))
+    assert 0 < a < b < c

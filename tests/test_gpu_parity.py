@@ -1,0 +1,198 @@
+"""GPU path vs the FP64 oracle, through the C ABI (ctypes binding).
+
+Integer-coordinate inputs make every FP32 sum exact, so there the GPU graph
+must equal the oracle's bit for bit (ids, distances, e_t, c_t per
+iteration). Continuous inputs follow the tie-aware rule in tests/parity.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import check_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def knng():
+    import paper_2112_06630_amd as k
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return k
+
+
+def dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X, np.float32)).to("cuda:0")
+
+
+def exact_build(knng, X, K, rho, delta, T, seed, path="auto", reorder=False):
+    ref = oracle.build_graph(X, K, rho, delta, T, seed)
+    ids, dists, st = knng.build(dev(X), K, rho, delta, T, seed, reorder=reorder, path=path)
+    ids = ids.cpu().numpy()
+    dists = dists.cpu().numpy().astype(np.float64)
+    assert st["iters"] == ref.iters
+    assert st["evals"] == ref.evals.tolist()
+    assert st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids, ref.ids)
+    assert np.array_equal(dists, ref.dists)
+    return st
+
+
+@pytest.mark.parametrize("N,d,K,rho,hi,seed", [
+    (600, 8, 10, 0.8, 12, 3),
+    (1000, 3, 15, 0.5, 40, 5),
+    (777, 16, 7, 1.0, 6, 11),
+    (500, 1, 5, 1.0, 300, 2),
+])
+def test_build_integer_points_bitwise_valu(knng, N, d, K, rho, hi, seed):
+    st = exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 15, seed, path="valu")
+    assert st["path"] == knng.PATH_VALU
+
+
+@pytest.mark.parametrize("N,d,K,rho,hi,seed", [
+    (700, 64, 10, 1.0, 9, 1),
+    (600, 100, 20, 0.5, 15, 2),
+    (900, 130, 16, 1.0, 5, 3),
+    (400, 33, 12, 0.9, 20, 4),
+])
+def test_build_integer_points_bitwise_mfma(knng, N, d, K, rho, hi, seed):
+    st = exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 15, seed, path="mfma")
+    assert st["path"] == knng.PATH_MFMA
+
+
+def test_image_like_subset_bitwise_mfma(knng):
+    """784-d 0..255 integer data (image-shaped workload at N=3000): exact in FP32."""
+    X = synth.image_like(3000, 1)
+    exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path="auto")
+
+
+def test_init_matches_oracle(knng):
+    X, p = synth.config(1)
+    ctx = knng.Context(dev(X), 10, seed=0)
+    ctx.init()
+    g = ctx.export()
+    ref = oracle.init(X, 10, 0)
+    check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), ref.ids, ref.dists, rel=0.0)
+    assert np.array_equal(np.sort(g.ids.cpu().numpy(), 1), np.sort(ref.ids, 1))
+    assert (g.flags.cpu().numpy() == 1).all()
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.5, 0.25])
+def test_sample_sets_match_oracle(knng, rho):
+    """Sampled new/old sets are integer-exact, for every t of an oracle trajectory."""
+    X, p = synth.config(1, N=1500)
+    K = 10
+    C = oracle.cap(K, rho)
+    r = oracle.build_graph(X, K, rho, 0.0, 5, 7, keep_states=True)
+    for s in r.states[:-1]:
+        ctx = knng.Context(dev(X), K, rho=rho, seed=7)
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        ctx.iterate()
+        nw, od, cnt = (a.cpu().numpy() for a in ctx.samples())
+        sm = oracle.sample(s, K, C, 7, s.t + 1)
+        for u in range(X.shape[0]):
+            a, b = cnt[u]
+            assert list(nw[u, :a]) == list(sm.cnew[u]), (s.t, u)
+            assert list(od[u, :b]) == list(sm.cold[u]), (s.t, u)
+        ctx.close()
+
+
+def test_step_parity_cfg1(knng):
+    """Load the oracle's G_t, run one GPU iteration, compare with the oracle's G_{t+1}."""
+    X, p = synth.config(1)
+    K = p["K"]
+    r = oracle.build_graph(X, K, p["rho"], p["delta"], p["max_iters"], p["seed"], keep_states=True)
+    for s, nxt, e, c in zip(r.states[:-1], r.states[1:], r.evals, r.changes):
+        ctx = knng.Context(dev(X), K, rho=p["rho"], seed=p["seed"])
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        eg, cg = ctx.iterate()
+        assert eg == e
+        g = ctx.export()
+        check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), nxt.ids, nxt.dists)
+        ctx.close()
+
+
+def test_build_cfg1_parity_and_recall(knng):
+    X, p = synth.config(1)
+    ref = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
+    ids, dists, st = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
+    ids = ids.cpu().numpy()
+    res = check_rows(X, ids, dists.cpu().numpy(), ref.ids, ref.dists)
+    assert res["exact_rows"] >= X.shape[0] - 2
+    ei, ed = oracle.bruteforce(X, p["K"])
+    assert oracle.recall(X, ids, ed) >= 0.99
+    assert st["converged"]
+
+
+def test_complete_graph_N_is_K_plus_1(knng):
+    X = synth.integer_points(17, 4, 9, 3)
+    st = exact_build(knng, X, 16, 1.0, 0.001, 5, 3)
+    assert st["iters"] == 1 and st["changes"] == [0]
+
+
+def test_identical_points_hubs(knng):
+    """All points equal: pure id tie-break; lists collapse onto the smallest ids,
+    whose reverse pools grow past the LDS stage (radix prefilter path)."""
+    X = np.full((3000, 5), 1.5, np.float32)
+    exact_build(knng, X, 12, 1.0, 0.0, 6, 9)
+
+
+def test_duplicate_points_and_small_K(knng):
+    rng = np.random.default_rng(5)
+    base = synth.integer_points(300, 6, 3, 5)
+    X = base[rng.integers(0, 300, 1200)]
+    exact_build(knng, X, 1, 1.0, 0.0, 8, 2)
+    exact_build(knng, X, 9, 0.05, 0.0, 8, 2)
+
+
+def test_max_K_valu(knng):
+    X = synth.integer_points(400, 4, 50, 8)
+    exact_build(knng, X, 64, 1.0, 0.001, 6, 8, path="valu")
+
+
+def test_zero_iterations_returns_init(knng):
+    X, _ = synth.config(1, N=500)
+    ids, dists, st = knng.build(dev(X), 10, 1.0, 0.001, 0, 4)
+    ref = oracle.init(X, 10, 4)
+    assert st["iters"] == 0
+    assert np.array_equal(np.sort(ids.cpu().numpy(), 1), np.sort(ref.ids, 1))
+
+
+def test_nonfinite_input_rejected(knng):
+    X = synth.integer_points(100, 4, 5, 1)
+    X[7, 2] = np.nan
+    with pytest.raises(knng.KnngError) as e:
+        knng.build(dev(X), 5)
+    assert e.value.status == 1
+    X[7, 2] = np.inf
+    with pytest.raises(knng.KnngError):
+        knng.build(dev(X), 5)
+
+
+def test_load_rejects_bad_rows(knng):
+    X = synth.integer_points(50, 3, 5, 1)
+    ctx = knng.Context(dev(X), 4)
+    ids = np.tile(np.arange(1, 5, dtype=np.int32), (50, 1))
+    ids[1] = [0, 2, 3, 4]
+    ids[2] = [0, 1, 3, 4]
+    ids[3] = [0, 1, 2, 4]
+    ids[4] = [0, 1, 2, 3]
+    flags = np.ones((50, 4), np.uint8)
+    ctx.load(torch.from_numpy(ids), torch.from_numpy(flags), 0)  # valid
+    bad = ids.copy()
+    bad[9, 0] = 9   # self
+    with pytest.raises(knng.KnngError):
+        ctx.load(torch.from_numpy(bad), torch.from_numpy(flags), 0)
+    bad = ids.copy()
+    bad[9, 1] = bad[9, 0]   # duplicate
+    with pytest.raises(knng.KnngError):
+        ctx.load(torch.from_numpy(bad), torch.from_numpy(flags), 0)
+
+
+def test_deterministic_repeat(knng):
+    X, p = synth.config(1)
+    a = knng.build(dev(X), 10, 1.0, 0.001, 20, 0)
+    b = knng.build(dev(X), 10, 1.0, 0.001, 20, 0)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2]["evals"] == b[2]["evals"] and a[2]["changes"] == b[2]["changes"]

@@ -1,0 +1,187 @@
+"""Throughput of the NN-Descent K-NN graph build on one MI355X.
+
+A step is one whole build (random init, iterations until changes < delta*N*K,
+write-out) of the image-shaped workload: N=60000 points of d=784 integer
+intensities 0..255 (~80% zeros), K=20, rho=1, delta=0.001, seed 1, at most
+30 iterations. Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: evals/s (sum of e_t over the build / build time), the
+time to tie-aware recall 0.99, the roofline of the local-join kernel (its
+algorithmic flops e_t * 2d per launch over its event-timed duration), and the
+FP64 oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = dict(workload="image60k_d784", N=60000, d=784, K=20, rho=1.0, delta=0.001, max_iters=30, seed=1)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("knng_kernels.hip", "knng_api.hip", "knng_impl.h"):
+        h.update(open(os.path.join(ROOT, "paper_2112_06630_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def exact_kth(X, K):
+    """Exact K-th neighbour distance per row (FP64, self excluded), on the GPU with torch."""
+    import torch
+    Xd = X.double()
+    n = (Xd * Xd).sum(1)
+    N = X.shape[0]
+    out = torch.empty(N, dtype=torch.float64, device=X.device)
+    for s in range(0, N, 4096):
+        e = min(N, s + 4096)
+        D = n[s:e, None] + n[None, :] - 2.0 * (Xd[s:e] @ Xd.T)
+        D[torch.arange(e - s, device=X.device), torch.arange(s, e, device=X.device)] = float("inf")
+        out[s:e] = torch.topk(D, K, dim=1, largest=False).values[:, -1]
+    return out
+
+
+def recall_of(X, ids, tau, rel=1e-5):
+    import torch
+    Xd = X.double()
+    good = 0
+    for s in range(0, X.shape[0], 2048):
+        e = min(X.shape[0], s + 2048)
+        diff = Xd[ids[s:e].long()] - Xd[s:e, None, :]
+        D = (diff * diff).sum(-1)
+        good += int((D <= tau[s:e, None] * (1 + rel) + 1e-9).sum())
+    return good / ids.numel()
+
+
+def cpu_baseline(Xnp, w, budget_s=20.0):
+    """FP64 oracle on the host: init + iterations 1, 2, ... of the same workload
+    until ~budget_s of CPU work; evals/s over the iterations run."""
+    import oracle
+    oracle.build(force=False)
+    C = oracle.cap(w["K"], w["rho"])
+    t0 = time.perf_counter()
+    st = oracle.init(Xnp, w["K"], w["seed"])
+    ev = 0
+    iters = 0
+    while time.perf_counter() - t0 < budget_s and iters < w["max_iters"]:
+        st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"])
+        ev += e
+        iters += 1
+    dt = time.perf_counter() - t0
+    return {"value": ev / dt, "unit": "distance evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, full {w['workload']} input, init + iterations 1..{iters} "
+                      f"({ev} evals in {dt:.1f} s)"}
+
+
+def traffic_record(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p)).get(kernel)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--reorder", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-recall", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2112_06630_amd as knng
+
+    w = WORKLOAD
+    Xnp = synth.image_like(w["N"], w["seed"])
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(Xnp).to(dev)
+    p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder))
+    ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
+    ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
+    dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
+    run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+                             workspace=ws, out=(ids, dists))
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(run()[2])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    evals = sum(stats[0]["evals"])
+    for s in stats[1:]:
+        assert s["evals"] == stats[0]["evals"] and s["changes"] == stats[0]["changes"], "non-deterministic build"
+    value = evals / (ms_per_step / 1e3)
+
+    # local-join roofline: algorithmic flops e_t * 2d per launch / event-timed duration
+    s0 = stats[len(stats) // 2]
+    join_ms = [np.median([s["join_ms"][i] for s in stats]) for i in range(s0["iters"])]
+    flops = [e * 2 * w["d"] for e in s0["evals"]]
+    achieved = sum(flops) / (sum(join_ms) / 1e3) / 1e12
+    kernel = "k_join_mfma" if s0["path"] == knng.PATH_MFMA else "k_join_valu"
+    traffic = traffic_record(kernel)
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
+            "avg_launch_ms": round(sum(join_ms) / len(join_ms), 4),
+            "flops_per_launch": int(sum(flops) / len(flops))}
+
+    # time to recall 0.99: per-iteration graphs from the step API (same deterministic trajectory)
+    rec = None
+    t99 = None
+    if not args.no_recall:
+        tau = exact_kth(X, w["K"])
+        ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder))
+        ctx.init()
+        curve = []
+        for t in range(1, s0["iters"] + 1):
+            ctx.iterate()
+            r = recall_of(X, ctx.export().ids, tau)
+            curve.append(r)
+        ctx.close()
+        rec = curve[-1]
+        cum = s0["init_ms"] + s0["reorder_ms"]
+        for t, r in enumerate(curve):
+            cum += float(np.median([s["iter_ms"][t] for s in stats]))
+            if r >= 0.99 and t99 is None:
+                t99 = cum
+    cpu = None if args.no_cpu else cpu_baseline(Xnp, w)
+
+    out = {
+        "metric": "distance evals/sec", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
+                   "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
+                   "reorder": bool(args.reorder), "path": "mfma" if s0["path"] == knng.PATH_MFMA else "valu"},
+        "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
+        "device_ms_per_build": round(float(np.median([s["total_ms"] for s in stats])), 3),
+        "phase_ms": {k: round(float(sum(s0[k])), 3) for k in ("sample_ms", "join_ms", "merge_ms")},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

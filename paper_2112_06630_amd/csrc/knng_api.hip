@@ -56,7 +56,7 @@ struct Plan {
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
-    size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_poff,
+    size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_poff,
         o_pkey, o_ppos, o_scan, o_counters, o_comp, o_comp2, o_best, o_size, o_offs, o_newpos, o_lkey2,
         o_lpos2, o_Xp2, o_orig2, o_flag;
 };
@@ -117,6 +117,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     P.o_rev = take(NK * 16);
     P.o_cand = take((size_t)N * 2 * C * 8);
     P.o_nn = take((size_t)N * 4);
+    P.o_big = take((size_t)N * 4);
     P.o_poff = take(((size_t)N + 1) * 4);
     P.o_pkey = take((size_t)P.pmax * 8);
     P.o_ppos = take((size_t)P.pmax * 4);
@@ -160,6 +161,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.rev = reinterpret_cast<uint4*>(b + P.o_rev);
     v.cand = reinterpret_cast<uint2*>(b + P.o_cand);
     v.nn = reinterpret_cast<uint32_t*>(b + P.o_nn);
+    v.big = reinterpret_cast<uint32_t*>(b + P.o_big);
     v.poff = reinterpret_cast<uint32_t*>(b + P.o_poff);
     v.pkey = reinterpret_cast<uint64_t*>(b + P.o_pkey);
     v.ppos = reinterpret_cast<uint32_t*>(b + P.o_ppos);

@@ -18,6 +18,7 @@ enum Counter : int {
     kCntPairs2 = 2,      // 2 * e_t (sum of per-target proposal capacities)
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
+    kCntBig = 5,         // owners whose pool exceeds one wave (select list length)
     kNumCounters = 8
 };
 
@@ -36,6 +37,7 @@ struct Views {
     uint4* rev;         // [N * K] reverse entries {w, orig src, pos src | flag, 0}
     uint2* cand;        // [N, 2C] sampled members {orig, pos}: new then old
     uint32_t* nn;       // [N] n_new | n_old << 16
+    uint32_t* big;      // [N] owners with pools of more than 64 entries
     uint32_t* cap;      // [N] upper bound of proposals per target
     uint32_t* poff;     // [N + 1] proposal bucket offsets
     uint32_t* pcnt;     // [N] proposal bucket cursors

@@ -50,12 +50,65 @@ __device__ __forceinline__ uint64_t rl64(uint64_t x, int j) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Cross-lane shuffles read the source lane's register only if that lane takes
+// part: every shuffle below is evaluated by the whole wave, never inside a
+// short-circuited condition.
+
 // Orders the LDS traffic of one wavefront: LDS operations of a wave execute
 // in issue order, so only compiler reordering has to be prevented.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One compare-exchange step of a bitonic network across the wave: lanes
+// lane and lane^j exchange; an ascending block keeps the smaller key in its
+// lower lane. Equal keys are left in place.
+__device__ __forceinline__ void cmpx(uint64_t& k, uint32_t& v, int j, bool asc) {
+    const int lane = lane_id();
+    const uint64_t ok = shfl_xor64(k, j);
+    const uint32_t ov = (uint32_t)__shfl_xor((int)v, j);
+    const bool low = (lane & j) == 0;
+    const bool sw = (asc == low) ? (ok < k) : (ok > k);
+    if (sw) {
+        k = ok;
+        v = ov;
+    }
+}
+
+// Ascending bitonic sort of 64 (key, value) pairs, one per lane.
+__device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) cmpx(k, v, j, (lane & size) == 0);
+    }
+}
+
+// Sorts a bitonic sequence of 64 pairs ascending.
+__device__ __forceinline__ void wave_bitonic_clean(uint64_t& k, uint32_t& v) {
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) cmpx(k, v, j, true);
 }
 
 __device__ __forceinline__ uint64_t key_of(float D, uint32_t id) {
@@ -220,7 +273,10 @@ __global__ __launch_bounds__(256) void k_init(Views v, uint64_t st, int gram) {
             c += (c >= (uint32_t)u) ? 1u : 0u;
             bool novel = true;
             for (int i = 0; i < have; ++i) novel &= (s_sel[w][i] != c);
-            for (int i = 0; i < 63; ++i) novel &= !(i < lane && rl32(c, i) == c);
+            for (int i = 0; i < 63; ++i) {
+                const uint32_t ci = rl32(c, i);
+                novel &= !(i < lane && ci == c);
+            }
             const uint64_t m = ballot(novel);
             const uint32_t r = mbcnt(m);
             wave_sync();
@@ -251,7 +307,10 @@ __global__ __launch_bounds__(256) void k_load_rows(Views v, const int32_t* __res
         }
         // a row must hold K distinct ids in [0, N), none equal to u
         bool bad = lane < v.K && (pid >= (uint32_t)v.N || pid == (uint32_t)u);
-        for (int j = 0; j < v.K; ++j) bad |= lane < v.K && j != lane && rl32(pid, j) == pid;
+        for (int j = 0; j < v.K; ++j) {
+            const uint32_t pj = rl32(pid, j);
+            bad |= lane < v.K && j != lane && pj == pid;
+        }
         if (ballot(bad)) {
             if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 4ull);
             continue;
@@ -468,13 +527,18 @@ __device__ void select_radix_thresholds(const Views& v, uint64_t st, int u, uint
     }
 }
 
-__global__ __launch_bounds__(256) void k_select(Views v, uint64_t st) {
+// Pools of more than 64 entries (owners with a large reverse in-degree):
+// staged in LDS (after a radix prefilter when they exceed the stage), ranks
+// by counting over the stage.
+__global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st) {
     __shared__ SelLds L;
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int N = v.N, K = v.K, C = v.C;
+    const int K = v.K, C = v.C;
     uint64_t* skey = L.key[w];
     uint32_t* spos = L.pos[w];
-    for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
+    const int nbig = (int)v.counters[kCntBig];
+    for (int bi = blockIdx.x * kSelWaves + w; bi < nbig; bi += gridDim.x * kSelWaves) {
+        const int u = (int)v.big[bi];
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
         const uint32_t ou = (uint32_t)v.orig[u];
@@ -601,8 +665,83 @@ __global__ __launch_bounds__(256) void k_select(Views v, uint64_t st) {
     }
 }
 
+// Pools of at most 64 entries, one per lane, in registers. Select key
+// (w << 32) | (id << 1) | old: sorting it puts the two copies of a member
+// reached by both routes with the same flag next to each other (the second
+// is a duplicate), and a member's NEW entry right before its OLD entry.
+// Ranks per flag are ballot prefix counts over the sorted lanes.
+__global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int N = v.N, K = v.K;
+    const uint32_t C = (uint32_t)v.C;
+    for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
+        const uint32_t rb = v.roff[u];
+        const int P = K + (int)(v.roff[u + 1] - rb);
+        if (P > 64) {
+            if (lane == 0) {
+                const uint32_t slot = (uint32_t)atomicAdd((unsigned long long*)&v.counters[kCntBig], 1ull);
+                v.big[slot] = (uint32_t)u;
+            }
+            continue;
+        }
+        const uint32_t ou = (uint32_t)v.orig[u];
+        uint64_t key = ~0ull;
+        uint32_t pos = 0;
+        if (lane < P) {
+            uint32_t id, pf, wt;
+            if (lane < K) {
+                const size_t e = (size_t)u * K + lane;
+                id = (uint32_t)v.lkey[e];
+                pf = v.lpos[e];
+                wt = pair_weight(st, ou, id);
+            } else {
+                const uint4 r = v.rev[rb + (uint32_t)(lane - K)];
+                wt = r.x;
+                id = r.y;
+                pf = r.z;
+            }
+            key = ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
+            pos = pf & kPosMask;
+        }
+        uint32_t idx = (uint32_t)lane;
+        wave_sort(key, idx);
+        const uint32_t mpos = (uint32_t)__shfl((int)pos, (int)idx);
+        const uint64_t p1 = shfl_up64(key, 1), p2 = shfl_up64(key, 2);
+        const bool real = key != ~0ull;
+        const bool dup = real && lane >= 1 && p1 == key;
+        const bool valid = real && !dup;
+        const bool isnew = (key & 1ull) == 0;
+        const uint64_t mnew = ballot(valid && isnew), mold = ballot(valid && !isnew);
+        const uint32_t rnew = mbcnt(mnew), rold = mbcnt(mold);
+        const bool seln = valid && isnew && rnew < C;
+        const bool s1 = __shfl_up(seln ? 1 : 0, 1) != 0, s2 = __shfl_up(seln ? 1 : 0, 2) != 0;
+        const bool twin = !isnew && ((lane >= 1 && (p1 | 1ull) == key && !(p1 & 1ull) && s1) ||
+                                     (lane >= 2 && (p2 | 1ull) == key && !(p2 & 1ull) && s2));
+        const bool cold = valid && !isnew && rold < C;
+        const bool removed = cold && twin;
+        const uint64_t mrem = ballot(removed);
+        const uint32_t nnew = min(C, (uint32_t)__popcll(mnew));
+        const uint32_t nold = min(C, (uint32_t)__popcll(mold)) - (uint32_t)__popcll(mrem);
+        uint2* cs = v.cand + (size_t)u * 2 * C;
+        const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
+        if (seln) {
+            cs[rnew] = make_uint2(id, mpos);
+            atomicAdd(&v.cap[mpos], nnew - 1 + nold);
+        }
+        if (cold && !removed) {
+            cs[nnew + rold - mbcnt(mrem)] = make_uint2(id, mpos);
+            if (nnew > 0) atomicAdd(&v.cap[mpos], nnew);
+        }
+        // forward NEW entries whose member was sampled new become OLD
+        if (real && isnew && idx < (uint32_t)K && (seln || (dup && s1)))
+            v.lpos[(size_t)u * K + idx] = mpos;
+        if (lane == 0) v.nn[u] = nnew | (nold << 16);
+    }
+}
+
 void launch_select(const Views& v, uint64_t st, hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st);
+    hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st);
+    hipLaunchKernelGGL(k_select_large, dim3(1024), dim3(256), 0, s, v, st);
 }
 
 // ------------------------------------------------------------------ join (a3, a4)
@@ -780,12 +919,18 @@ void launch_join_mfma(const Views& v, hipStream_t s) {
 
 constexpr int kMergeWaves = 4;
 
-// One wave per target with proposals: the list sits one entry per lane
-// (sorted); proposals are read 64 at a time, dropped if not below the current
-// K-th key or if their id is in the snapshot list, and the survivors are
-// inserted one by one (ballot rank, shift up). The same id proposed twice
-// keeps its smaller key. Entries that enter are NEW; c_t counts them.
+// One wave per target with proposals. The list sits one entry per lane,
+// ascending; lanes >= K hold +inf. Proposals are read 64 at a time and
+// dropped when not below the current K-th key or when their id is in the
+// snapshot list or already in the current list. A chunk with few survivors
+// inserts them one by one (ballot rank, shift up); a larger one is sorted
+// (bitonic), reversed and folded into the list with a lane-wise min, which
+// leaves a bitonic sequence holding the 64 smallest keys, sorted again by one
+// half-cleaner pass; equal keys (one id proposed by two owners) are then
+// collapsed. Entries that enter are NEW; c_t counts ids not in the snapshot.
 __global__ __launch_bounds__(256) void k_merge(Views v) {
+    __shared__ uint64_t s_k[kMergeWaves][64];
+    __shared__ uint32_t s_p[kMergeWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
     uint64_t changes = 0, props = 0;
@@ -797,62 +942,95 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         uint64_t key = lane < K ? v.lkey[row + lane] : ~0ull;
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
-        bool fromc = false;
         uint64_t kth = rl64(key, K - 1);
+        bool grown = false;  // list holds entries from proposals
         for (uint32_t c0 = 0; c0 < n; c0 += 64) {
             const uint32_t i = c0 + (uint32_t)lane;
             uint64_t pk = ~0ull;
             uint32_t pp = 0;
             if (i < n) {
                 pk = v.pkey[base + i];
-                pp = v.ppos[base + i];
+                pp = v.ppos[base + i] | kNewBit;
             }
             bool ok = pk < kth;
+            if (__popcll(ballot(ok)) == 0) continue;
             const uint32_t pid = (uint32_t)pk;
             for (int k = 0; k < K; ++k) ok &= rl32(snap, k) != pid;
+            if (grown) {
+                const uint32_t cur = (uint32_t)key;
+                for (int k = 0; k < K; ++k) ok &= rl32(cur, k) != pid;
+            }
             uint64_t mask = ballot(ok);
-            while (mask) {
-                const int j = __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
-                const uint64_t x = rl64(pk, j);
-                if (x >= kth) continue;
-                const uint32_t xp = rl32(pp, j);
-                const uint64_t same = ballot(lane < K && (uint32_t)key == (uint32_t)x);
-                if (same) {
-                    const int sl = __ffsll((long long)same) - 1;
-                    if (x >= rl64(key, sl)) continue;
-                    const uint64_t kd = __shfl_down(key, 1);
-                    const uint32_t pd = __shfl_down(pf, 1);
-                    const bool fd = __shfl_down(fromc ? 1 : 0, 1) != 0;
-                    if (lane >= sl && lane < K) {
-                        const bool last = lane == K - 1;
-                        key = last ? ~0ull : kd;
-                        pf = last ? 0u : pd;
-                        fromc = last ? false : fd;
+            if (mask == 0) continue;
+            grown = true;
+            if (__popcll(mask) <= 4) {
+                while (mask) {
+                    const int j = __ffsll((long long)mask) - 1;
+                    mask &= mask - 1;
+                    const uint64_t x = rl64(pk, j);
+                    if (x >= kth) continue;
+                    if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;  // same id, same key
+                    const uint32_t xp = rl32(pp, j);
+                    const int at = __popcll(ballot(lane < K && key < x));
+                    const uint64_t ku = shfl_up64(key, 1);
+                    const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
+                    if (lane > at && lane < K) {
+                        key = ku;
+                        pf = pu;
                     }
+                    if (lane == at) {
+                        key = x;
+                        pf = xp;
+                    }
+                    kth = rl64(key, K - 1);
                 }
-                const int at = __popcll(ballot(lane < K && key < x));
-                const uint64_t ku = __shfl_up(key, 1);
-                const uint32_t pu = __shfl_up(pf, 1);
-                const bool fu = __shfl_up(fromc ? 1 : 0, 1) != 0;
-                if (lane > at && lane < K) {
-                    key = ku;
-                    pf = pu;
-                    fromc = fu;
+            } else {
+                if (!ok) pk = ~0ull;
+                wave_sort(pk, pp);
+                const uint64_t rk = shfl64(pk, 63 - lane);
+                const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
+                if (rk < key) {
+                    key = rk;
+                    pf = rp;
                 }
-                if (lane == at) {
-                    key = x;
-                    pf = xp | kNewBit;
-                    fromc = true;
+                wave_bitonic_clean(key, pf);
+                const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
+                const bool dupk = lane > 0 && key != ~0ull && prevk == key;
+                const uint64_t dm = ballot(dupk);
+                if (dm) {
+                    s_k[w][lane] = ~0ull;
+                    wave_sync();
+                    if (!dupk) {
+                        const uint32_t to = (uint32_t)lane - mbcnt(dm);
+                        s_k[w][to] = key;
+                        s_p[w][to] = pf;
+                    }
+                    wave_sync();
+                    key = s_k[w][lane];
+                    pf = s_p[w][lane];
+                    wave_sync();
+                }
+                if (lane >= K) {
+                    key = ~0ull;
+                    pf = 0u;
                 }
                 kth = rl64(key, K - 1);
             }
         }
+        // an id twice in a row would mean two different keys for one pair
+        bool twice = false;
+        for (int k = 0; k < K; ++k) {
+            const uint32_t ik = rl32((uint32_t)key, k);
+            twice |= lane < K && k != lane && ik == (uint32_t)key;
+        }
+        if (ballot(twice) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 8ull);
+        bool entered = lane < K;
+        for (int k = 0; k < K; ++k) entered &= rl32(snap, k) != (uint32_t)key;
         if (lane < K) {
             v.lkey[row + lane] = key;
             v.lpos[row + lane] = pf;
         }
-        changes += (uint64_t)__popcll(ballot(lane < K && fromc));
+        changes += (uint64_t)__popcll(ballot(entered));
         props += n;
     }
     if (lane == 0 && (changes | props)) {

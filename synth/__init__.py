@@ -41,46 +41,54 @@ def clustered_labels(N: int, d: int, n_clusters: int, seed: int, spread: float =
     return gaussian_mixture(N, d, n_clusters, seed, -10.0, 10.0, spread, return_labels=True)
 
 
-def _bump_field(rng, side: int, n_bumps: int) -> np.ndarray:
-    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
-    f = np.zeros((side, side))
-    for _ in range(n_bumps):
-        cy, cx = rng.uniform(6, side - 6, 2)
-        sy, sx = rng.uniform(1.5, 4.0, 2)
-        f += rng.uniform(0.6, 1.0) * np.exp(-0.5 * (((yy - cy) / sy) ** 2 + ((xx - cx) / sx) ** 2))
-    return f / f.max()
-
-
-def image_like(N: int = 60000, seed: int = 1, side: int = 28, n_protos: int = 10,
-               on_frac: float = 0.2, drop: float = 0.1, noise: float = 0.03,
-               return_labels: bool = False):
+def image_like(N: int = 60000, seed: int = 1, side: int = 28, n_protos: int = 10, on_frac: float = 0.2,
+               noise: float = 0.01, jitter: float = 1.0, return_labels: bool = False):
     """784-d image-shaped integers in [0, 255], ~80% zeros (stand-in for MNIST, Sec. 4).
 
-    10 prototypes are smooth fields (sums of Gaussian bumps) thresholded to the
-    top ``on_frac`` pixels; a point picks a prototype, scales its intensities by
-    U(0.6, 1), drops each on-pixel with probability ``drop`` and sets each pixel
-    with probability ``noise`` to U{1..255}; values are rounded and clipped.
+    Each of 10 prototypes is a smooth field, a sum of 3-6 Gaussian bumps. A
+    point picks a prototype and deforms it with a few continuous parameters
+    (a global shift and stretch, a per-bump jitter of ``jitter`` pixels, per-bump
+    amplitudes), so the points lie near a low-dimensional manifold the way
+    handwritten digits do. The top ``on_frac`` pixels of the field are kept and
+    mapped to intensities 90..255, scaled by U(0.6, 1); each pixel is then set to
+    U{1..255} with probability ``noise``; values are rounded and clipped.
     Squared norms stay below 2^23, so all pair distances are exact in FP32.
     """
     rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float32)
+    yy, xx = yy.reshape(-1), xx.reshape(-1)
     protos = []
     for _ in range(n_protos):
-        f = _bump_field(rng, side, int(rng.integers(3, 7)))
-        thr = np.quantile(f, 1.0 - on_frac)
-        p = np.where(f >= thr, 90.0 + 165.0 * (f - thr) / max(1e-12, 1.0 - thr), 0.0)
-        protos.append(p.reshape(-1))
-    protos = np.stack(protos)
-    d = side * side
+        nb = int(rng.integers(3, 7))
+        protos.append((rng.uniform(7, side - 7, (nb, 2)), rng.uniform(1.5, 4.0, (nb, 2)), rng.uniform(0.6, 1.0, nb)))
     labels = rng.integers(0, n_protos, N)
+    d = side * side
     X = np.empty((N, d), np.float32)
-    for s in range(0, N, 8192):
-        n = min(8192, N - s)
-        base = protos[labels[s:s + n]] * rng.uniform(0.6, 1.0, (n, 1))
-        keep = rng.random((n, d)) >= drop
-        v = base * keep
+    for s in range(0, N, 4096):
+        n = min(4096, N - s)
+        out = np.zeros((n, d), np.float32)
+        for k, (c, sg, a) in enumerate(protos):
+            idx = np.nonzero(labels[s:s + n] == k)[0]
+            if len(idx) == 0:
+                continue
+            m, nb = len(idx), len(a)
+            shift = rng.normal(0, 1.0, (m, 1, 2)) + rng.normal(0, jitter, (m, nb, 2))
+            stretch = np.exp(rng.normal(0, 0.08, (m, 1, 2)))
+            amp = a[None, :] * rng.uniform(0.75, 1.0, (m, nb))
+            cc = (c[None] + shift).astype(np.float32)
+            ss = (sg[None] * stretch).astype(np.float32)
+            f = np.zeros((m, d), np.float32)
+            for b in range(nb):
+                f += amp[:, b:b + 1].astype(np.float32) * np.exp(
+                    -0.5 * (((yy[None] - cc[:, b, 0:1]) / ss[:, b, 0:1]) ** 2
+                            + ((xx[None] - cc[:, b, 1:2]) / ss[:, b, 1:2]) ** 2))
+            f /= f.max(1, keepdims=True)
+            thr = np.quantile(f, 1.0 - on_frac, axis=1, keepdims=True)
+            v = np.where(f >= thr, 90.0 + 165.0 * (f - thr) / np.maximum(1e-6, 1.0 - thr), 0.0)
+            out[idx] = v * rng.uniform(0.6, 1.0, (m, 1))
         nz = rng.random((n, d)) < noise
-        v = np.where(nz, rng.integers(1, 256, (n, d)).astype(np.float64), v)
-        X[s:s + n] = np.clip(np.rint(v), 0, 255)
+        out = np.where(nz, rng.integers(1, 256, (n, d)).astype(np.float32), out)
+        X[s:s + n] = np.clip(np.rint(out), 0, 255)
     return (X, labels) if return_labels else X
 
 

@@ -1,0 +1,40 @@
+"""Seeded input generators: shapes, value distributions, reproducibility."""
+import numpy as np
+
+import synth
+
+
+def test_image_like_shape_and_distribution():
+    X = synth.image_like(3000, 1)
+    assert X.shape == (3000, 784) and X.dtype == np.float32
+    assert abs((X == 0).mean() - 0.80) <= 0.02
+    assert X.min() == 0 and X.max() <= 255 and np.array_equal(X, np.rint(X))
+    # squared norms below 2^23 keep every pair distance exact in FP32
+    assert (X.astype(np.float64) ** 2).sum(1).max() < 2 ** 23
+    assert np.array_equal(X, synth.image_like(3000, 1))
+
+
+def test_lowd_blobs():
+    X, lab = synth.lowd_blobs(20000, 2, return_labels=True)
+    assert X.shape == (20000, 3)
+    assert abs((lab == -1).mean() - 0.1) < 1e-3
+    assert X.min() > -0.2 and X.max() < 1.2
+
+
+def test_gaussian_and_integer():
+    X = synth.gaussian_mixture(500, 8, 10, 0)
+    assert X.shape == (500, 8) and X.dtype == np.float32
+    Y = synth.integer_points(100, 5, 7, 1)
+    assert Y.min() >= 0 and Y.max() <= 7 and np.array_equal(Y, np.rint(Y))
+
+
+def test_anisotropic_clusters_small():
+    X = synth.anisotropic_clusters(2000, 96, 3, 10)
+    assert X.shape == (2000, 96) and np.isfinite(X).all()
+
+
+def test_batched_sizes():
+    b = synth.batched_datasets(64, 4)
+    Ns = [x.shape[0] for x, _ in b]
+    ds = {x.shape[1] for x, _ in b}
+    assert min(Ns) >= 500 and max(Ns) <= 20000 and ds <= {16, 64, 128}

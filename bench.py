@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--reorder", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the builds, copy this many MiB once (device to device) so that "
+                         "HBM counters can be scaled by a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -129,6 +132,13 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
+    if args.copy_probe_mib:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     evals = sum(stats[0]["evals"])
     for s in stats[1:]:
         assert s["evals"] == stats[0]["evals"] and s["changes"] == stats[0]["changes"], "non-deterministic build"

@@ -140,6 +140,11 @@ knng_status knng_export(knng_ctx* ctx, int32_t* d_ids, float* d_dists, uint8_t* 
  * (n_new, n_old per point). C = min(K, max(1, ceil(rho*K))). */
 knng_status knng_export_samples(knng_ctx* ctx, int32_t* d_new, int32_t* d_old, int32_t* d_counts);
 
+/* Storage order of the points: d_orig_of_pos[N] (int32, device) receives the
+ * original id stored at each position; the identity until the graph-ordered
+ * permutation (Sec. 3.2) has run. */
+knng_status knng_export_order(knng_ctx* ctx, int32_t* d_orig_of_pos);
+
 /* Statistics accumulated by the context so far (host). */
 knng_status knng_get_stats(const knng_ctx* ctx, knng_stats* stats);
 

@@ -71,13 +71,14 @@ def _load() -> ctypes.CDLL:
     L.knng_export.argtypes = [P, P, P, P]
     L.knng_export_samples.argtypes = [P, P, P, P]
     L.knng_get_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    L.knng_export_order.argtypes = [P, P]
     L.knng_destroy.argtypes = [P]
     L.knng_destroy.restype = None
     L.knng_sample_cap.argtypes = [i32, ctypes.c_double]
     L.knng_sample_cap.restype = i32
     L.knng_last_error.restype = ctypes.c_char_p
     for n in ("knng_build", "knng_create", "knng_init_graph", "knng_load_graph", "knng_iterate",
-              "knng_export", "knng_export_samples", "knng_get_stats"):
+              "knng_export", "knng_export_samples", "knng_get_stats", "knng_export_order"):
         getattr(L, n).restype = ctypes.c_int
     return L
 
@@ -229,6 +230,12 @@ class Context:
         _check(lib.knng_export_samples(self._h, ctypes.c_void_p(nw.data_ptr()), ctypes.c_void_p(od.data_ptr()),
                                        ctypes.c_void_p(cnt.data_ptr())))
         return nw, od, cnt
+
+    def order(self) -> torch.Tensor:
+        """Original id stored at each position (the permutation, once applied)."""
+        o = torch.empty(self.N, dtype=torch.int32, device=self.X.device)
+        _check(lib.knng_export_order(self._h, ctypes.c_void_p(o.data_ptr())))
+        return o
 
     def stats(self) -> dict:
         s = _Stats()

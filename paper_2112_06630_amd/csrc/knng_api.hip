@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <utility>
 #include <cstring>
 #include <string>
 
@@ -51,14 +52,15 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Plan {
     int path;        // resolved knng_path
+    int reorder;
     int dp;
     int C;
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
-    size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_poff,
-        o_pkey, o_ppos, o_scan, o_counters, o_comp, o_comp2, o_best, o_size, o_offs, o_newpos, o_lkey2,
-        o_lpos2, o_Xp2, o_orig2, o_flag;
+    size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
+        o_pkey, o_ppos, o_scan, o_counters, o_partial, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag;
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -74,7 +76,6 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "precision: only KNNG_FP32 is available");
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA) return fail(KNNG_EINVAL, "unknown path");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
-    if (p->reorder) return fail(KNNG_EINVAL, "reorder is not available in this build");
     return KNNG_OK;
 }
 
@@ -87,6 +88,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     if (path == KNNG_PATH_AUTO) path = (d >= 64 && 2 * P.C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
     if (path == KNNG_PATH_MFMA && 2 * P.C > 64) return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
     P.path = path;
+    P.reorder = p->reorder ? 1 : 0;
     P.dp = (int)(path == KNNG_PATH_MFMA ? round_up(d, 32) : round_up(d, 4));
     if (path == KNNG_PATH_VALU) {
         Views tv{};
@@ -118,21 +120,29 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     P.o_cand = take((size_t)N * 2 * C * 8);
     P.o_nn = take((size_t)N * 4);
     P.o_big = take((size_t)N * 4);
+    P.o_hubs = take((size_t)N * 4);
     P.o_poff = take(((size_t)N + 1) * 4);
     P.o_pkey = take((size_t)P.pmax * 8);
     P.o_ppos = take((size_t)P.pmax * 4);
     P.o_scan = take(scan_tmp_words((int)N) * 4);
     P.o_counters = take(kNumCounters * 8);
-    P.o_comp = take((size_t)N * 4);
-    P.o_comp2 = take((size_t)N * 4);
-    P.o_best = take((size_t)N * 8);
-    P.o_size = take((size_t)N * 4);
-    P.o_offs = take((size_t)N * 4);
-    P.o_newpos = take((size_t)N * 4);
-    P.o_lkey2 = take(NK * 8);
-    P.o_lpos2 = take(NK * 4);
-    P.o_Xp2 = take((size_t)N * P.dp * 4);
-    P.o_orig2 = take((size_t)N * 4);
+    P.o_partial = take(partial_words() * 8);
+    if (p->reorder) {   // permutation scratch only when the permutation is on
+        P.o_comp = take((size_t)N * 4);
+        P.o_comp2 = take((size_t)N * 4);
+        P.o_par = take((size_t)N * 4);
+        P.o_lvl = take((size_t)N * 4);
+        P.o_best = take((size_t)N * 8);
+        P.o_size = take((size_t)N * 4);
+        P.o_offs = take(((size_t)N + 1) * 4);
+        P.o_cur = take((size_t)N * 4);
+        P.o_newpos = take((size_t)N * 4);
+        P.o_lkey2 = take(NK * 8);
+        P.o_lpos2 = take(NK * 4);
+        P.o_Xp2 = take((size_t)N * P.dp * 4);
+        P.o_nrm2 = take((size_t)N * 4);
+        P.o_orig2 = take((size_t)N * 4);
+    }
     P.o_flag = take(64);
     P.total = off;
     return KNNG_OK;
@@ -162,21 +172,29 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.cand = reinterpret_cast<uint2*>(b + P.o_cand);
     v.nn = reinterpret_cast<uint32_t*>(b + P.o_nn);
     v.big = reinterpret_cast<uint32_t*>(b + P.o_big);
+    v.hubs = reinterpret_cast<uint32_t*>(b + P.o_hubs);
     v.poff = reinterpret_cast<uint32_t*>(b + P.o_poff);
     v.pkey = reinterpret_cast<uint64_t*>(b + P.o_pkey);
     v.ppos = reinterpret_cast<uint32_t*>(b + P.o_ppos);
     v.scan_tmp = reinterpret_cast<uint32_t*>(b + P.o_scan);
     v.counters = reinterpret_cast<uint64_t*>(b + P.o_counters);
-    v.comp = reinterpret_cast<int32_t*>(b + P.o_comp);
-    v.comp2 = reinterpret_cast<int32_t*>(b + P.o_comp2);
-    v.best = reinterpret_cast<uint64_t*>(b + P.o_best);
-    v.size = reinterpret_cast<uint32_t*>(b + P.o_size);
-    v.offs = reinterpret_cast<uint32_t*>(b + P.o_offs);
-    v.newpos = reinterpret_cast<int32_t*>(b + P.o_newpos);
-    v.lkey2 = reinterpret_cast<uint64_t*>(b + P.o_lkey2);
-    v.lpos2 = reinterpret_cast<uint32_t*>(b + P.o_lpos2);
-    v.Xp2 = reinterpret_cast<float*>(b + P.o_Xp2);
-    v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
+    v.partial = reinterpret_cast<uint64_t*>(b + P.o_partial);
+    if (P.reorder) {
+        v.comp = reinterpret_cast<int32_t*>(b + P.o_comp);
+        v.comp2 = reinterpret_cast<int32_t*>(b + P.o_comp2);
+        v.par = reinterpret_cast<int32_t*>(b + P.o_par);
+        v.lvl = reinterpret_cast<uint32_t*>(b + P.o_lvl);
+        v.best = reinterpret_cast<uint64_t*>(b + P.o_best);
+        v.size = reinterpret_cast<uint32_t*>(b + P.o_size);
+        v.offs = reinterpret_cast<uint32_t*>(b + P.o_offs);
+        v.cur = reinterpret_cast<uint32_t*>(b + P.o_cur);
+        v.newpos = reinterpret_cast<int32_t*>(b + P.o_newpos);
+        v.lkey2 = reinterpret_cast<uint64_t*>(b + P.o_lkey2);
+        v.lpos2 = reinterpret_cast<uint32_t*>(b + P.o_lpos2);
+        v.Xp2 = reinterpret_cast<float*>(b + P.o_Xp2);
+        v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
+        v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
+    }
     v.flag = reinterpret_cast<uint32_t*>(b + P.o_flag);
     return v;
 }
@@ -200,6 +218,7 @@ struct knng_ctx {
     const float* dX;
     int t;               // iterations completed
     bool permuted;
+    int perm_levels;
     bool has_graph;
     knng_stats stats;
     hipEvent_t ev[6];
@@ -218,6 +237,46 @@ float ms_between(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.f;
     return ms;
+}
+
+// Graph-ordered permutation (Sec. 3.2), once after iteration 1: cluster the
+// current lists level by level (a read-back every 4 levels to stop early),
+// lay the hook forest out, move rows and lists, and swap the buffers.
+knng_status do_permute(knng_ctx* c) {
+    Views& v = c->v;
+    hipStream_t s = c->stream;
+    HIP_TRY(hipEventRecord(c->ev[4], s));
+    launch_perm_begin(v, s);
+    uint32_t fl[4] = {0, 0, 0, 0};
+    for (int l = 0; l < perm_levels_max(); l += 4) {
+        for (int j = 0; j < 4; ++j) launch_perm_level(v, (uint32_t)(l + j), s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(fl, v.flag, sizeof(fl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (fl[0]) break;
+    }
+    launch_perm_finish(v, fl[2], s);
+    std::swap(v.Xp, v.Xp2);
+    std::swap(v.nrm, v.nrm2);
+    std::swap(v.orig, v.orig2);
+    std::swap(v.lkey, v.lkey2);
+    std::swap(v.lpos, v.lpos2);
+    launch_perm_posof(v, s);
+    HIP_TRY(hipEventRecord(c->ev[5], s));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    c->stats.reorder_ms = ms_between(c->ev[4], c->ev[5]);
+    c->perm_levels = (int)fl[2];
+    knng_status rs = read_counters(c);
+    if (rs != KNNG_OK) return rs;
+    if (c->hc[kCntError]) {
+        char buf[96];
+        snprintf(buf, sizeof buf, "device invariant failed in the permutation (code %llu)",
+                 (unsigned long long)c->hc[kCntError]);
+        return fail(KNNG_EDEVICE, buf);
+    }
+    c->permuted = true;
+    return KNNG_OK;
 }
 
 knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
@@ -267,13 +326,8 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     S.iters = t;
     c->t = t;
     if (t == 1 && c->p.reorder && !c->permuted) {
-        HIP_TRY(hipEventRecord(c->ev[4], s));
-        launch_permute(v, s);
-        HIP_TRY(hipEventRecord(c->ev[5], s));
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamSynchronize(s));
-        S.reorder_ms = ms_between(c->ev[4], c->ev[5]);
-        c->permuted = true;
+        knng_status ps = do_permute(c);
+        if (ps != KNNG_OK) return ps;
     }
     if (evals) *evals = e;
     if (changes) *changes = ch;
@@ -391,6 +445,13 @@ knng_status knng_export_samples(knng_ctx* c, int32_t* d_new, int32_t* d_old, int
     if (c->t < 1) return fail(KNNG_EINVAL, "no iteration has run");
     launch_export_samples(c->v, d_new, d_old, d_counts, c->stream);
     HIP_TRY(hipGetLastError());
+    return KNNG_OK;
+}
+
+knng_status knng_export_order(knng_ctx* c, int32_t* d_orig_of_pos) {
+    if (!c || !d_orig_of_pos) return fail(KNNG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(d_orig_of_pos, c->v.orig, sizeof(int32_t) * (size_t)c->N, hipMemcpyDeviceToDevice,
+                           c->stream));
     return KNNG_OK;
 }
 

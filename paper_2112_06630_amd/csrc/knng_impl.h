@@ -18,7 +18,7 @@ enum Counter : int {
     kCntPairs2 = 2,      // 2 * e_t (sum of per-target proposal capacities)
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
-    kCntBig = 5,         // owners whose pool exceeds one wave (select list length)
+    kCntHubs = 6,        // targets whose proposal bucket is merged by a workgroup
     kNumCounters = 8
 };
 
@@ -37,7 +37,8 @@ struct Views {
     uint4* rev;         // [N * K] reverse entries {w, orig src, pos src | flag, 0}
     uint2* cand;        // [N, 2C] sampled members {orig, pos}: new then old
     uint32_t* nn;       // [N] n_new | n_old << 16
-    uint32_t* big;      // [N] owners with pools of more than 64 entries
+    uint32_t* big;      // [N] 1: the owner's pool has more than 64 entries
+    uint32_t* hubs;     // [N] targets with large proposal buckets
     uint32_t* cap;      // [N] upper bound of proposals per target
     uint32_t* poff;     // [N + 1] proposal bucket offsets
     uint32_t* pcnt;     // [N] proposal bucket cursors
@@ -45,21 +46,27 @@ struct Views {
     uint32_t* ppos;     // [Pmax] proposal source positions
     uint32_t* scan_tmp; // scan scratch
     uint64_t* counters; // [kNumCounters]
+    uint64_t* partial;  // [partial_words()] per-block partial sums of the merge
     // permutation scratch
-    int32_t* comp;      // [N]
-    int32_t* comp2;     // [N]
-    uint64_t* best;     // [N]
-    uint32_t* size;     // [N]
-    uint32_t* offs;     // [N]
+    int32_t* comp;      // [N] component label (a position) of each point
+    int32_t* comp2;     // [N] pointer-jumping scratch
+    int32_t* par;       // [N] hook parent
+    uint32_t* lvl;      // [N] hook level (kNoLevel: never hooked)
+    uint64_t* best;     // [N] cheapest outgoing edge per component
+    uint32_t* size;     // [N] subtree size in the hook forest
+    uint32_t* offs;     // [N] first position of the subtree
+    uint32_t* cur;      // [N] allocation cursor
     int32_t* newpos;    // [N]
-    uint64_t* lkey2;    // [N, K] permute staging
+    uint64_t* lkey2;    // [N, K] permuted copies (swapped with the originals)
     uint32_t* lpos2;    // [N, K]
     float* Xp2;         // [N, dp]
+    float* nrm2;        // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
 };
 
 size_t scan_tmp_words(int n);
+size_t partial_words();
 
 // kernels (launchers; all enqueue on `s`)
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -78,7 +85,11 @@ void launch_merge(const Views& v, hipStream_t s);
 void launch_finish_counters(const Views& v, hipStream_t s);
 void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);
 void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t* counts, hipStream_t s);
-void launch_permute(const Views& v, hipStream_t s);
+int perm_levels_max();
+void launch_perm_begin(const Views& v, hipStream_t s);
+void launch_perm_level(const Views& v, uint32_t level, hipStream_t s);
+void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s);
+void launch_perm_posof(const Views& v, hipStream_t s);
 bool join_valu_fits(const Views& v);
 
 }  // namespace knng

@@ -170,6 +170,23 @@ __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t b, double rcp) {
     return q;
 }
 
+// Items are split into 8 contiguous ranges, one per XCD: workgroups are
+// dispatched round-robin over the 8 XCDs, so workgroup b runs on XCD b % 8,
+// and owners that are close in storage order (after the graph-ordered
+// permutation: close in the data space) then share one L2.
+struct XcdRange {
+    int next, end, step;
+};
+
+__device__ __forceinline__ XcdRange xcd_range(int n, int waves_per_block, int wave) {
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int x = b & 7, bi = b >> 3;
+    const int nbx = (G - x + 7) >> 3;           // workgroups on this XCD
+    const int per = (n + 7) >> 3;               // items per XCD range
+    const int lo = min(n, x * per), hi = min(n, lo + per);
+    return XcdRange{lo + bi * waves_per_block + wave, hi, nbx * waves_per_block};
+}
+
 static inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -536,9 +553,8 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st) {
     const int K = v.K, C = v.C;
     uint64_t* skey = L.key[w];
     uint32_t* spos = L.pos[w];
-    const int nbig = (int)v.counters[kCntBig];
-    for (int bi = blockIdx.x * kSelWaves + w; bi < nbig; bi += gridDim.x * kSelWaves) {
-        const int u = (int)v.big[bi];
+    for (int u = blockIdx.x * kSelWaves + w; u < v.N; u += gridDim.x * kSelWaves) {
+        if (!v.big[u]) continue;
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
         const uint32_t ou = (uint32_t)v.orig[u];
@@ -665,6 +681,179 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st) {
     }
 }
 
+// Large pools when 2C <= 64: per flag, a weight threshold T is searched so
+// that between 2C (>= C distinct members, as a member appears at most twice)
+// and 64 entries of that flag have w <= T; those are gathered into one lane
+// each and sorted like a small pool. Each search step is one ballot-count
+// pass over the pool. OLD entries whose member was sampled NEW are removed
+// by comparing with the (at most C) sampled new ids.
+__device__ __forceinline__ uint64_t sel_key(uint32_t wt, uint32_t id, uint32_t pf) {
+    return ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
+}
+
+__device__ __forceinline__ void pool_read(const Views& v, uint64_t st, int u, uint32_t ou, uint32_t rb, int i,
+                                          uint32_t& wt, uint32_t& id, uint32_t& pf) {
+    if (i < v.K) {
+        const size_t e = (size_t)u * v.K + i;
+        id = (uint32_t)v.lkey[e];
+        pf = v.lpos[e];
+        wt = pair_weight(st, ou, id);
+    } else {
+        const uint4 r = v.rev[rb + (uint32_t)(i - v.K)];
+        wt = r.x;
+        id = r.y;
+        pf = r.z;
+    }
+}
+
+constexpr int kSelLWaves = 4;
+
+__global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st) {
+    __shared__ uint64_t s_key[kSelLWaves][64];
+    __shared__ uint32_t s_idx[kSelLWaves][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int K = v.K;
+    const uint32_t C = (uint32_t)v.C;
+    for (int u = blockIdx.x * kSelLWaves + w; u < v.N; u += gridDim.x * kSelLWaves) {
+        if (!v.big[u]) continue;
+        const uint32_t rb = v.roff[u];
+        const int P = K + (int)(v.roff[u + 1] - rb);
+        const uint32_t ou = (uint32_t)v.orig[u];
+        uint32_t tot[2] = {0u, 0u};
+        for (int i0 = 0; i0 < P; i0 += 64) {
+            const int i = i0 + lane;
+            uint32_t wt = 0, id = 0, pf = 0;
+            if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+            tot[0] += __popcll(ballot(i < P && (pf & kNewBit)));
+            tot[1] += __popcll(ballot(i < P && !(pf & kNewBit)));
+        }
+        uint32_t newid = 0xffffffffu;  // lane r < nnew: id of the sampled new member of rank r
+        uint32_t nnew = 0, nold = 0;
+        bool nsel = false;             // this lane holds a sampled new member (position npos)
+        uint32_t npos = 0;
+        uint32_t flip_idx = 0xffffffffu, flip_pos = 0;
+        uint2* cs = v.cand + (size_t)u * 2 * C;
+        bool failed = false;
+        for (int f = 0; f < 2; ++f) {
+            // ---- threshold ----
+            uint32_t T = 0xffffffffu;
+            if (tot[f] > 64) {
+                const uint32_t need = 2 * C;
+                uint64_t lo = 0, hi = 0xffffffffull;
+                uint64_t t = ((uint64_t)((need + 64) / 2) << 32) / tot[f];
+                bool found = false;
+                for (int it = 0; it < 48 && !found; ++it) {
+                    uint32_t cnt = 0;
+                    for (int i0 = 0; i0 < P; i0 += 64) {
+                        const int i = i0 + lane;
+                        uint32_t wt = 0, id = 0, pf = 0;
+                        if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+                        const bool isf = ((pf & kNewBit) ? 0 : 1) == f;
+                        cnt += __popcll(ballot(i < P && isf && wt <= (uint32_t)t));
+                    }
+                    if (cnt >= need && cnt <= 64) {
+                        found = true;
+                    } else {
+                        if (cnt < need) lo = t; else hi = t;
+                        t = lo + (hi - lo) / 2;
+                        if (hi - lo <= 1) break;
+                    }
+                }
+                if (!found) {
+                    failed = true;
+                    break;
+                }
+                T = (uint32_t)t;
+            }
+            // ---- gather the survivors of flag f ----
+            uint32_t n = 0;
+            s_key[w][lane] = ~0ull;
+            wave_sync();
+            for (int i0 = 0; i0 < P; i0 += 64) {
+                const int i = i0 + lane;
+                uint32_t wt = 0, id = 0, pf = 0;
+                if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+                const bool surv = i < P && (((pf & kNewBit) ? 0 : 1) == f) && wt <= T;
+                const uint64_t m = ballot(surv);
+                const uint32_t slot = n + mbcnt(m);
+                if (surv && slot < 64) {
+                    s_key[w][slot] = sel_key(wt, id, pf);
+                    s_idx[w][slot] = (uint32_t)i;
+                }
+                n += (uint32_t)__popcll(m);
+            }
+            wave_sync();
+            if (n > 64) {
+                failed = true;
+                break;
+            }
+            uint64_t key = s_key[w][lane];
+            uint32_t idx = (uint32_t)lane < n ? s_idx[w][lane] : 0xffffffffu;
+            wave_sync();
+            wave_sort(key, idx);
+            const uint64_t p1 = shfl_up64(key, 1);
+            const bool real = key != ~0ull;
+            const bool dup = real && lane >= 1 && p1 == key;
+            const bool valid = real && !dup;
+            const uint64_t mv = ballot(valid);
+            const uint32_t r = mbcnt(mv);
+            const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
+            uint32_t pos = 0;
+            if (valid && r < C) {
+                uint32_t wt2, id2, pf2;
+                pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
+                pos = pf2 & kPosMask;
+            }
+            if (f == 0) {
+                const bool sel = valid && r < C;
+                const int s1 = __shfl_up(sel ? 1 : 0, 1);
+                nnew = min(C, (uint32_t)__popcll(mv));
+                if (sel) cs[r] = make_uint2(id, pos);
+                // forward NEW entries of sampled members flip to OLD once the OLD
+                // pass (which reads the flags as sampled) is done; the forward copy
+                // may be the duplicate (second) one
+                if (idx < (uint32_t)K && (sel || (dup && s1))) {
+                    uint32_t wt2, id2, pf2;
+                    pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
+                    flip_idx = idx;
+                    flip_pos = pf2 & kPosMask;
+                }
+                // sampled new ids to lanes 0..nnew-1 (they are the first valid lanes in order)
+                s_idx[w][lane] = 0xffffffffu;
+                wave_sync();
+                if (sel) s_idx[w][r] = id;
+                wave_sync();
+                newid = s_idx[w][lane];
+                wave_sync();
+                nsel = sel;
+                npos = pos;
+            } else {
+                bool innew = false;
+                for (uint32_t k = 0; k < nnew; ++k) {
+                    const uint32_t nk = rl32(newid, (int)k);
+                    innew |= nk == id;
+                }
+                const bool cand_old = valid && r < C;
+                const bool removed = cand_old && innew;
+                const uint64_t mrem = ballot(removed);
+                nold = min(C, (uint32_t)__popcll(mv)) - (uint32_t)__popcll(mrem);
+                if (cand_old && !removed) {
+                    cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
+                    if (nnew > 0) atomicAdd(&v.cap[pos], nnew);
+                }
+            }
+        }
+        if (failed) {
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
+            continue;
+        }
+        if (nsel) atomicAdd(&v.cap[npos], nnew - 1 + nold);
+        if (flip_idx != 0xffffffffu) v.lpos[(size_t)u * K + flip_idx] = flip_pos;
+        if (lane == 0) v.nn[u] = nnew | (nold << 16);
+        wave_sync();
+    }
+}
+
 // Pools of at most 64 entries, one per lane, in registers. Select key
 // (w << 32) | (id << 1) | old: sorting it puts the two copies of a member
 // reached by both routes with the same flag next to each other (the second
@@ -677,13 +866,8 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st) {
     for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
-        if (P > 64) {
-            if (lane == 0) {
-                const uint32_t slot = (uint32_t)atomicAdd((unsigned long long*)&v.counters[kCntBig], 1ull);
-                v.big[slot] = (uint32_t)u;
-            }
-            continue;
-        }
+        if (lane == 0) v.big[u] = P > 64 ? 1u : 0u;
+        if (P > 64) continue;
         const uint32_t ou = (uint32_t)v.orig[u];
         uint64_t key = ~0ull;
         uint32_t pos = 0;
@@ -741,17 +925,43 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st) {
 
 void launch_select(const Views& v, uint64_t st, hipStream_t s) {
     hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st);
-    hipLaunchKernelGGL(k_select_large, dim3(1024), dim3(256), 0, s, v, st);
+    if (2 * v.C <= 64)
+        hipLaunchKernelGGL(k_select_large_thr, dim3(grid_for(v.N, kSelLWaves, 4096)), dim3(256), 0, s, v, st);
+    else
+        hipLaunchKernelGGL(k_select_large, dim3(grid_for(v.N, kSelWaves, 4096)), dim3(256), 0, s, v, st);
 }
 
 // ------------------------------------------------------------------ join (a3, a4)
 
-// Append a proposal to the bucket of target position t. The capacity of each
-// bucket bounds its proposals by construction; the check keeps a violated
-// bound from writing outside it.
-__device__ __forceinline__ void emit(const Views& v, uint32_t t, uint64_t key, uint32_t src) {
-    const uint32_t slot = v.poff[t] + atomicAdd(&v.pcnt[t], 1u);
-    if (slot < v.poff[t + 1]) {
+// Proposals of one owner are bucketed in three steps so that the global
+// atomics are one per (owner, target member) instead of one per proposal:
+// count per member in LDS, reserve the member's share of its target's bucket
+// with one atomicAdd, then write each proposal at base + LDS cursor. The
+// capacity of each bucket bounds its proposals by construction; the check
+// keeps a violated bound from writing outside it.
+struct EmitLds {
+    uint32_t* cnt;   // [m] proposals per member (then the cursor)
+    uint32_t* base;  // [m] first slot reserved in the member's bucket
+    uint32_t* end;   // [m] end of the member's bucket
+};
+
+__device__ __forceinline__ void emit_count(const EmitLds& e, int t) { atomicAdd(&e.cnt[t], 1u); }
+
+__device__ __forceinline__ void emit_reserve(const Views& v, const EmitLds& e, const uint32_t* mpos, int m) {
+    wave_sync();
+    for (int t = lane_id(); t < m; t += 64) {
+        const uint32_t c = e.cnt[t];
+        const uint32_t pt = mpos[t];
+        e.base[t] = c ? v.poff[pt] + atomicAdd(&v.pcnt[pt], c) : 0u;
+        e.end[t] = v.poff[pt + 1];
+        e.cnt[t] = 0u;
+    }
+    wave_sync();
+}
+
+__device__ __forceinline__ void emit_write(const Views& v, const EmitLds& e, int t, uint64_t key, uint32_t src) {
+    const uint32_t slot = e.base[t] + atomicAdd(&e.cnt[t], 1u);
+    if (slot < e.end[t]) {
         v.pkey[slot] = key;
         v.ppos[slot] = src;
     } else {
@@ -759,11 +969,16 @@ __device__ __forceinline__ void emit(const Views& v, uint32_t t, uint64_t key, u
     }
 }
 
+__device__ __forceinline__ void emit_clear(const EmitLds& e, int m) {
+    for (int t = lane_id(); t < m; t += 64) e.cnt[t] = 0u;
+    wave_sync();
+}
+
 constexpr int kJoinWaves = 4;
 
-static inline size_t join_valu_wave_bytes(const Views& v) {
+__host__ __device__ static inline size_t join_valu_wave_bytes(const Views& v) {
     const size_t m = 2 * (size_t)v.C;
-    return m * v.dp * 4 + m * 16;
+    return m * v.dp * 4 + m * 28;
 }
 
 bool join_valu_fits(const Views& v) { return join_valu_wave_bytes(v) * kJoinWaves <= 64 * 1024; }
@@ -771,18 +986,23 @@ bool join_valu_fits(const Views& v) { return join_valu_wave_bytes(v) * kJoinWave
 // Low-d local join: one wave per owner; member rows staged in LDS, one lane
 // per (new member, member) cell; direct-form distances; each pair proposes
 // both ways, filtered against the targets' snapshot K-th keys (a proposal not
-// below that key can never enter the list).
+// below that key can never enter the list). The cells are walked twice:
+// once to count proposals per member, once (recomputing the cheap low-d
+// distance) to write them.
 __global__ __launch_bounds__(256) void k_join_valu(Views v) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int C2 = 2 * v.C, dp = v.dp, dp4 = dp >> 2, K = v.K;
     const double rdp4 = 1.0 / dp4;
-    unsigned char* base = smem + (size_t)w * ((size_t)C2 * dp * 4 + (size_t)C2 * 16);
+    unsigned char* base = smem + (size_t)w * join_valu_wave_bytes(v);
     float* rows = reinterpret_cast<float*>(base);
     uint64_t* thr = reinterpret_cast<uint64_t*>(base + (size_t)C2 * dp * 4);
     uint32_t* oid = reinterpret_cast<uint32_t*>(thr + C2);
     uint32_t* opos = oid + C2;
-    for (int u = blockIdx.x * kJoinWaves + w; u < v.N; u += gridDim.x * kJoinWaves) {
+    EmitLds el{opos + C2, opos + 2 * C2, opos + 3 * C2};
+    emit_clear(el, C2);
+    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
+    for (int u = xr.next; u < xr.end; u += xr.step) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
@@ -802,16 +1022,25 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
         wave_sync();
         const int ncell = nnew * m;
         const double rm = 1.0 / m;
-        for (int idx = lane; idx < ncell; idx += 64) {
-            const int i = (int)udiv((uint32_t)idx, (uint32_t)m, rm), j = idx - i * m;
-            if (j < nnew && j <= i) continue;
-            const float D = dist_direct(rows + (size_t)i * dp, rows + (size_t)j * dp, dp);
-            const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
-            const uint64_t ki = kb | oid[j], kj = kb | oid[i];
-            if (ki < thr[i]) emit(v, opos[i], ki, opos[j]);
-            if (kj < thr[j]) emit(v, opos[j], kj, opos[i]);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int idx = lane; idx < ncell; idx += 64) {
+                const int i = (int)udiv((uint32_t)idx, (uint32_t)m, rm), j = idx - i * m;
+                if (j < nnew && j <= i) continue;
+                const float D = dist_direct(rows + (size_t)i * dp, rows + (size_t)j * dp, dp);
+                const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
+                const uint64_t ki = kb | oid[j], kj = kb | oid[i];
+                if (pass == 0) {
+                    if (ki < thr[i]) emit_count(el, i);
+                    if (kj < thr[j]) emit_count(el, j);
+                } else {
+                    if (ki < thr[i]) emit_write(v, el, i, ki, opos[j]);
+                    if (kj < thr[j]) emit_write(v, el, j, kj, opos[i]);
+                }
+            }
+            if (pass == 0) emit_reserve(v, el, opos, m);
         }
         wave_sync();
+        emit_clear(el, m);
     }
 }
 
@@ -835,10 +1064,14 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
     __shared__ float s_nrm[kJoinWaves][64];
+    __shared__ uint32_t s_emit[kJoinWaves][3][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int C2 = 2 * v.C, dp = v.dp, K = v.K;
     const int c16 = lane & 15, g = lane >> 4;
-    for (int u = blockIdx.x * kJoinWaves + w; u < v.N; u += gridDim.x * kJoinWaves) {
+    EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
+    emit_clear(el, 64);
+    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
+    for (int u = xr.next; u < xr.end; u += xr.step) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
@@ -884,30 +1117,41 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
                             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[rt][q], f[ct][q], acc[t], 0, 0, 0);
             }
         }
-        // epilogue: lane holds rows 16rt + 4g + r, column 16ct + c16 of tile t
-        int t = 0;
+        // epilogue: lane holds rows 16rt + 4g + r, column 16ct + c16 of tile t;
+        // walked twice (count, then write)
+        for (int pass = 0; pass < 2; ++pass) {
+            int t = 0;
 #pragma unroll
-        for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
 #pragma unroll
-            for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t) {
-                if (!(rt < RT && ct < CT)) continue;
-                const int j = ct * 16 + c16;
-                if (j >= m) continue;
-                const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
-                const uint64_t tj = s_thr[w][j];
-                const float nj = s_nrm[w][j];
-                for (int r = 0; r < 4; ++r) {
-                    const int i = rt * 16 + g * 4 + r;
-                    if (i >= nnew || (j < nnew && j <= i)) continue;
-                    float D = (s_nrm[w][i] + nj) - 2.0f * acc[t][r];
-                    D = D > 0.f ? D : 0.f;
-                    const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
-                    const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
-                    if (ki < s_thr[w][i]) emit(v, s_pos[w][i], ki, pj);
-                    if (kj < tj) emit(v, pj, kj, s_pos[w][i]);
+                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t) {
+                    if (!(rt < RT && ct < CT)) continue;
+                    const int j = ct * 16 + c16;
+                    if (j >= m) continue;
+                    const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
+                    const uint64_t tj = s_thr[w][j];
+                    const float nj = s_nrm[w][j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = rt * 16 + g * 4 + r;
+                        if (i >= nnew || (j < nnew && j <= i)) continue;
+                        float D = (s_nrm[w][i] + nj) - 2.0f * acc[t][r];
+                        D = D > 0.f ? D : 0.f;
+                        const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
+                        const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
+                        if (pass == 0) {
+                            if (ki < s_thr[w][i]) emit_count(el, i);
+                            if (kj < tj) emit_count(el, j);
+                        } else {
+                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki, pj);
+                            if (kj < tj) emit_write(v, el, j, kj, s_pos[w][i]);
+                        }
+                    }
                 }
-            }
+            if (pass == 0) emit_reserve(v, el, s_pos[w], m);
+        }
         wave_sync();
+        emit_clear(el, m);
     }
 }
 
@@ -918,16 +1162,134 @@ void launch_join_mfma(const Views& v, hipStream_t s) {
 // ------------------------------------------------------------------ merge (a5)
 
 constexpr int kMergeWaves = 4;
+constexpr uint32_t kHubProposals = 1024;  // buckets above this are merged by a whole workgroup
+constexpr int kHubWaves = 16;
+constexpr int kMergeBlocks = 4096;      // partial-sum slots of k_merge
+constexpr int kHubBlocks = 512;
 
-// One wave per target with proposals. The list sits one entry per lane,
-// ascending; lanes >= K hold +inf. Proposals are read 64 at a time and
-// dropped when not below the current K-th key or when their id is in the
-// snapshot list or already in the current list. A chunk with few survivors
-// inserts them one by one (ballot rank, shift up); a larger one is sorted
-// (bitonic), reversed and folded into the list with a lane-wise min, which
-// leaves a bitonic sequence holding the 64 smallest keys, sorted again by one
-// half-cleaner pass; equal keys (one id proposed by two owners) are then
-// collapsed. Entries that enter are NEW; c_t counts ids not in the snapshot.
+// Folds proposals src[c0 .. n) (chunks of 64, every `stride` elements) into
+// the list held one entry per lane in (key, pf), ascending, +inf beyond K.
+// A proposal is dropped when it is not below the current K-th key, or its id
+// is in the snapshot list or already in the list. A chunk with few
+// survivors inserts them one by one (ballot rank, shift up); a larger one is
+// sorted (bitonic), reversed and folded into the list with a lane-wise min,
+// which leaves a bitonic sequence holding the 64 smallest keys, sorted again
+// by one half-cleaner pass; equal keys (one id proposed by two owners) are
+// then collapsed through LDS (sk, sp: 64 slots of this wave).
+__device__ void merge_chunks(const uint64_t* pks, const uint32_t* pps, uint32_t c0, uint32_t n, uint32_t stride,
+                             int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth, bool& grown,
+                             uint64_t* sk, uint32_t* sp) {
+    const int lane = lane_id();
+    uint64_t nk = ~0ull;
+    uint32_t np = 0;
+    if (c0 + (uint32_t)lane < n) {
+        nk = pks[c0 + lane];
+        np = pps[c0 + lane];
+    }
+    for (; c0 < n; c0 += stride) {
+        uint64_t pk = nk;
+        uint32_t pp = np | kNewBit;
+        // next chunk in flight while this one is merged
+        nk = ~0ull;
+        np = 0;
+        if (c0 + stride + (uint32_t)lane < n) {
+            nk = pks[c0 + stride + lane];
+            np = pps[c0 + stride + lane];
+        }
+        bool ok = pk < kth;
+        if (ballot(ok) == 0) continue;
+        const uint32_t pid = (uint32_t)pk;
+        for (int k = 0; k < K; ++k) {
+            const uint32_t sidk = rl32(snap, k);
+            ok &= sidk != pid;
+        }
+        if (grown) {
+            const uint32_t cur = (uint32_t)key;
+            for (int k = 0; k < K; ++k) {
+                const uint32_t cidk = rl32(cur, k);
+                ok &= cidk != pid;
+            }
+        }
+        uint64_t mask = ballot(ok);
+        if (mask == 0) continue;
+        grown = true;
+        if (__popcll(mask) <= 4) {
+            while (mask) {
+                const int j = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const uint64_t x = rl64(pk, j);
+                if (x >= kth) continue;
+                if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;  // same id, same key
+                const uint32_t xp = rl32(pp, j);
+                const int at = __popcll(ballot(lane < K && key < x));
+                const uint64_t ku = shfl_up64(key, 1);
+                const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
+                if (lane > at && lane < K) {
+                    key = ku;
+                    pf = pu;
+                }
+                if (lane == at) {
+                    key = x;
+                    pf = xp;
+                }
+                kth = rl64(key, K - 1);
+            }
+        } else {
+            if (!ok) pk = ~0ull;
+            wave_sort(pk, pp);
+            const uint64_t rk = shfl64(pk, 63 - lane);
+            const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
+            if (rk < key) {
+                key = rk;
+                pf = rp;
+            }
+            wave_bitonic_clean(key, pf);
+            const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
+            const bool dupk = lane > 0 && key != ~0ull && prevk == key;
+            const uint64_t dm = ballot(dupk);
+            if (dm) {
+                sk[lane] = ~0ull;
+                wave_sync();
+                if (!dupk) {
+                    const uint32_t to = (uint32_t)lane - mbcnt(dm);
+                    sk[to] = key;
+                    sp[to] = pf;
+                }
+                wave_sync();
+                key = sk[lane];
+                pf = sp[lane];
+                wave_sync();
+            }
+            if (lane >= K) {
+                key = ~0ull;
+                pf = 0u;
+            }
+            kth = rl64(key, K - 1);
+        }
+    }
+}
+
+// Writes a merged row back; checks that no id appears twice (that would
+// mean two different keys for one pair) and counts ids not in the snapshot.
+__device__ __forceinline__ uint64_t finish_merged_row(const Views& v, size_t row, uint64_t key, uint32_t pf,
+                                                      uint32_t snap) {
+    const int lane = lane_id(), K = v.K;
+    bool twice = false, entered = lane < K;
+    for (int k = 0; k < K; ++k) {
+        const uint32_t ik = rl32((uint32_t)key, k);
+        const uint32_t sk = rl32(snap, k);
+        twice |= lane < K && k != lane && ik == (uint32_t)key;
+        entered &= sk != (uint32_t)key;
+    }
+    if (ballot(twice) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 8ull);
+    if (lane < K) {
+        v.lkey[row + lane] = key;
+        v.lpos[row + lane] = pf;
+    }
+    return (uint64_t)__popcll(ballot(entered));
+}
+
+// One wave per target; buckets above kHubProposals go to k_merge_hubs.
 __global__ __launch_bounds__(256) void k_merge(Views v) {
     __shared__ uint64_t s_k[kMergeWaves][64];
     __shared__ uint32_t s_p[kMergeWaves][64];
@@ -938,117 +1300,122 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         const uint32_t base = v.poff[p];
         const uint32_t n = min(v.pcnt[p], v.poff[p + 1] - base);
         if (n == 0) continue;
+        if (n > kHubProposals) {
+            if (lane == 0) {
+                const uint32_t slot = (uint32_t)atomicAdd((unsigned long long*)&v.counters[kCntHubs], 1ull);
+                v.hubs[slot] = (uint32_t)p;
+            }
+            continue;
+        }
         const size_t row = (size_t)p * K;
         uint64_t key = lane < K ? v.lkey[row + lane] : ~0ull;
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
-        bool grown = false;  // list holds entries from proposals
-        for (uint32_t c0 = 0; c0 < n; c0 += 64) {
-            const uint32_t i = c0 + (uint32_t)lane;
-            uint64_t pk = ~0ull;
-            uint32_t pp = 0;
-            if (i < n) {
-                pk = v.pkey[base + i];
-                pp = v.ppos[base + i] | kNewBit;
-            }
-            bool ok = pk < kth;
-            if (__popcll(ballot(ok)) == 0) continue;
-            const uint32_t pid = (uint32_t)pk;
-            for (int k = 0; k < K; ++k) ok &= rl32(snap, k) != pid;
-            if (grown) {
-                const uint32_t cur = (uint32_t)key;
-                for (int k = 0; k < K; ++k) ok &= rl32(cur, k) != pid;
-            }
-            uint64_t mask = ballot(ok);
-            if (mask == 0) continue;
-            grown = true;
-            if (__popcll(mask) <= 4) {
-                while (mask) {
-                    const int j = __ffsll((long long)mask) - 1;
-                    mask &= mask - 1;
-                    const uint64_t x = rl64(pk, j);
-                    if (x >= kth) continue;
-                    if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;  // same id, same key
-                    const uint32_t xp = rl32(pp, j);
-                    const int at = __popcll(ballot(lane < K && key < x));
-                    const uint64_t ku = shfl_up64(key, 1);
-                    const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
-                    if (lane > at && lane < K) {
-                        key = ku;
-                        pf = pu;
-                    }
-                    if (lane == at) {
-                        key = x;
-                        pf = xp;
-                    }
-                    kth = rl64(key, K - 1);
-                }
-            } else {
-                if (!ok) pk = ~0ull;
-                wave_sort(pk, pp);
-                const uint64_t rk = shfl64(pk, 63 - lane);
-                const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
-                if (rk < key) {
-                    key = rk;
-                    pf = rp;
-                }
-                wave_bitonic_clean(key, pf);
-                const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
-                const bool dupk = lane > 0 && key != ~0ull && prevk == key;
-                const uint64_t dm = ballot(dupk);
-                if (dm) {
-                    s_k[w][lane] = ~0ull;
-                    wave_sync();
-                    if (!dupk) {
-                        const uint32_t to = (uint32_t)lane - mbcnt(dm);
-                        s_k[w][to] = key;
-                        s_p[w][to] = pf;
-                    }
-                    wave_sync();
-                    key = s_k[w][lane];
-                    pf = s_p[w][lane];
-                    wave_sync();
-                }
-                if (lane >= K) {
-                    key = ~0ull;
-                    pf = 0u;
-                }
-                kth = rl64(key, K - 1);
-            }
-        }
-        // an id twice in a row would mean two different keys for one pair
-        bool twice = false;
-        for (int k = 0; k < K; ++k) {
-            const uint32_t ik = rl32((uint32_t)key, k);
-            twice |= lane < K && k != lane && ik == (uint32_t)key;
-        }
-        if (ballot(twice) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 8ull);
-        bool entered = lane < K;
-        for (int k = 0; k < K; ++k) entered &= rl32(snap, k) != (uint32_t)key;
-        if (lane < K) {
-            v.lkey[row + lane] = key;
-            v.lpos[row + lane] = pf;
-        }
-        changes += (uint64_t)__popcll(ballot(entered));
+        bool grown = false;
+        merge_chunks(v.pkey + base, v.ppos + base, 0, n, 64, K, snap, key, pf, kth, grown, s_k[w], s_p[w]);
+        changes += finish_merged_row(v, row, key, pf, snap);
         props += n;
     }
-    if (lane == 0 && (changes | props)) {
-        atomicAdd((unsigned long long*)&v.counters[kCntChanges], (unsigned long long)changes);
-        atomicAdd((unsigned long long*)&v.counters[kCntProposals], (unsigned long long)props);
+    // per-block partial sums (no same-address atomics); summed by k_finish_counters
+    __shared__ uint64_t s_red[kMergeWaves][2];
+    if (lane == 0) {
+        s_red[w][0] = changes;
+        s_red[w][1] = props;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0;
+        for (int i = 0; i < kMergeWaves; ++i) {
+            a += s_red[i][0];
+            b += s_red[i][1];
+        }
+        v.partial[2 * blockIdx.x] = a;
+        v.partial[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// Targets with large buckets: 16 waves each fold a strided share of the
+// bucket into their own copy of the list; wave 0 then folds the other 15
+// partial lists (from LDS) into its own. Equal to folding the whole bucket,
+// since the K smallest of a union are the K smallest of the partial results.
+__global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
+    __shared__ uint64_t s_k[kHubWaves][64];
+    __shared__ uint32_t s_p[kHubWaves][64];
+    __shared__ uint64_t s_lk[kHubWaves][64];
+    __shared__ uint32_t s_lp[kHubWaves][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int K = v.K;
+    const int nh = (int)v.counters[kCntHubs];
+    uint64_t changes = 0, props = 0;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int p = (int)v.hubs[h];
+        const uint32_t base = v.poff[p];
+        const uint32_t n = min(v.pcnt[p], v.poff[p + 1] - base);
+        const size_t row = (size_t)p * K;
+        uint64_t key = lane < K ? v.lkey[row + lane] : ~0ull;
+        uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
+        const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
+        uint64_t kth = rl64(key, K - 1);
+        bool grown = false;
+        merge_chunks(v.pkey + base, v.ppos + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth,
+                     grown, s_k[w], s_p[w]);
+        s_lk[w][lane] = key;
+        s_lp[w][lane] = pf & kPosMask;  // merge_chunks marks folded entries NEW again
+        __syncthreads();
+        if (w == 0) {
+            // partial lists keep their flags: pass them with the NEW bit only where they had it
+            merge_chunks(&s_lk[1][0], &s_lp[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth, grown,
+                         s_k[0], s_p[0]);
+            changes += finish_merged_row(v, row, key, pf, snap);
+            props += n;
+        }
+        __syncthreads();
+    }
+    if (w == 0 && lane == 0) {
+        v.partial[2 * (kMergeBlocks + blockIdx.x)] = changes;
+        v.partial[2 * (kMergeBlocks + blockIdx.x) + 1] = props;
     }
 }
 
 void launch_merge(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(v.N, kMergeWaves, 4096)), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_merge, dim3(kMergeBlocks), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_merge_hubs, dim3(kHubBlocks), dim3(1024), 0, s, v);
 }
 
-__global__ void k_finish_counters(Views v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) v.counters[kCntPairs2] = v.poff[v.N];
+size_t partial_words() { return 2 * (size_t)(kMergeBlocks + kHubBlocks); }
+
+__global__ __launch_bounds__(1024) void k_finish_counters(Views v) {
+    __shared__ uint64_t s_a[16], s_b[16];
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    uint64_t a = 0, b = 0;
+    for (int i = t; i < kMergeBlocks + kHubBlocks; i += 1024) {
+        a += v.partial[2 * i];
+        b += v.partial[2 * i + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += shfl_xor64(a, o);
+        b += shfl_xor64(b, o);
+    }
+    if (lane == 0) {
+        s_a[w] = a;
+        s_b[w] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint64_t sa = 0, sb = 0;
+        for (int i = 0; i < 16; ++i) {
+            sa += s_a[i];
+            sb += s_b[i];
+        }
+        v.counters[kCntChanges] = sa;
+        v.counters[kCntProposals] = sb;
+        v.counters[kCntPairs2] = v.poff[v.N];
+    }
 }
 
 void launch_finish_counters(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(64), 0, s, v);
+    hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(1024), 0, s, v);
 }
 
 // ------------------------------------------------------------------ finalize (a8)
@@ -1093,7 +1460,215 @@ void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t
 }
 
 // ------------------------------------------------------------------ permutation (a7)
+//
+// Sec. 3.2 reorders the points once, early, so that points close in the data
+// space are close in memory; its greedy Alg. 1 is one sequential pass. The
+// device version clusters the current K-NN graph with Boruvka-style hooking:
+// at every level each component picks its cheapest edge (distance, entry
+// index) to another component among the first kPermEdges entries of its
+// members' lists, both endpoints competing for it, and hooks into the other
+// component (the smaller label stays root when two components pick the same
+// edge, the only possible cycle). The hook forest is laid out in post-order
+// with the children of a node ordered by decreasing hook level, so every
+// component of every level occupies a contiguous range of positions. The
+// permutation is invisible in the results: hashes and tie-breaks use
+// original ids.
+constexpr uint32_t kNoLevel = 0xffffffffu;
+constexpr int kPermEdges = 8;
 
-void launch_permute(const Views&, hipStream_t) {}
+__global__ void k_perm_init(Views v) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < v.N; p += gridDim.x * blockDim.x) {
+        v.comp[p] = p;
+        v.par[p] = p;
+        v.lvl[p] = kNoLevel;
+        v.size[p] = 1u;
+        v.cur[p] = 0u;
+        v.best[p] = ~0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) v.flag[threadIdx.x] = 0u;
+}
+
+// flag[0]: clustering finished (a level hooked nothing); flag[1]: a hook happened this level
+__global__ void k_perm_edges(Views v) {
+    if (v.flag[0]) return;
+    const int E = min(v.K, kPermEdges);
+    const int64_t total = (int64_t)v.N * E;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int u = (int)(i / E), k = (int)(i - (int64_t)u * E);
+        const uint32_t e = (uint32_t)u * (uint32_t)v.K + (uint32_t)k;
+        const int pv = (int)(v.lpos[e] & kPosMask);
+        const int cu = v.comp[u], cv = v.comp[pv];
+        if (cu == cv) continue;
+        const uint64_t key = ((v.lkey[e] >> 32) << 32) | e;
+        if (key < v.best[cu]) atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)key);
+        if (key < v.best[cv]) atomicMin((unsigned long long*)&v.best[cv], (unsigned long long)key);
+    }
+}
+
+__global__ void k_perm_hook(Views v, uint32_t level) {
+    if (v.flag[0]) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x) {
+        int jump = c;
+        if (v.comp[c] == c) {
+            const uint64_t b = v.best[c];
+            if (b != ~0ull) {
+                const uint32_t e = (uint32_t)b;
+                const int u = (int)(e / (uint32_t)v.K);
+                const int pv = (int)(v.lpos[e] & kPosMask);
+                const int cu = v.comp[u];
+                const int other = cu == c ? v.comp[pv] : cu;
+                const bool mutual = v.best[other] == b;
+                if (!(mutual && c < other)) {
+                    v.par[c] = other;
+                    v.lvl[c] = level;
+                    jump = other;
+                    v.flag[1] = 1u;
+                }
+            }
+        }
+        v.comp2[c] = jump;
+    }
+}
+
+// pointer jumping among this level's roots: comp2 converges to the new root.
+// A root that hooked at this level takes that new root as its parent, so the
+// hooks of one level form stars (a chain A->B->C within one level would make
+// the subtree sizes depend on the order in which the level is summed).
+__global__ void k_perm_jump(Views v, uint32_t level) {
+    if (v.flag[0]) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x) {
+        if (v.comp[c] != c) continue;
+        int x = v.comp2[c];
+        // hook chains among one level's roots are acyclic (two components that
+        // pick the same edge keep the smaller label as root); the step cap only
+        // turns a violated invariant into an error instead of a spin
+        int steps = 0;
+        for (; steps < 4096; ++steps) {
+            const int y = v.comp2[x];
+            if (y == x) break;
+            x = y;
+        }
+        if (steps == 4096) atomicOr((unsigned long long*)&v.counters[kCntError], 32ull);
+        v.comp2[c] = x;
+        if (v.lvl[c] == level) v.par[c] = x;
+    }
+}
+
+__global__ void k_perm_relabel(Views v) {
+    if (v.flag[0]) return;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < v.N; p += gridDim.x * blockDim.x) {
+        v.comp[p] = v.comp2[v.comp[p]];
+        v.best[p] = ~0ull;
+    }
+}
+
+__global__ void k_perm_level_end(Views v) {
+    if (v.flag[0]) return;
+    if (!v.flag[1]) v.flag[0] = 1u;
+    v.flag[1] = 0u;
+    v.flag[2] += 1u;  // levels run
+}
+
+__global__ void k_perm_sizes(Views v, uint32_t level) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x)
+        if (v.lvl[c] == level) atomicAdd(&v.size[v.par[c]], v.size[c]);
+}
+
+__global__ void k_perm_rootsz(Views v) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x)
+        v.cur[c] = v.lvl[c] == kNoLevel ? v.size[c] : 0u;
+}
+
+__global__ void k_perm_clear_cur(Views v) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x) v.cur[c] = 0u;
+}
+
+// children get the next free block of their parent's range, highest hook level first
+__global__ void k_perm_offsets(Views v, uint32_t level) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x)
+        if (v.lvl[c] == level) {
+            const int pa = v.par[c];
+            v.offs[c] = v.offs[pa] + atomicAdd(&v.cur[pa], v.size[c]);
+        }
+}
+
+// post-order: a node sits at the end of its subtree's range
+__global__ void k_perm_newpos(Views v) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < v.N; c += gridDim.x * blockDim.x)
+        v.newpos[c] = (int32_t)(v.offs[c] + v.size[c] - 1u);
+}
+
+__global__ void k_perm_rows(Views v) {
+    const int dp4 = v.dp >> 2;
+    const int64_t total = (int64_t)v.N * dp4;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(i / dp4), c = (int)(i - (int64_t)p * dp4);
+        const int q = v.newpos[p];
+        if (q < 0 || q >= v.N) {
+            atomicOr((unsigned long long*)&v.counters[kCntError], 64ull);
+            continue;
+        }
+        reinterpret_cast<float4*>(v.Xp2 + (size_t)q * v.dp)[c] = reinterpret_cast<const float4*>(v.Xp + (size_t)p * v.dp)[c];
+        if (c == 0) {
+            v.orig2[q] = v.orig[p];
+            v.nrm2[q] = v.nrm[p];
+        }
+    }
+}
+
+__global__ void k_perm_lists(Views v) {
+    const int64_t NK = (int64_t)v.N * v.K;
+    const double rk = 1.0 / v.K;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)udiv((uint32_t)e, (uint32_t)v.K, rk), k = (int)(e - (int64_t)p * v.K);
+        const int q = v.newpos[p];
+        const uint32_t pf = v.lpos[e];
+        const int qn = v.newpos[pf & kPosMask];
+        if (q < 0 || q >= v.N || qn < 0 || qn >= v.N) {
+            atomicOr((unsigned long long*)&v.counters[kCntError], 64ull);
+            continue;
+        }
+        const size_t to = (size_t)q * v.K + k;
+        v.lkey2[to] = v.lkey[e];
+        v.lpos2[to] = (uint32_t)qn | (pf & kNewBit);
+    }
+}
+
+__global__ void k_perm_posof(Views v) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < v.N; p += gridDim.x * blockDim.x) v.posof[v.orig[p]] = p;
+}
+
+int perm_levels_max() { return 32; }
+
+void launch_perm_begin(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_init, dim3(grid_for(v.N, 256, 8192)), dim3(256), 0, s, v);
+}
+
+void launch_perm_level(const Views& v, uint32_t level, hipStream_t s) {
+    const int g = grid_for(v.N, 256, 8192);
+    hipLaunchKernelGGL(k_perm_edges, dim3(grid_for((int64_t)v.N * min(v.K, kPermEdges), 256, 16384)), dim3(256), 0,
+                       s, v);
+    hipLaunchKernelGGL(k_perm_hook, dim3(g), dim3(256), 0, s, v, level);
+    hipLaunchKernelGGL(k_perm_jump, dim3(g), dim3(256), 0, s, v, level);
+    hipLaunchKernelGGL(k_perm_relabel, dim3(g), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_perm_level_end, dim3(1), dim3(1), 0, s, v);
+}
+
+void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s) {
+    const int g = grid_for(v.N, 256, 8192);
+    for (uint32_t l = 0; l < levels; ++l) hipLaunchKernelGGL(k_perm_sizes, dim3(g), dim3(256), 0, s, v, l);
+    hipLaunchKernelGGL(k_perm_rootsz, dim3(g), dim3(256), 0, s, v);
+    launch_scan(v.cur, v.offs, v.N, v.scan_tmp, s);
+    hipLaunchKernelGGL(k_perm_clear_cur, dim3(g), dim3(256), 0, s, v);
+    for (int l = (int)levels - 1; l >= 0; --l)
+        hipLaunchKernelGGL(k_perm_offsets, dim3(g), dim3(256), 0, s, v, (uint32_t)l);
+    hipLaunchKernelGGL(k_perm_newpos, dim3(g), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_perm_rows, dim3(grid_for((int64_t)v.N * (v.dp >> 2), 256, 16384)), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_perm_lists, dim3(grid_for((int64_t)v.N * v.K, 256, 16384)), dim3(256), 0, s, v);
+}
+
+void launch_perm_posof(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_posof, dim3(grid_for(v.N, 256, 8192)), dim3(256), 0, s, v);
+}
 
 }  // namespace knng

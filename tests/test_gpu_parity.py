@@ -196,3 +196,48 @@ def test_deterministic_repeat(knng):
     b = knng.build(dev(X), 10, 1.0, 0.001, 20, 0)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
     assert a[2]["evals"] == b[2]["evals"] and a[2]["changes"] == b[2]["changes"]
+
+
+# ----------------------------------------------------------------- permutation (Sec. 3.2)
+
+@pytest.mark.parametrize("path", ["valu", "mfma"])
+def test_permutation_is_result_invisible_integer(knng, path):
+    """Reordering changes storage only: ids, distances, e_t, c_t stay bitwise equal."""
+    d = 8 if path == "valu" else 72
+    X = synth.integer_points(3000, d, 9, 21)
+    a = knng.build(dev(X), 12, 0.8, 0.001, 15, 5, reorder=False, path=path)
+    b = knng.build(dev(X), 12, 0.8, 0.001, 15, 5, reorder=True, path=path)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2]["evals"] == b[2]["evals"] and a[2]["changes"] == b[2]["changes"]
+    assert b[2]["reorder_ms"] > 0
+    st = exact_build(knng, X, 12, 0.8, 0.001, 15, 5, path=path, reorder=True)
+    assert st["iters"] == a[2]["iters"]
+
+
+def test_permutation_is_result_invisible_cfg1(knng):
+    X, p = synth.config(1)
+    a = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=False)
+    b = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_permutation_order_and_cluster_purity(knng):
+    """The order is a permutation; on data satisfying the clustered assumption
+    (Sec. 3.2) each cluster ends up in (nearly) one contiguous run of
+    positions, in contrast with the random input order. Fig. 4 tracks the
+    same property as cluster fractions in sliding windows."""
+    X, lab = synth.clustered_labels(16384, 8, 8, 3)
+    ctx = knng.Context(dev(X), 20, rho=1.0, seed=1, reorder=True)
+    ctx.init()
+    ctx.iterate()
+    ctx.iterate()
+    order = ctx.order().cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(16384))
+    seq = lab[order]
+    changes = int((seq[1:] != seq[:-1]).sum())
+    assert changes <= 64, changes                      # random order: ~14000
+    for c in range(8):
+        idx = np.nonzero(seq == c)[0]
+        runs = np.split(idx, np.nonzero(np.diff(idx) != 1)[0] + 1)
+        assert max(len(r) for r in runs) >= 0.9 * len(idx)
+    ctx.close()

@@ -21,8 +21,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-WORKLOAD = dict(workload="image60k_d784", N=60000, d=784, K=20, rho=1.0, delta=0.001, max_iters=30, seed=1)
+WORKLOADS = {
+    # the headline workload (default)
+    "image60k_d784": dict(workload="image60k_d784", N=60000, d=784, K=20, rho=1.0, delta=0.001, max_iters=30,
+                          seed=1, gen=lambda: __import__("synth").image_like(60000, 1)),
+    "gauss2k_d8": dict(workload="gauss2k_d8", N=2000, d=8, K=10, rho=1.0, delta=0.001, max_iters=20, seed=0,
+                       gen=lambda: __import__("synth").config(1)[0]),
+    "blobs4m_d3": dict(workload="blobs4m_d3", N=4_000_000, d=3, K=15, rho=0.5, delta=0.001, max_iters=30, seed=2,
+                       gen=lambda: __import__("synth").lowd_blobs(4_000_000, 2)),
+    "aniso200k_d960": dict(workload="aniso200k_d960", N=200_000, d=960, K=20, rho=0.5, delta=0.001, max_iters=30,
+                           seed=3, gen=lambda: __import__("synth").anisotropic_clusters(200_000, 960, 3)),
+}
+WORKLOAD = WORKLOADS["image60k_d784"]
 
 
 def kernel_source_hash() -> str:
@@ -32,31 +44,33 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def exact_kth(X, K):
-    """Exact K-th neighbour distance per row (FP64, self excluded), on the GPU with torch."""
+def exact_kth(X, K, rows):
+    """Exact K-th neighbour distance (FP64, self excluded) of the query rows,
+    on the GPU with torch (evaluation only, not the method's path)."""
     import torch
     Xd = X.double()
     n = (Xd * Xd).sum(1)
-    N = X.shape[0]
-    out = torch.empty(N, dtype=torch.float64, device=X.device)
-    for s in range(0, N, 4096):
-        e = min(N, s + 4096)
-        D = n[s:e, None] + n[None, :] - 2.0 * (Xd[s:e] @ Xd.T)
-        D[torch.arange(e - s, device=X.device), torch.arange(s, e, device=X.device)] = float("inf")
-        out[s:e] = torch.topk(D, K, dim=1, largest=False).values[:, -1]
+    out = torch.empty(len(rows), dtype=torch.float64, device=X.device)
+    step = max(1, min(4096, (1 << 28) // X.shape[0]))
+    for s in range(0, len(rows), step):
+        r = rows[s:s + step]
+        D = n[r, None] + n[None, :] - 2.0 * (Xd[r] @ Xd.T)
+        D[torch.arange(len(r), device=X.device), r] = float("inf")
+        out[s:s + step] = torch.topk(D, K, dim=1, largest=False).values[:, -1]
     return out
 
 
-def recall_of(X, ids, tau, rel=1e-5):
-    import torch
+def recall_of(X, ids, tau, rows, rel=1e-5):
+    """Tie-aware recall over the query rows: a found id counts when its FP64
+    distance is within rel of the exact K-th distance."""
     Xd = X.double()
     good = 0
-    for s in range(0, X.shape[0], 2048):
-        e = min(X.shape[0], s + 2048)
-        diff = Xd[ids[s:e].long()] - Xd[s:e, None, :]
+    for s in range(0, len(rows), 2048):
+        r = rows[s:s + 2048]
+        diff = Xd[ids[r].long()] - Xd[r, None, :]
         D = (diff * diff).sum(-1)
-        good += int((D <= tau[s:e, None] * (1 + rel) + 1e-9).sum())
-    return good / ids.numel()
+        good += int((D <= tau[s:s + 2048, None] * (1 + rel) + 1e-9).sum())
+    return good / (len(rows) * ids.shape[1])
 
 
 def cpu_baseline(Xnp, w, budget_s=20.0):
@@ -97,6 +111,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--reorder", type=int, default=0)
+    ap.add_argument("--workload", default="image60k_d784", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--recall-rows", type=int, default=100000,
+                    help="query rows for recall (all rows when N is smaller; a seeded sample otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -112,16 +130,17 @@ def main():
     import synth
     import paper_2112_06630_amd as knng
 
-    w = WORKLOAD
-    Xnp = synth.image_like(w["N"], w["seed"])
+    w = WORKLOADS[args.workload]
+    Xnp = w["gen"]()
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
-    p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder))
+    p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+                         precision=args.precision)
     ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
     ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
     dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
     run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                             workspace=ws, out=(ids, dists))
+                             workspace=ws, out=(ids, dists), precision=args.precision)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -150,9 +169,12 @@ def main():
     flops = [e * 2 * w["d"] for e in s0["evals"]]
     achieved = sum(flops) / (sum(join_ms) / 1e3) / 1e12
     kernel = "k_join_mfma" if s0["path"] == knng.PATH_MFMA else "k_join_valu"
+    if args.precision == "bf16":
+        kernel = "k_join_bf16"
     traffic = traffic_record(kernel)
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic, "kernel": kernel,
+    peak = PEAK_BF16_MFMA_TFLOPS if args.precision == "bf16" else PEAK_FP32_MFMA_TFLOPS
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kernel,
             "avg_launch_ms": round(sum(join_ms) / len(join_ms), 4),
             "flops_per_launch": int(sum(flops) / len(flops))}
 
@@ -160,13 +182,20 @@ def main():
     rec = None
     t99 = None
     if not args.no_recall:
-        tau = exact_kth(X, w["K"])
-        ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder))
+        N = w["N"]
+        if N <= args.recall_rows:
+            rows = torch.arange(N, device=dev)
+        else:
+            rows = torch.from_numpy(np.sort(np.random.default_rng(12345).choice(N, args.recall_rows,
+                                                                                replace=False))).to(dev)
+        tau = exact_kth(X, w["K"], rows)
+        ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+                           precision=args.precision)
         ctx.init()
         curve = []
         for t in range(1, s0["iters"] + 1):
             ctx.iterate()
-            r = recall_of(X, ctx.export().ids, tau)
+            r = recall_of(X, ctx.export().ids, tau, rows)
             curve.append(r)
         ctx.close()
         rec = curve[-1]
@@ -176,16 +205,22 @@ def main():
             if r >= 0.99 and t99 is None:
                 t99 = cum
     cpu = None if args.no_cpu else cpu_baseline(Xnp, w)
+    if cpu is not None and args.precision != "fp32":
+        cpu["sample"] += " (the oracle computes FP64 distances)"
 
     out = {
         "metric": "distance evals/sec", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32" if args.precision == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
-                   "reorder": bool(args.reorder), "path": "mfma" if s0["path"] == knng.PATH_MFMA else "valu"},
+                   "reorder": bool(args.reorder), "path": "mfma" if s0["path"] == knng.PATH_MFMA else "valu",
+                   "precision": args.precision},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
+        "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
+        "rescored_per_build": int(sum(s0.get("rescored", []))),
+        "reorder_ms": round(float(s0["reorder_ms"]), 3), "init_ms": round(float(s0["init_ms"]), 3),
         "device_ms_per_build": round(float(np.median([s["total_ms"] for s in stats])), 3),
         "phase_ms": {k: round(float(sum(s0[k])), 3) for k in ("sample_ms", "join_ms", "merge_ms")},
         "roofline": roof, "cpu_baseline": cpu,

@@ -49,7 +49,9 @@ typedef enum {
 
 typedef enum {
     KNNG_FP32 = 0,        /* distances in FP32 */
-    KNNG_BF16_SCREEN = 1  /* reserved: BF16 screening with FP32 rescore */
+    KNNG_BF16_SCREEN = 1  /* BF16 copies screen candidates on MFMA (FP32 accumulation) with a
+                             rigorous error margin; survivors are rescored in FP32 from the
+                             original rows and only rescored distances are stored (MFMA path) */
 } knng_precision;
 
 typedef enum {
@@ -78,9 +80,12 @@ typedef struct {
     int32_t converged;                    /* 1 if the stop rule held */
     int32_t path;                         /* path used (knng_path, resolved) */
     int32_t dpad;                         /* padded row length in floats */
+    int32_t precision;                    /* knng_precision used */
+    int32_t reserved;
     int64_t evals[KNNG_MAX_ITERS];        /* e_t: distance evaluations of iteration t */
     int64_t changes[KNNG_MAX_ITERS];      /* c_t: ids that entered a list */
     int64_t proposals[KNNG_MAX_ITERS];    /* proposals that passed the snapshot filter */
+    int64_t rescored[KNNG_MAX_ITERS];     /* BF16 form: pairs that passed the screen (rescored in FP32) */
     float iter_ms[KNNG_MAX_ITERS];        /* whole iteration */
     float sample_ms[KNNG_MAX_ITERS];      /* reverse bucketing + selection */
     float join_ms[KNNG_MAX_ITERS];        /* local join (pairs, distances, proposals) */

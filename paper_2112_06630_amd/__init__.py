@@ -45,9 +45,9 @@ class Params(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("dpad", ctypes.c_int32),
+                ("dpad", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("evals", ctypes.c_int64 * MAX_ITERS), ("changes", ctypes.c_int64 * MAX_ITERS),
-                ("proposals", ctypes.c_int64 * MAX_ITERS),
+                ("proposals", ctypes.c_int64 * MAX_ITERS), ("rescored", ctypes.c_int64 * MAX_ITERS),
                 ("iter_ms", ctypes.c_float * MAX_ITERS), ("sample_ms", ctypes.c_float * MAX_ITERS),
                 ("join_ms", ctypes.c_float * MAX_ITERS), ("merge_ms", ctypes.c_float * MAX_ITERS),
                 ("init_ms", ctypes.c_float), ("reorder_ms", ctypes.c_float),
@@ -96,10 +96,15 @@ def _check(st: int, allow=(OK,)):
     return st
 
 
+PRECISION_FP32, PRECISION_BF16_SCREEN = 0, 1
+_PRECISIONS = {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16_SCREEN}
+
+
 def make_params(K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
-                reorder: bool = False, path: str | int = "auto") -> Params:
+                reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32") -> Params:
     pth = _PATHS[path] if isinstance(path, str) else int(path)
-    return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, 0,
+    prc = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, prc,
                   1 if reorder else 0, pth)
 
 
@@ -127,8 +132,9 @@ def _check_x(X: torch.Tensor):
 
 def _stats_dict(s: _Stats) -> dict:
     it = s.iters
-    return dict(iters=it, converged=bool(s.converged), path=s.path, dpad=s.dpad,
+    return dict(iters=it, converged=bool(s.converged), path=s.path, dpad=s.dpad, precision=s.precision,
                 evals=list(s.evals[:it]), changes=list(s.changes[:it]), proposals=list(s.proposals[:it]),
+                rescored=list(s.rescored[:it]),
                 iter_ms=list(s.iter_ms[:it]), sample_ms=list(s.sample_ms[:it]), join_ms=list(s.join_ms[:it]),
                 merge_ms=list(s.merge_ms[:it]), init_ms=s.init_ms, reorder_ms=s.reorder_ms,
                 finalize_ms=s.finalize_ms, total_ms=s.total_ms)
@@ -136,7 +142,7 @@ def _stats_dict(s: _Stats) -> dict:
 
 def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
           reorder: bool = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
-          out: tuple | None = None):
+          out: tuple | None = None, precision: str | int = "fp32"):
     """K-NN graph of the rows of X (device float32 [N, d]).
 
     Returns (ids int32 [N, K], dists float32 [N, K] squared l2, stats dict);
@@ -145,7 +151,7 @@ def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_i
     """
     _check_x(X)
     N, d = X.shape
-    p = make_params(K, rho, delta, max_iters, seed, reorder, path)
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision)
     ws = workspace_bytes(N, d, p)
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(ws, dtype=torch.uint8, device=X.device)
@@ -172,12 +178,12 @@ class Context:
     """Step API: one build whose state lives in a caller-held workspace."""
 
     def __init__(self, X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
-                 seed: int = 0, reorder: bool = False, path: str | int = "auto"):
+                 seed: int = 0, reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32"):
         _check_x(X)
         self.X = X
         self.N, self.d = X.shape
         self.K = K
-        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path)
+        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path, precision)
         self.C = sample_cap(K, rho)
         self.ws_bytes = workspace_bytes(self.N, self.d, self.params)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=X.device)

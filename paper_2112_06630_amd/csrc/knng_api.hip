@@ -53,13 +53,14 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 struct Plan {
     int path;        // resolved knng_path
     int reorder;
+    int bf16;        // BF16-screened precision form
     int dp;
     int C;
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
-        o_pkey, o_ppos, o_scan, o_counters, o_partial, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
+        o_pkey, o_ppos, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
         o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag;
 };
 
@@ -73,7 +74,7 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return fail(KNNG_EINVAL, "delta must be finite and >= 0");
     if (p->max_iters < 0 || p->max_iters > KNNG_MAX_ITERS)
         return fail(KNNG_EINVAL, "max_iters must be in [0, 64]");
-    if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "precision: only KNNG_FP32 is available");
+    if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA) return fail(KNNG_EINVAL, "unknown path");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
     return KNNG_OK;
@@ -85,6 +86,11 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     const int K = p->K;
     P.C = sample_cap(K, p->rho);
     int path = p->path;
+    P.bf16 = p->precision == KNNG_BF16_SCREEN ? 1 : 0;
+    if (P.bf16) {
+        if (path == KNNG_PATH_VALU) return fail(KNNG_EINVAL, "the BF16-screened form runs on the MFMA path");
+        path = KNNG_PATH_MFMA;
+    }
     if (path == KNNG_PATH_AUTO) path = (d >= 64 && 2 * P.C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
     if (path == KNNG_PATH_MFMA && 2 * P.C > 64) return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
     P.path = path;
@@ -127,6 +133,14 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     P.o_scan = take(scan_tmp_words((int)N) * 4);
     P.o_counters = take(kNumCounters * 8);
     P.o_partial = take(partial_words() * 8);
+    if (P.bf16) {
+        P.o_Xb = take((size_t)N * P.dp * 2);
+        P.o_nb = take((size_t)N * 4);
+        if (p->reorder) {
+            P.o_Xb2 = take((size_t)N * P.dp * 2);
+            P.o_nb2 = take((size_t)N * 4);
+        }
+    }
     if (p->reorder) {   // permutation scratch only when the permutation is on
         P.o_comp = take((size_t)N * 4);
         P.o_comp2 = take((size_t)N * 4);
@@ -179,6 +193,14 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.scan_tmp = reinterpret_cast<uint32_t*>(b + P.o_scan);
     v.counters = reinterpret_cast<uint64_t*>(b + P.o_counters);
     v.partial = reinterpret_cast<uint64_t*>(b + P.o_partial);
+    if (P.bf16) {
+        v.Xb = reinterpret_cast<uint16_t*>(b + P.o_Xb);
+        v.nb = reinterpret_cast<float*>(b + P.o_nb);
+        if (P.reorder) {
+            v.Xb2 = reinterpret_cast<uint16_t*>(b + P.o_Xb2);
+            v.nb2 = reinterpret_cast<float*>(b + P.o_nb2);
+        }
+    }
     if (P.reorder) {
         v.comp = reinterpret_cast<int32_t*>(b + P.o_comp);
         v.comp2 = reinterpret_cast<int32_t*>(b + P.o_comp2);
@@ -261,6 +283,8 @@ knng_status do_permute(knng_ctx* c) {
     std::swap(v.orig, v.orig2);
     std::swap(v.lkey, v.lkey2);
     std::swap(v.lpos, v.lpos2);
+    std::swap(v.Xb, v.Xb2);
+    std::swap(v.nb, v.nb2);
     launch_perm_posof(v, s);
     HIP_TRY(hipEventRecord(c->ev[5], s));
     HIP_TRY(hipGetLastError());
@@ -295,7 +319,9 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     launch_select(v, st, s);
     launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
-    if (c->plan.path == KNNG_PATH_MFMA)
+    if (c->plan.bf16)
+        launch_join_bf16(v, s);
+    else if (c->plan.path == KNNG_PATH_MFMA)
         launch_join_mfma(v, s);
     else
         launch_join_valu(v, s);
@@ -319,6 +345,7 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     S.evals[i] = e;
     S.changes[i] = ch;
     S.proposals[i] = (int64_t)c->hc[kCntProposals];
+    S.rescored[i] = (int64_t)c->hc[kCntRescored];
     S.sample_ms[i] = ms_between(c->ev[0], c->ev[1]);
     S.join_ms[i] = ms_between(c->ev[1], c->ev[2]);
     S.merge_ms[i] = ms_between(c->ev[2], c->ev[3]);
@@ -374,6 +401,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     c->v = carve(P, N, d, params->K, d_ws);
     std::memset(&c->stats, 0, sizeof(c->stats));
     c->stats.path = P.path;
+    c->stats.precision = P.bf16 ? KNNG_BF16_SCREEN : KNNG_FP32;
     c->stats.dpad = P.dp;
     for (auto& e : c->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
@@ -384,6 +412,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
     launch_pad_rows(dX, c->v, c->stream);
     if (P.path == KNNG_PATH_MFMA) launch_norms(c->v, c->stream);
+    if (P.bf16) launch_make_bf16(c->v, c->stream);
     if (hipGetLastError() != hipSuccess || read_counters(c) != KNNG_OK) {
         knng_destroy(c);
         return fail(KNNG_EDEVICE, "row padding failed");
@@ -399,7 +428,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
 knng_status knng_init_graph(knng_ctx* c) {
     if (!c) return fail(KNNG_EINVAL, "ctx is NULL");
     if (c->permuted) return fail(KNNG_EINVAL, "init after permutation is not supported");
-    launch_init(c->v, stream_state(c->p.seed, 1, 0), c->plan.path == KNNG_PATH_MFMA, c->stream);
+    launch_init(c->v, stream_state(c->p.seed, 1, 0), c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16, c->stream);
     HIP_TRY(hipGetLastError());
     c->t = 0;
     c->has_graph = true;
@@ -412,7 +441,7 @@ knng_status knng_load_graph(knng_ctx* c, const int32_t* d_ids, const uint8_t* d_
     if (c->permuted) return fail(KNNG_EINVAL, "load after permutation is not supported");
     if (t < 0 || t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "t out of range");
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
-    launch_load_rows(c->v, d_ids, d_flags, c->plan.path == KNNG_PATH_MFMA, c->stream);
+    launch_load_rows(c->v, d_ids, d_flags, c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16, c->stream);
     HIP_TRY(hipGetLastError());
     knng_status rs = read_counters(c);
     if (rs != KNNG_OK) return rs;

@@ -19,6 +19,7 @@ enum Counter : int {
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
     kCntHubs = 6,        // targets whose proposal bucket is merged by a workgroup
+    kCntRescored = 7,    // precision form: pairs that passed the BF16 screen and were rescored
     kNumCounters = 8
 };
 
@@ -27,6 +28,8 @@ struct Views {
     int N, d, dp, K, C;
     float* Xp;          // [N, dp] rows in position order, zero padded
     float* nrm;         // [N] squared norms (Gram path)
+    uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
+    float* nb;          // [N] squared norms of the BF16 rows
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
@@ -61,6 +64,8 @@ struct Views {
     uint32_t* lpos2;    // [N, K]
     float* Xp2;         // [N, dp]
     float* nrm2;        // [N]
+    uint16_t* Xb2;      // [N, dp]
+    float* nb2;         // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
 };
@@ -81,6 +86,8 @@ void launch_rev_scatter(const Views& v, uint64_t st_sample, hipStream_t s);
 void launch_select(const Views& v, uint64_t st_sample, hipStream_t s);
 void launch_join_valu(const Views& v, hipStream_t s);
 void launch_join_mfma(const Views& v, hipStream_t s);
+void launch_make_bf16(const Views& v, hipStream_t s);
+void launch_join_bf16(const Views& v, hipStream_t s);
 void launch_merge(const Views& v, hipStream_t s);
 void launch_finish_counters(const Views& v, hipStream_t s);
 void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);

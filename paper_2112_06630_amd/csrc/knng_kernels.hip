@@ -1159,6 +1159,211 @@ void launch_join_mfma(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_join_mfma, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
 }
 
+// ------------------------------------------------------------------ precision form (a9)
+//
+// BF16 copies of the rows feed BF16 MFMA Gram tiles with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16) as a screen; every direction that can pass the
+// snapshot filter is rescored in FP32 from the original rows, and only the
+// rescored distances are proposed, filtered exactly and stored.
+//
+// Screen bound. With x~ = bf16(x) rounded to nearest, |x~_j - x_j| <= u_b |x_j|,
+// u_b = 2^-8, so | ||x~-y~|| - ||x-y|| | <= eps = u_b (||x|| + ||y||) and
+// |D~e - D| <= 2 eps sqrt(D) + eps^2 for D~e the exact distance of the BF16 rows.
+// The tile computes D~ = n~x + n~y - 2 x~.y~ in FP32 (BF16 products are exact in
+// FP32) with |D~ - D~e| <= (d+3) 2^-24 (||x~|| + ||y~||)^2. A pair with D <= T
+// therefore has D~ <= T + 2 eps sqrt(T) + eps^2 + (d+3) 2^-24 (||x~|| + ||y~||)^2,
+// the test applied (in FP64, with the bound enlarged by 2^-20 relative).
+//
+// Rescore. One wave per pair: lane l sums (x_j - y_j)^2 over j = l, l+64, ...
+// in order, lane partials are added by a fixed tree and lane 0's value is
+// broadcast: one deterministic FP32 formula, symmetric in (x, y).
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__global__ void k_make_bf16(Views v) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < v.N; p += gridDim.x * blockDim.x) {
+        const float* x = v.Xp + (size_t)p * v.dp;
+        uint16_t* y = v.Xb + (size_t)p * v.dp;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (int j = 0; j < v.dp; j += 4) {
+            const float4 a = *reinterpret_cast<const float4*>(x + j);
+            const uint16_t b0 = bf16_rne(a.x), b1 = bf16_rne(a.y), b2 = bf16_rne(a.z), b3 = bf16_rne(a.w);
+            y[j] = b0;
+            y[j + 1] = b1;
+            y[j + 2] = b2;
+            y[j + 3] = b3;
+            const float f0 = bf16_to_f32(b0), f1 = bf16_to_f32(b1), f2 = bf16_to_f32(b2), f3 = bf16_to_f32(b3);
+            s0 = fmaf(f0, f0, s0);
+            s1 = fmaf(f1, f1, s1);
+            s2 = fmaf(f2, f2, s2);
+            s3 = fmaf(f3, f3, s3);
+        }
+        v.nb[p] = (s0 + s1) + (s2 + s3);
+    }
+}
+
+void launch_make_bf16(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_make_bf16, dim3(grid_for(v.N, 256, 8192)), dim3(256), 0, s, v);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 squared distance of two rows, one wave: strided lane partial sums,
+// fixed reduction tree, lane 0's value broadcast.
+__device__ __forceinline__ float dist_wave(const float* __restrict__ a, const float* __restrict__ b, int dp) {
+    const int lane = lane_id();
+    float s = 0.f;
+    for (int j = lane; j < dp; j += 64) {
+        const float t = a[j] - b[j];
+        s = fmaf(t, t, s);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    return __uint_as_float(rl32(__float_as_uint(s), 0));
+}
+
+constexpr int kBfMaxSurv = 3 * 32 * 32 / 2;   // survivor pairs per owner <= e(u) <= C(C-1)/2 + C^2 < 1.5 C^2, C <= 32
+
+__global__ __launch_bounds__(256) void k_join_bf16(Views v) {
+    __shared__ uint64_t s_thr[kJoinWaves][64];
+    __shared__ uint32_t s_oid[kJoinWaves][64];
+    __shared__ uint32_t s_pos[kJoinWaves][64];
+    __shared__ float s_nrm[kJoinWaves][64];
+    __shared__ float s_nb[kJoinWaves][64];
+    __shared__ uint32_t s_emit[kJoinWaves][3][64];
+    __shared__ uint32_t s_surv[kJoinWaves][kBfMaxSurv];   // survivors: i | j << 8 | directions << 16
+    __shared__ float s_sd[kJoinWaves][kBfMaxSurv];        // their rescored FP32 distances
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int C2 = 2 * v.C, dp = v.dp, K = v.K;
+    const int c16 = lane & 15, g = lane >> 4;
+    EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
+    emit_clear(el, 64);
+    uint64_t rescored = 0;
+    const double ub = 1.0 / 256.0;
+    const double cfp = (double)(dp + 3) * (1.0 / 16777216.0);
+    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
+    for (int u = xr.next; u < xr.end; u += xr.step) {
+        const uint32_t nn = v.nn[u];
+        const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
+        if (nnew == 0) continue;
+        const uint2* cs = v.cand + (size_t)u * C2;
+        if (lane < m) {
+            const uint2 c = cs[lane];
+            s_oid[w][lane] = c.x;
+            s_pos[w][lane] = c.y;
+            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
+            s_nrm[w][lane] = v.nrm[c.y];
+            s_nb[w][lane] = v.nb[c.y];
+        }
+        wave_sync();
+        const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
+        const uint16_t* rp[kMfmaMaxCT];
+        bool rv[kMfmaMaxCT];
+        for (int ct = 0; ct < kMfmaMaxCT; ++ct) {
+            const int j = ct * 16 + c16;
+            rv[ct] = ct < CT && j < m;
+            rp[ct] = v.Xb + (size_t)(rv[ct] ? s_pos[w][j] : 0u) * dp + g * 8;
+        }
+        floatx4 acc[kMfmaMaxCT * (kMfmaMaxCT + 1) / 2];
+        for (int t = 0; t < kMfmaMaxCT * (kMfmaMaxCT + 1) / 2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < dp; k0 += 32) {
+            bf16x8 f[kMfmaMaxCT];
+#pragma unroll
+            for (int ct = 0; ct < kMfmaMaxCT; ++ct) {
+                uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+                if (rv[ct]) raw = *reinterpret_cast<const uint4*>(rp[ct] + k0);
+                f[ct] = __builtin_bit_cast(bf16x8, raw);
+            }
+            int t = 0;
+#pragma unroll
+            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+#pragma unroll
+                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t)
+                    if (rt < RT && ct < CT)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[rt], f[ct], acc[t], 0, 0, 0);
+        }
+        // screen: every cell and direction that can pass the snapshot filter
+        uint32_t nsv = 0;
+        {
+            int t = 0;
+#pragma unroll
+            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+#pragma unroll
+                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t) {
+                    if (!(rt < RT && ct < CT)) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = rt * 16 + g * 4 + r, j = ct * 16 + c16;
+                        bool si = false, sj = false;
+                        if (j < m && i < nnew && !(j < nnew && j <= i)) {
+                            const double Dt = (double)((s_nb[w][i] + s_nb[w][j]) - 2.0f * acc[t][r]);
+                            const double eps = ub * (sqrt((double)s_nrm[w][i]) + sqrt((double)s_nrm[w][j]));
+                            const double nbs = sqrt((double)s_nb[w][i]) + sqrt((double)s_nb[w][j]);
+                            const double fp = cfp * nbs * nbs;
+                            const double Ti = (double)__uint_as_float((uint32_t)(s_thr[w][i] >> 32));
+                            const double Tj = (double)__uint_as_float((uint32_t)(s_thr[w][j] >> 32));
+                            const double mi = (2.0 * eps * sqrt(Ti) + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
+                            const double mj = (2.0 * eps * sqrt(Tj) + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
+                            si = Dt - mi <= Ti;
+                            sj = Dt - mj <= Tj;
+                        }
+                        const bool sv = si || sj;
+                        const uint64_t mk = ballot(sv);
+                        const uint32_t slot = nsv + mbcnt(mk);
+                        if (sv && slot < (uint32_t)kBfMaxSurv)
+                            s_surv[w][slot] = (uint32_t)i | ((uint32_t)j << 8) | (si ? 1u << 16 : 0u) |
+                                              (sj ? 1u << 17 : 0u);
+                        nsv += (uint32_t)__popcll(mk);
+                    }
+                }
+        }
+        if (nsv > (uint32_t)kBfMaxSurv) {  // cannot happen: survivors <= e(u) <= 1.5 C^2
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 128ull);
+            nsv = kBfMaxSurv;
+        }
+        wave_sync();
+        // rescore in FP32 from the original rows
+        for (uint32_t q = 0; q < nsv; ++q) {
+            const uint32_t e = s_surv[w][q];
+            const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
+            const float D = dist_wave(v.Xp + (size_t)s_pos[w][a] * dp, v.Xp + (size_t)s_pos[w][b] * dp, dp);
+            if (lane == 0) s_sd[w][q] = D;
+        }
+        rescored += nsv;
+        wave_sync();
+        // exact filter on the rescored keys: count, reserve, write
+        for (int pass = 0; pass < 2; ++pass) {
+            for (uint32_t q = (uint32_t)lane; q < nsv; q += 64) {
+                const uint32_t e = s_surv[w][q];
+                const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
+                const uint64_t kb = (uint64_t)__float_as_uint(s_sd[w][q]) << 32;
+                const uint64_t ka = kb | s_oid[w][b], kbb = kb | s_oid[w][a];
+                const bool da = (e >> 16) & 1u, db = (e >> 17) & 1u;
+                if (pass == 0) {
+                    if (da && ka < s_thr[w][a]) emit_count(el, a);
+                    if (db && kbb < s_thr[w][b]) emit_count(el, b);
+                } else {
+                    if (da && ka < s_thr[w][a]) emit_write(v, el, a, ka, s_pos[w][b]);
+                    if (db && kbb < s_thr[w][b]) emit_write(v, el, b, kbb, s_pos[w][a]);
+                }
+            }
+            if (pass == 0) emit_reserve(v, el, s_pos[w], m);
+        }
+        wave_sync();
+        emit_clear(el, m);
+    }
+    if (lane == 0 && rescored) atomicAdd((unsigned long long*)&v.counters[kCntRescored], (unsigned long long)rescored);
+}
+
+void launch_join_bf16(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_join_bf16, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+}
+
 // ------------------------------------------------------------------ merge (a5)
 
 constexpr int kMergeWaves = 4;
@@ -1616,6 +1821,18 @@ __global__ void k_perm_rows(Views v) {
     }
 }
 
+__global__ void k_perm_rows_bf16(Views v) {
+    const int dp8 = v.dp >> 3;   // 16-byte groups of 8 BF16 values (dp % 32 == 0)
+    const int64_t total = (int64_t)v.N * dp8;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(i / dp8), c = (int)(i - (int64_t)p * dp8);
+        const int q = v.newpos[p];
+        if (q < 0 || q >= v.N) continue;  // reported by k_perm_rows
+        reinterpret_cast<uint4*>(v.Xb2 + (size_t)q * v.dp)[c] = reinterpret_cast<const uint4*>(v.Xb + (size_t)p * v.dp)[c];
+        if (c == 0) v.nb2[q] = v.nb[p];
+    }
+}
+
 __global__ void k_perm_lists(Views v) {
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
@@ -1665,6 +1882,9 @@ void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s) {
     hipLaunchKernelGGL(k_perm_newpos, dim3(g), dim3(256), 0, s, v);
     hipLaunchKernelGGL(k_perm_rows, dim3(grid_for((int64_t)v.N * (v.dp >> 2), 256, 16384)), dim3(256), 0, s, v);
     hipLaunchKernelGGL(k_perm_lists, dim3(grid_for((int64_t)v.N * v.K, 256, 16384)), dim3(256), 0, s, v);
+    if (v.Xb)
+        hipLaunchKernelGGL(k_perm_rows_bf16, dim3(grid_for((int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256), 0, s,
+                           v);
 }
 
 void launch_perm_posof(const Views& v, hipStream_t s) {

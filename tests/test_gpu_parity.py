@@ -241,3 +241,53 @@ def test_permutation_order_and_cluster_purity(knng):
         runs = np.split(idx, np.nonzero(np.diff(idx) != 1)[0] + 1)
         assert max(len(r) for r in runs) >= 0.9 * len(idx)
     ctx.close()
+
+
+# ----------------------------------------------------------------- precision form (BF16 screen + FP32 rescore)
+
+@pytest.mark.parametrize("N,d,K,rho,hi,seed", [
+    (700, 64, 10, 1.0, 9, 1),
+    (900, 130, 16, 0.5, 200, 3),
+])
+def test_bf16_screen_integer_bitwise(knng, N, d, K, rho, hi, seed):
+    """Integers <= 256 are exact in BF16 and every sum is exact in FP32: the
+    screened form must reproduce the oracle bit for bit."""
+    X = synth.integer_points(N, d, hi, seed)
+    ref = oracle.build_graph(X, K, rho, 0.001, 15, seed)
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 15, seed, precision="bf16")
+    assert st["precision"] == 1
+    assert st["evals"] == ref.evals.tolist() and st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)
+    assert all(0 < r <= 2 * e for r, e in zip(st["rescored"], st["evals"]) if e)
+
+
+def test_bf16_screen_image_like_bitwise(knng):
+    X = synth.image_like(2500, 1)
+    ref = oracle.build_graph(X, 20, 1.0, 0.001, 30, 1)
+    ids, dists, st = knng.build(dev(X), 20, 1.0, 0.001, 30, 1, precision="bf16")
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert st["changes"] == ref.changes.tolist()
+
+
+def test_bf16_screen_continuous_parity(knng):
+    """Anisotropic clusters (the precision workload's shape, N=3000): tie-aware
+    parity with the FP64 oracle, stored distances within the FP32 direct-form
+    bound, and the screen passes far fewer pairs than it evaluates late on."""
+    X = synth.anisotropic_clusters(3000, 960, 3, 20)
+    K, rho = 20, 0.5
+    ref = oracle.build_graph(X, K, rho, 0.001, 30, 3)
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, 3, precision="bf16")
+    res = check_rows(X, ids.cpu().numpy(), dists.cpu().numpy(), ref.ids, ref.dists, dpad=960, gram=False)
+    assert res["exact_rows"] >= 3000 - 10
+    ei, ed = oracle.bruteforce(X, K)
+    assert oracle.recall(X, ids.cpu().numpy(), ed) >= 0.99
+    late = [r / (2 * e) for r, e in zip(st["rescored"], st["evals"]) if e][-3:]
+    assert min(late) < 0.5
+
+
+def test_bf16_screen_with_permutation(knng):
+    X = synth.anisotropic_clusters(2000, 192, 5, 12)
+    a = knng.build(dev(X), 12, 0.5, 0.001, 20, 5, precision="bf16", reorder=False)
+    b = knng.build(dev(X), 12, 0.5, 0.001, 20, 5, precision="bf16", reorder=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])

@@ -156,6 +156,58 @@ knng_status knng_get_stats(const knng_ctx* ctx, knng_stats* stats);
 /* Free the host handle (no device memory is owned). */
 void knng_destroy(knng_ctx* ctx);
 
+/* ---- batched form: many independent datasets in one graph launch ---- */
+
+/* One dataset of a batch: device input rows dX [N, d] (float32, row-major,
+ * finite) and device outputs d_ids / d_dists [N, K] (original row indices
+ * within the dataset, squared l2), each row sorted by (distance, id). */
+typedef struct {
+    const float* dX;
+    int64_t N;
+    int32_t d;
+    int32_t reserved;
+    uint64_t seed;       /* the dataset's own seed (params.seed is not used) */
+    int32_t* d_ids;
+    float* d_dists;
+} knng_dataset;
+
+typedef struct knng_batch knng_batch;
+
+/* Workspace bytes of a batch (room for either join path of every group). */
+size_t knng_batch_workspace_bytes(const knng_dataset* descs, int32_t n, const knng_params* params);
+
+/* Plan a batch: groups datasets by dimension and join path, uploads the
+ * per-dataset tables (seeds, offsets, pointers) into the workspace and checks
+ * every input is finite. `tuning` is NULL/"auto" (time both join paths per
+ * dimension on the batch itself and keep the faster: the autotuner) or a
+ * table such as "16:valu,64:mfma,128:mfma". params.K, rho, delta, max_iters
+ * (>= 1) apply to every dataset; params.reorder must be 0, params.precision
+ * KNNG_FP32. Synchronises `stream`. Results equal those of one knng_build per
+ * dataset with the same join path. */
+knng_status knng_batch_plan(knng_batch** out, const knng_dataset* descs, int32_t n, const knng_params* params,
+                            void* d_ws, size_t ws_bytes, const char* tuning, void* stream);
+
+/* The tuning table the plan uses (valid until knng_batch_destroy). */
+const char* knng_batch_tuning(const knng_batch* plan);
+
+/* Enqueue the whole batched build (setup, init, max_iters iterations in which
+ * finished datasets are skipped, write-out). Allocates nothing and never
+ * synchronises: it may be captured in a graph. */
+knng_status knng_batch_execute(knng_batch* plan, void* stream);
+
+/* Capture knng_batch_execute on `stream` (not the default stream) into a
+ * graph owned by the plan; knng_batch_launch then runs it in one launch. */
+knng_status knng_batch_capture(knng_batch* plan, void* stream);
+knng_status knng_batch_launch(knng_batch* plan, void* stream);
+
+/* After the build: per dataset (caller order) iterations run, converged flag,
+ * and e_t / c_t per iteration (arrays [n * max_iters], nullable). Synchronises
+ * `stream`; KNNG_EDEVICE if a device invariant failed during the build. */
+knng_status knng_batch_stats(knng_batch* plan, int32_t* iters, int32_t* converged, int64_t* evals,
+                             int64_t* changes, void* stream);
+
+void knng_batch_destroy(knng_batch* plan);
+
 /* Per-flag sample cap C for (K, rho). */
 int32_t knng_sample_cap(int32_t K, double rho);
 

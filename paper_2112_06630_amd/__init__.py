@@ -247,3 +247,114 @@ class Context:
         s = _Stats()
         _check(lib.knng_get_stats(self._h, ctypes.byref(s)))
         return _stats_dict(s)
+
+
+# ----------------------------------------------------------------------------- batched form
+
+class _Dataset(ctypes.Structure):
+    _fields_ = [("dX", ctypes.c_void_p), ("N", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64), ("d_ids", ctypes.c_void_p),
+                ("d_dists", ctypes.c_void_p)]
+
+
+def _load_batch(L):
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+    PD, PP = ctypes.POINTER(_Dataset), ctypes.POINTER(Params)
+    L.knng_batch_workspace_bytes.argtypes = [PD, i32, PP]
+    L.knng_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.knng_batch_plan.argtypes = [ctypes.POINTER(P), PD, i32, PP, P, ctypes.c_size_t, ctypes.c_char_p, P]
+    L.knng_batch_tuning.argtypes = [P]
+    L.knng_batch_tuning.restype = ctypes.c_char_p
+    L.knng_batch_execute.argtypes = [P, P]
+    L.knng_batch_capture.argtypes = [P, P]
+    L.knng_batch_launch.argtypes = [P, P]
+    L.knng_batch_stats.argtypes = [P, P, P, P, P, P]
+    L.knng_batch_destroy.argtypes = [P]
+    L.knng_batch_destroy.restype = None
+    for n in ("knng_batch_plan", "knng_batch_execute", "knng_batch_capture", "knng_batch_launch",
+              "knng_batch_stats"):
+        getattr(L, n).restype = ctypes.c_int
+
+
+_load_batch(lib)
+
+
+class Batch:
+    """Many independent datasets built together (one graph launch once captured).
+
+    ``Xs``: list of device float32 [N_i, d_i] tensors; ``seeds``: one seed per
+    dataset. ``tuning``: None/"auto" runs the autotuner, or a table such as
+    "16:valu,64:mfma,128:mfma". Work is ordered on ``stream`` (a non-default
+    torch stream; one is created when not given).
+    """
+
+    def __init__(self, Xs, seeds, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
+                 path: str | int = "auto", tuning: str | None = None, stream=None):
+        if len(Xs) != len(seeds) or not Xs:
+            raise ValueError("one seed per dataset")
+        for X in Xs:
+            _check_x(X)
+        dev = Xs[0].device
+        self.Xs = Xs
+        self.K = K
+        self.max_iters = max_iters
+        self.stream = stream or torch.cuda.Stream(device=dev)
+        self.ids = [torch.empty((X.shape[0], K), dtype=torch.int32, device=dev) for X in Xs]
+        self.dists = [torch.empty((X.shape[0], K), dtype=torch.float32, device=dev) for X in Xs]
+        n = len(Xs)
+        self._descs = (_Dataset * n)()
+        for i, (X, s) in enumerate(zip(Xs, seeds)):
+            self._descs[i] = _Dataset(X.data_ptr(), X.shape[0], X.shape[1], 0, int(s) & 0xFFFFFFFFFFFFFFFF,
+                                      self.ids[i].data_ptr(), self.dists[i].data_ptr())
+        self.params = make_params(K, rho, delta, max_iters, 0, False, path)
+        nb = int(lib.knng_batch_workspace_bytes(self._descs, n, ctypes.byref(self.params)))
+        if nb == 0:
+            raise KnngError(EINVAL, _err())
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream(dev).synchronize()
+        _check(lib.knng_batch_plan(ctypes.byref(h), self._descs, n, ctypes.byref(self.params),
+                                   ctypes.c_void_p(self.ws.data_ptr()), nb,
+                                   (tuning or "auto").encode(), ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+        self.captured = False
+
+    @property
+    def tuning(self) -> str:
+        return lib.knng_batch_tuning(self._h).decode()
+
+    def execute(self):
+        _check(lib.knng_batch_execute(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def capture(self):
+        _check(lib.knng_batch_capture(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.captured = True
+
+    def launch(self):
+        _check(lib.knng_batch_launch(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def stats(self) -> dict:
+        import numpy as np
+        n, T = len(self.Xs), self.max_iters
+        it = np.zeros(n, np.int32)
+        cv = np.zeros(n, np.int32)
+        ev = np.zeros((n, T), np.int64)
+        ch = np.zeros((n, T), np.int64)
+        _check(lib.knng_batch_stats(self._h, it.ctypes.data, cv.ctypes.data, ev.ctypes.data, ch.ctypes.data,
+                                    ctypes.c_void_p(self.stream.cuda_stream)))
+        return dict(iters=it, converged=cv, evals=[list(ev[i, :it[i]]) for i in range(n)],
+                    changes=[list(ch[i, :it[i]]) for i in range(n)])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.knng_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

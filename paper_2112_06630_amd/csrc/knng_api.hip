@@ -7,9 +7,13 @@
 // original order. All device memory comes from the caller's workspace.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <utility>
+#include <vector>
 #include <cstring>
 #include <string>
 
@@ -315,8 +319,8 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_rev_hist(v, s);
     launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
-    launch_rev_scatter(v, st, s);
-    launch_select(v, st, s);
+    launch_rev_scatter(v, st, t, s);
+    launch_select(v, st, t, s);
     launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
     if (c->plan.bf16)
@@ -546,6 +550,454 @@ knng_status knng_build(const float* dX, int64_t N, int32_t d, const knng_params*
     if (stats) *stats = c->stats;
     cleanup();
     return (conv || params->max_iters == 0) ? KNNG_OK : KNNG_ENOTCONV;
+}
+
+
+}  // extern "C"
+// ====================================================================== batched form
+//
+// Datasets with the same padded row length and join path form one group; a
+// group is one union build (contiguous position range per dataset, per-dataset
+// seeds, iteration counters, stop rules and statistics on the device). The
+// execute call only enqueues kernels (no allocation, no synchronisation), so
+// it can be captured in a graph; all groups and all T_max iterations form one
+// graph launch. Finished datasets are skipped by every kernel.
+
+namespace {
+
+struct BatchGroup {
+    int d = 0, dp = 0, path = 0;
+    std::vector<int> members;   // dataset indices in the caller's order
+    int64_t N = 0;
+    Plan plan{};
+    size_t off = 0;             // byte offset of the group's region in the workspace
+    size_t tables_off = 0;      // offset of the batch tables inside the region
+    Views v{};
+};
+
+struct TableLayout {
+    size_t ds, dsbase, active, st_init, st_table, chg, chgoff, out_ids, out_dists, in_X, in_d, iters, conv, stats, total;
+};
+
+TableLayout table_layout(int64_t N, int nds, int T) {
+    TableLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (size_t)round_up((int64_t)bytes, 256);
+        return o;
+    };
+    L.ds = take((size_t)N * 4);
+    L.dsbase = take(((size_t)nds + 1) * 4);
+    L.active = take((size_t)nds * 4);
+    L.st_init = take((size_t)nds * 8);
+    L.st_table = take((size_t)nds * T * 8);
+    L.chg = take((size_t)N * 4);
+    L.chgoff = take(((size_t)N + 1) * 4);
+    L.out_ids = take((size_t)nds * 8);
+    L.out_dists = take((size_t)nds * 8);
+    L.in_X = take((size_t)nds * 8);
+    L.in_d = take((size_t)nds * 4);
+    L.iters = take((size_t)nds * 4);
+    L.conv = take((size_t)nds * 4);
+    L.stats = take((size_t)nds * T * 16);
+    L.total = off;
+    return L;
+}
+
+int parse_tuned_path(const std::string& table, int d) {
+    // "16:valu,64:mfma" -> path for d, 0 if absent
+    size_t pos = 0;
+    while (pos < table.size()) {
+        size_t end = table.find(',', pos);
+        if (end == std::string::npos) end = table.size();
+        const std::string item = table.substr(pos, end - pos);
+        const size_t c = item.find(':');
+        if (c != std::string::npos && std::atoi(item.substr(0, c).c_str()) == d) {
+            const std::string v = item.substr(c + 1);
+            if (v == "valu") return KNNG_PATH_VALU;
+            if (v == "mfma") return KNNG_PATH_MFMA;
+        }
+        pos = end + 1;
+    }
+    return 0;
+}
+
+}  // namespace
+
+struct knng_batch {
+    knng_params p{};
+    std::vector<knng_dataset> descs;
+    std::vector<BatchGroup> groups;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string tuning;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+knng_status batch_validate(const knng_dataset* descs, int32_t n, const knng_params* p) {
+    if (!descs || n < 1) return fail(KNNG_EINVAL, "no datasets");
+    if (!p) return fail(KNNG_EINVAL, "params is NULL");
+    if (p->reorder) return fail(KNNG_EINVAL, "the batched form runs without the permutation");
+    if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "the batched form runs in FP32");
+    if (p->max_iters < 1) return fail(KNNG_EINVAL, "the batched form needs max_iters >= 1");
+    for (int i = 0; i < n; ++i) {
+        if (!descs[i].dX || !descs[i].d_ids || !descs[i].d_dists) return fail(KNNG_EINVAL, "dataset pointer is NULL");
+        knng_status s = validate(descs[i].N, descs[i].d, p);
+        if (s != KNNG_OK) return s;
+    }
+    return KNNG_OK;
+}
+
+// groups by (padded length, path); the path per d comes from the tuning table
+// or defaults to the single-build rule
+knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params* p, const std::string& tuning,
+                         std::vector<BatchGroup>& groups, size_t& total) {
+    groups.clear();
+    const int C = sample_cap(p->K, p->rho);
+    for (int i = 0; i < n; ++i) {
+        const int d = descs[i].d;
+        int path = p->path != KNNG_PATH_AUTO ? p->path : parse_tuned_path(tuning, d);
+        if (!path) path = (d >= 64 && 2 * C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
+        const int dp = (int)(path == KNNG_PATH_MFMA ? round_up(d, 32) : round_up(d, 4));
+        BatchGroup* g = nullptr;
+        for (auto& x : groups)
+            if (x.dp == dp && x.path == path && x.d == d) g = &x;
+        if (!g) {
+            groups.push_back(BatchGroup{});
+            g = &groups.back();
+            g->d = d;
+            g->dp = dp;
+            g->path = path;
+        }
+        g->members.push_back(i);
+        g->N += descs[i].N;
+    }
+    total = 0;
+    for (auto& g : groups) {
+        if (g.N >= (1LL << 31) / p->K) return fail(KNNG_EINVAL, "a dimension group is too large for one union");
+        knng_params gp = *p;
+        gp.path = g.path;
+        gp.reorder = 0;
+        Plan P{};
+        knng_status s = make_plan(g.N, g.d, &gp, P);
+        if (s != KNNG_OK) return s;
+        g.plan = P;
+        g.off = total;
+        g.tables_off = P.total;
+        total += P.total + table_layout(g.N, (int)g.members.size(), p->max_iters).total;
+        total = (size_t)round_up((int64_t)total, 4096);
+    }
+    return KNNG_OK;
+}
+
+knng_status batch_upload(knng_batch* b, hipStream_t s) {
+    const int T = b->p.max_iters;
+    for (auto& g : b->groups) {
+        const int nds = (int)g.members.size();
+        const TableLayout L = table_layout(g.N, nds, T);
+        char* base = b->ws + g.off;
+        g.v = carve(g.plan, g.N, g.d, b->p.K, base);
+        char* tb = base + g.tables_off;
+        Views& v = g.v;
+        v.nds = nds;
+        v.ds = reinterpret_cast<uint32_t*>(tb + L.ds);
+        v.dsbase = reinterpret_cast<uint32_t*>(tb + L.dsbase);
+        v.active = reinterpret_cast<uint32_t*>(tb + L.active);
+        v.st_init = reinterpret_cast<uint64_t*>(tb + L.st_init);
+        v.st_table = reinterpret_cast<uint64_t*>(tb + L.st_table);
+        v.chg = reinterpret_cast<uint32_t*>(tb + L.chg);
+        v.chgoff = reinterpret_cast<uint32_t*>(tb + L.chgoff);
+        v.out_ids = reinterpret_cast<int32_t* const*>(tb + L.out_ids);
+        v.out_dists = reinterpret_cast<float* const*>(tb + L.out_dists);
+        v.in_X = reinterpret_cast<const float* const*>(tb + L.in_X);
+        v.in_d = reinterpret_cast<int32_t*>(tb + L.in_d);
+        v.ds_iters = reinterpret_cast<int32_t*>(tb + L.iters);
+        v.ds_conv = reinterpret_cast<int32_t*>(tb + L.conv);
+        v.ds_stats = reinterpret_cast<int64_t*>(tb + L.stats);
+        std::vector<uint32_t> dsbase(nds + 1);
+        std::vector<uint64_t> st_init(nds), st_table((size_t)nds * T);
+        std::vector<const void*> oi(nds), od(nds), ix(nds);
+        std::vector<int32_t> idd(nds);
+        uint32_t acc = 0;
+        for (int k = 0; k < nds; ++k) {
+            const knng_dataset& D = b->descs[g.members[k]];
+            dsbase[k] = acc;
+            acc += (uint32_t)D.N;
+            st_init[k] = stream_state(D.seed, 1, 0);
+            for (int t = 1; t <= T; ++t) st_table[(size_t)(t - 1) * nds + k] = stream_state(D.seed, 2, (uint64_t)t);
+            oi[k] = D.d_ids;
+            od[k] = D.d_dists;
+            ix[k] = D.dX;
+            idd[k] = D.d;
+        }
+        dsbase[nds] = acc;
+        HIP_TRY(hipMemcpyAsync(tb + L.dsbase, dsbase.data(), dsbase.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.st_init, st_init.data(), st_init.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.st_table, st_table.data(), st_table.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.out_ids, oi.data(), oi.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.out_dists, od.data(), od.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.in_X, ix.data(), ix.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(tb + L.in_d, idd.data(), idd.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));   // host staging vectors go out of scope
+    }
+    return KNNG_OK;
+}
+
+// Enqueue one group's setup + init, or one iteration t, or its write-out.
+void batch_group_setup(const BatchGroup& g, hipStream_t s) {
+    const Views& v = g.v;
+    launch_fill_u64(v.counters, 0ull, kNumCounters, s);
+    launch_batch_setup(v, s);
+    if (g.path == KNNG_PATH_MFMA) launch_norms(v, s);
+    launch_init(v, 0, g.path == KNNG_PATH_MFMA, s);
+}
+
+void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hipStream_t s) {
+    const Views& v = g.v;
+    launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
+    launch_fill_u32(v.chg, 0u, (int64_t)v.N, s);
+    launch_rev_hist(v, s);
+    launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
+    launch_rev_scatter(v, 0, t, s);
+    launch_select(v, 0, t, s);
+    launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
+    if (g.path == KNNG_PATH_MFMA)
+        launch_join_mfma(v, s);
+    else
+        launch_join_valu(v, s);
+    launch_merge(v, s);
+    launch_scan(v.chg, v.chgoff, v.N, v.scan_tmp, s);
+    launch_batch_step(v, t, p.max_iters, p.K, p.delta, s);
+}
+
+void batch_enqueue(knng_batch* b, hipStream_t s) {
+    // larger groups first: they set the critical path
+    for (const auto& g : b->groups) batch_group_setup(g, s);
+    for (int t = 1; t <= b->p.max_iters; ++t)
+        for (const auto& g : b->groups) batch_group_iteration(g, t, b->p, s);
+    for (const auto& g : b->groups) launch_batch_finalize(g.v, s);
+}
+
+// Autotuner: for every d where both join paths are possible, time init plus
+// two iterations of the group with each path (HIP events) and keep the faster.
+knng_status batch_autotune(knng_batch* b, hipStream_t s) {
+    std::string table;
+    std::vector<int> ds_seen;
+    for (const auto& D : b->descs)
+        if (std::find(ds_seen.begin(), ds_seen.end(), D.d) == ds_seen.end()) ds_seen.push_back(D.d);
+    std::sort(ds_seen.begin(), ds_seen.end());
+    const int C = sample_cap(b->p.K, b->p.rho);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (int d : ds_seen) {
+        int best_path = d >= 64 && 2 * C <= 64 ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
+        if (2 * C <= 64) {
+            float best_ms = 1e30f;
+            for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA}) {
+                knng_batch tb;
+                tb.p = b->p;
+                tb.p.path = path;
+                tb.p.max_iters = 2;
+                for (const auto& D : b->descs)
+                    if (D.d == d) tb.descs.push_back(D);
+                size_t total = 0;
+                if (batch_groups(tb.descs.data(), (int32_t)tb.descs.size(), &tb.p, "", tb.groups, total) != KNNG_OK)
+                    continue;
+                if (total > b->ws_bytes) continue;
+                tb.ws = b->ws;
+                tb.ws_bytes = b->ws_bytes;
+                if (batch_upload(&tb, s) != KNNG_OK) continue;
+                for (const auto& g : tb.groups) batch_group_setup(g, s);
+                HIP_TRY(hipEventRecord(e0, s));
+                for (int t = 1; t <= 2; ++t)
+                    for (const auto& g : tb.groups) batch_group_iteration(g, t, tb.p, s);
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                const float ms = ms_between(e0, e1);
+                if (ms >= 0.f && ms < best_ms) {
+                    best_ms = ms;
+                    best_path = path;
+                }
+            }
+        }
+        if (!table.empty()) table += ",";
+        table += std::to_string(d) + (best_path == KNNG_PATH_MFMA ? ":mfma" : ":valu");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tuning = table;
+    return KNNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t knng_batch_workspace_bytes(const knng_dataset* descs, int32_t n, const knng_params* params) {
+    if (batch_validate(descs, n, params) != KNNG_OK) return 0;
+    // room for either join path of every group (the autotuner may pick either)
+    size_t best = 0;
+    for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA}) {
+        knng_params p = *params;
+        if (params->path != KNNG_PATH_AUTO && params->path != path) continue;
+        p.path = path;
+        std::vector<BatchGroup> groups;
+        size_t total = 0;
+        if (batch_groups(descs, n, &p, "", groups, total) == KNNG_OK) best = std::max(best, total);
+    }
+    knng_params p = *params;
+    std::vector<BatchGroup> groups;
+    size_t total = 0;
+    if (batch_groups(descs, n, &p, "", groups, total) == KNNG_OK) best = std::max(best, total);
+    if (best == 0) (void)fail(KNNG_EINVAL, "no valid layout for these datasets");
+    return best;
+}
+
+knng_status knng_batch_plan(knng_batch** out, const knng_dataset* descs, int32_t n, const knng_params* params,
+                            void* d_ws, size_t ws_bytes, const char* tuning, void* stream) {
+    g_err.clear();
+    if (!out) return fail(KNNG_EINVAL, "out is NULL");
+    *out = nullptr;
+    knng_status s = batch_validate(descs, n, params);
+    if (s != KNNG_OK) return s;
+    if (!d_ws) return fail(KNNG_EINVAL, "workspace is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    knng_batch* b = new (std::nothrow) knng_batch();
+    if (!b) return fail(KNNG_ENOMEM, "host allocation of the plan failed");
+    b->p = *params;
+    b->descs.assign(descs, descs + n);
+    b->ws = static_cast<char*>(d_ws);
+    b->ws_bytes = ws_bytes;
+    if (params->path == KNNG_PATH_AUTO && (!tuning || !*tuning || std::string(tuning) == "auto")) {
+        s = batch_autotune(b, st);
+        if (s != KNNG_OK) {
+            delete b;
+            return s;
+        }
+    } else {
+        b->tuning = tuning ? tuning : "";
+    }
+    size_t total = 0;
+    s = batch_groups(descs, n, params, b->tuning, b->groups, total);
+    if (s != KNNG_OK) {
+        delete b;
+        return s;
+    }
+    if (total > ws_bytes) {
+        delete b;
+        char buf[128];
+        snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", ws_bytes, total);
+        return fail(KNNG_ENOMEM, buf);
+    }
+    std::sort(b->groups.begin(), b->groups.end(), [](const BatchGroup& x, const BatchGroup& y) {
+        return (double)x.N * x.dp > (double)y.N * y.dp;
+    });
+    s = batch_upload(b, st);
+    if (s != KNNG_OK) {
+        delete b;
+        return s;
+    }
+    // finiteness of every input (once, here, so that execute needs no read-back)
+    uint64_t hc[kNumCounters];
+    for (const auto& g : b->groups) {
+        launch_fill_u64(g.v.counters, 0ull, kNumCounters, st);
+        launch_batch_setup(g.v, st);
+        if (hipMemcpyAsync(hc, g.v.counters, sizeof hc, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            delete b;
+            return fail(KNNG_EDEVICE, "batch setup failed");
+        }
+        if (hc[kCntNonFinite]) {
+            delete b;
+            return fail(KNNG_EINVAL, "a dataset holds a NaN or an infinity");
+        }
+    }
+    *out = b;
+    return KNNG_OK;
+}
+
+const char* knng_batch_tuning(const knng_batch* b) { return b ? b->tuning.c_str() : ""; }
+
+knng_status knng_batch_execute(knng_batch* b, void* stream) {
+    if (!b) return fail(KNNG_EINVAL, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    batch_enqueue(b, s);
+    HIP_TRY(hipGetLastError());
+    return KNNG_OK;
+}
+
+knng_status knng_batch_capture(knng_batch* b, void* stream) {
+    if (!b) return fail(KNNG_EINVAL, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!s) return fail(KNNG_EINVAL, "capture needs a non-default stream");
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    batch_enqueue(b, s);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(s, &g));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return KNNG_OK;
+}
+
+knng_status knng_batch_launch(knng_batch* b, void* stream) {
+    if (!b || !b->exec) return fail(KNNG_EINVAL, "no captured graph: call knng_batch_capture first");
+    HIP_TRY(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    return KNNG_OK;
+}
+
+knng_status knng_batch_stats(knng_batch* b, int32_t* iters, int32_t* converged, int64_t* evals, int64_t* changes,
+                             void* stream) {
+    if (!b) return fail(KNNG_EINVAL, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int T = b->p.max_iters;
+    for (const auto& g : b->groups) {
+        const int nds = (int)g.members.size();
+        std::vector<int32_t> it(nds), cv(nds);
+        std::vector<int64_t> st((size_t)nds * T * 2);
+        uint64_t hc[kNumCounters];
+        HIP_TRY(hipMemcpyAsync(it.data(), g.v.ds_iters, nds * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(cv.data(), g.v.ds_conv, nds * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(st.data(), g.v.ds_stats, st.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hc, g.v.counters, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hc[kCntError]) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "device invariant failed in a batched build (code %llu)",
+                     (unsigned long long)hc[kCntError]);
+            return fail(KNNG_EDEVICE, buf);
+        }
+        for (int k = 0; k < nds; ++k) {
+            const int i = g.members[k];
+            if (iters) iters[i] = it[k];
+            if (converged) converged[i] = cv[k];
+            for (int t = 0; t < T; ++t) {
+                const bool run = t < it[k];
+                if (evals) evals[(size_t)i * T + t] = run ? st[((size_t)k * T + t) * 2] : 0;
+                if (changes) changes[(size_t)i * T + t] = run ? st[((size_t)k * T + t) * 2 + 1] : 0;
+            }
+        }
+    }
+    return KNNG_OK;
+}
+
+void knng_batch_destroy(knng_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
 }
 
 }  // extern "C"

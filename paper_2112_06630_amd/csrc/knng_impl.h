@@ -50,6 +50,22 @@ struct Views {
     uint32_t* scan_tmp; // scan scratch
     uint64_t* counters; // [kNumCounters]
     uint64_t* partial;  // [partial_words()] per-block partial sums of the merge
+    // batched form (null for a single build): datasets occupy contiguous position ranges
+    int nds;                    // number of datasets
+    const uint32_t* ds;         // [N] dataset of each position
+    const uint32_t* dsbase;     // [nds + 1] first position of each dataset
+    uint32_t* active;           // [nds] 1 while the dataset iterates
+    const uint64_t* st_init;    // [nds] init stream state of each dataset's seed
+    const uint64_t* st_table;   // [T_max, nds] sample stream state of iteration t (row t-1)
+    uint32_t* chg;              // [N] ids that entered each target's list this iteration
+    uint32_t* chgoff;           // [N + 1] scan of chg
+    int32_t* const* out_ids;    // [nds] per-dataset outputs
+    float* const* out_dists;    // [nds]
+    const float* const* in_X;   // [nds] per-dataset inputs
+    const int32_t* in_d;        // [nds]
+    int32_t* ds_iters;          // [nds] iterations run
+    int32_t* ds_conv;           // [nds] 1 if the stop rule held
+    int64_t* ds_stats;          // [nds, T_max, 2] evals and changes per iteration
     // permutation scratch
     int32_t* comp;      // [N] component label (a position) of each point
     int32_t* comp2;     // [N] pointer-jumping scratch
@@ -81,9 +97,14 @@ void launch_norms(const Views& v, hipStream_t s);
 void launch_init(const Views& v, uint64_t st_init, int gram, hipStream_t s);
 void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int gram, hipStream_t s);
 void launch_rev_hist(const Views& v, hipStream_t s);
+// batched form
+void launch_batch_setup(const Views& v, hipStream_t s);
+void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s);
+void launch_batch_finalize(const Views& v, hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t val, int64_t n, hipStream_t s);
 void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
-void launch_rev_scatter(const Views& v, uint64_t st_sample, hipStream_t s);
-void launch_select(const Views& v, uint64_t st_sample, hipStream_t s);
+void launch_rev_scatter(const Views& v, uint64_t st_sample, int t, hipStream_t s);
+void launch_select(const Views& v, uint64_t st_sample, int t, hipStream_t s);
 void launch_join_valu(const Views& v, hipStream_t s);
 void launch_join_mfma(const Views& v, hipStream_t s);
 void launch_make_bf16(const Views& v, hipStream_t s);

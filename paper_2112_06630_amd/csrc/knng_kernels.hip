@@ -111,6 +111,15 @@ __device__ __forceinline__ void wave_bitonic_clean(uint64_t& k, uint32_t& v) {
     for (int j = 32; j > 0; j >>= 1) cmpx(k, v, j, true);
 }
 
+// Batched form: position p belongs to dataset ds[p]; a single build has no
+// dataset table and every position is active.
+__device__ __forceinline__ bool pos_active(const Views& v, int p) { return !v.ds || v.active[v.ds[p]] != 0u; }
+
+// Sample stream state of the owner's dataset for iteration t (t >= 1).
+__device__ __forceinline__ uint64_t sample_state(const Views& v, int p, uint64_t st, int t) {
+    return v.ds ? v.st_table[(size_t)(t - 1) * v.nds + v.ds[p]] : st;
+}
+
 __device__ __forceinline__ uint64_t key_of(float D, uint32_t id) {
     return ((uint64_t)__float_as_uint(D) << 32) | id;
 }
@@ -211,6 +220,16 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
 }
 
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
+}
+
 void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
@@ -280,14 +299,25 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
 __global__ __launch_bounds__(256) void k_init(Views v, uint64_t st, int gram) {
     __shared__ uint32_t s_sel[kRowWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int N = v.N, K = v.K;
-    for (int u = blockIdx.x * kRowWaves + w; u < N; u += gridDim.x * kRowWaves) {
+    const int K = v.K;
+    for (int u = blockIdx.x * kRowWaves + w; u < v.N; u += gridDim.x * kRowWaves) {
+        // ids are local to the dataset (the whole build for a single one)
+        uint32_t base = 0, n = (uint32_t)v.N;
+        uint64_t sti = st;
+        if (v.ds) {
+            const uint32_t i = v.ds[u];
+            base = v.dsbase[i];
+            n = v.dsbase[i + 1] - base;
+            sti = v.st_init[i];
+        }
+        const uint32_t ul = (uint32_t)u - base;
         int have = 0;
-        for (uint32_t base = 0; have < K; base += 64) {
-            const uint32_t j = base + (uint32_t)lane;
-            const uint64_t h = mix64(st ^ (((uint64_t)(uint32_t)u << 32) | j));
-            uint32_t c = (uint32_t)(((h >> 32) * (uint64_t)(uint32_t)(N - 1)) >> 32);
-            c += (c >= (uint32_t)u) ? 1u : 0u;
+        for (uint32_t b0 = 0; have < K; b0 += 64) {
+            const uint32_t j = b0 + (uint32_t)lane;
+            const uint64_t h = mix64(sti ^ (((uint64_t)ul << 32) | j));
+            uint32_t c = (uint32_t)(((h >> 32) * (uint64_t)(n - 1)) >> 32);
+            c += (c >= ul) ? 1u : 0u;
+            c += base;
             bool novel = true;
             for (int i = 0; i < have; ++i) novel &= (s_sel[w][i] != c);
             for (int i = 0; i < 63; ++i) {
@@ -413,22 +443,28 @@ void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStr
 
 // ------------------------------------------------------------------ reverse lists (a2)
 
-__global__ void k_rev_hist(const uint32_t* __restrict__ lpos, int64_t NK, uint32_t* __restrict__ rdeg) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&rdeg[lpos[e] & kPosMask], 1u);
+__global__ void k_rev_hist(Views v) {
+    const int64_t NK = (int64_t)v.N * v.K;
+    const double rk = 1.0 / v.K;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
+        if (v.ds && !pos_active(v, (int)udiv((uint32_t)e, (uint32_t)v.K, rk))) continue;
+        atomicAdd(&v.rdeg[v.lpos[e] & kPosMask], 1u);
+    }
 }
 
 void launch_rev_hist(const Views& v, hipStream_t s) {
     const int64_t NK = (int64_t)v.N * v.K;
-    hipLaunchKernelGGL(k_rev_hist, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v.lpos, NK, v.rdeg);
+    hipLaunchKernelGGL(k_rev_hist, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v);
 }
 
 // Each edge u->v (flag f) becomes the reverse entry {w, orig u, pos u | f} of v.
-__global__ void k_rev_scatter(Views v, uint64_t st) {
+__global__ void k_rev_scatter(Views v, uint64_t st0, int t) {
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
         const int u = (int)udiv((uint32_t)e, (uint32_t)v.K, rk);
+        if (v.ds && !pos_active(v, u)) continue;
+        const uint64_t st = sample_state(v, u, st0, t);
         const uint32_t pf = v.lpos[e];
         const uint32_t tp = pf & kPosMask;
         const uint32_t ov = (uint32_t)v.lkey[e];
@@ -439,9 +475,9 @@ __global__ void k_rev_scatter(Views v, uint64_t st) {
     }
 }
 
-void launch_rev_scatter(const Views& v, uint64_t st, hipStream_t s) {
+void launch_rev_scatter(const Views& v, uint64_t st, int t, hipStream_t s) {
     const int64_t NK = (int64_t)v.N * v.K;
-    hipLaunchKernelGGL(k_rev_scatter, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v, st);
+    hipLaunchKernelGGL(k_rev_scatter, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v, st, t);
 }
 
 // ------------------------------------------------------------------ select (a2)
@@ -547,7 +583,7 @@ __device__ void select_radix_thresholds(const Views& v, uint64_t st, int u, uint
 // Pools of more than 64 entries (owners with a large reverse in-degree):
 // staged in LDS (after a radix prefilter when they exceed the stage), ranks
 // by counting over the stage.
-__global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st) {
+__global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int t) {
     __shared__ SelLds L;
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K, C = v.C;
@@ -555,6 +591,7 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st) {
     uint32_t* spos = L.pos[w];
     for (int u = blockIdx.x * kSelWaves + w; u < v.N; u += gridDim.x * kSelWaves) {
         if (!v.big[u]) continue;
+        const uint64_t st = sample_state(v, u, st0, t);
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
         const uint32_t ou = (uint32_t)v.orig[u];
@@ -708,7 +745,7 @@ __device__ __forceinline__ void pool_read(const Views& v, uint64_t st, int u, ui
 
 constexpr int kSelLWaves = 4;
 
-__global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st) {
+__global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0, int t) {
     __shared__ uint64_t s_key[kSelLWaves][64];
     __shared__ uint32_t s_idx[kSelLWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -716,6 +753,7 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st) 
     const uint32_t C = (uint32_t)v.C;
     for (int u = blockIdx.x * kSelLWaves + w; u < v.N; u += gridDim.x * kSelLWaves) {
         if (!v.big[u]) continue;
+        const uint64_t st = sample_state(v, u, st0, t);
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
         const uint32_t ou = (uint32_t)v.orig[u];
@@ -859,11 +897,19 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st) 
 // reached by both routes with the same flag next to each other (the second
 // is a duplicate), and a member's NEW entry right before its OLD entry.
 // Ranks per flag are ballot prefix counts over the sorted lanes.
-__global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st) {
+__global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int t) {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int N = v.N, K = v.K;
     const uint32_t C = (uint32_t)v.C;
     for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
+        if (v.ds && !pos_active(v, u)) {   // finished dataset: nothing sampled, nothing joined
+            if (lane == 0) {
+                v.big[u] = 0u;
+                v.nn[u] = 0u;
+            }
+            continue;
+        }
+        const uint64_t st = sample_state(v, u, st0, t);
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
         if (lane == 0) v.big[u] = P > 64 ? 1u : 0u;
@@ -923,12 +969,12 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st) {
     }
 }
 
-void launch_select(const Views& v, uint64_t st, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st);
+void launch_select(const Views& v, uint64_t st, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
     if (2 * v.C <= 64)
-        hipLaunchKernelGGL(k_select_large_thr, dim3(grid_for(v.N, kSelLWaves, 4096)), dim3(256), 0, s, v, st);
+        hipLaunchKernelGGL(k_select_large_thr, dim3(grid_for(v.N, kSelLWaves, 4096)), dim3(256), 0, s, v, st, t);
     else
-        hipLaunchKernelGGL(k_select_large, dim3(grid_for(v.N, kSelWaves, 4096)), dim3(256), 0, s, v, st);
+        hipLaunchKernelGGL(k_select_large, dim3(grid_for(v.N, kSelWaves, 4096)), dim3(256), 0, s, v, st, t);
 }
 
 // ------------------------------------------------------------------ join (a3, a4)
@@ -1491,7 +1537,9 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, size_t row
         v.lkey[row + lane] = key;
         v.lpos[row + lane] = pf;
     }
-    return (uint64_t)__popcll(ballot(entered));
+    const uint64_t c = (uint64_t)__popcll(ballot(entered));
+    if (v.chg && lane == 0) v.chg[row / K] = (uint32_t)c;   // batched form: changes per target
+    return c;
 }
 
 // One wave per target; buckets above kHubProposals go to k_merge_hubs.
@@ -1662,6 +1710,92 @@ __global__ void k_export_samples(Views v, int32_t* __restrict__ dnew, int32_t* _
 
 void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t* counts, hipStream_t s) {
     hipLaunchKernelGGL(k_export_samples, dim3(grid_for(v.N, 256, 8192)), dim3(256), 0, s, v, dnew, dold, counts);
+}
+
+// ------------------------------------------------------------------ batched form (a10)
+//
+// Many independent datasets share one position space (each a contiguous
+// range); every kernel above is per node and never follows an edge out of a
+// node's own dataset, so one launch advances every active dataset by one
+// iteration. Each dataset keeps its seed (init/sample stream states), its
+// iteration counter, its stop rule and its statistics on the device; nothing
+// is read back, so the whole build can be captured in one graph.
+
+// one workgroup per dataset: dataset index, local ids, padded rows
+__global__ void k_batch_setup(Views v) {
+    for (int i = blockIdx.x; i < v.nds; i += gridDim.x) {
+        const uint32_t b = v.dsbase[i], e = v.dsbase[i + 1];
+        const int d = v.in_d[i];
+        const float* X = v.in_X[i];
+        uint32_t* dsw = const_cast<uint32_t*>(v.ds);
+        for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+            dsw[p] = (uint32_t)i;
+            v.orig[p] = (int32_t)(p - b);
+            v.posof[p] = (int32_t)(p - b);
+        }
+        const int64_t cnt = (int64_t)(e - b) * v.dp;
+        bool bad = false;
+        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+            const int64_t r = q / v.dp;
+            const int c = (int)(q - r * v.dp);
+            const float x = c < d ? X[r * d + c] : 0.f;
+            bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
+            v.Xp[(size_t)b * v.dp + q] = x;
+        }
+        if (bad) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
+        if (threadIdx.x == 0) {
+            v.active[i] = 1u;
+            v.ds_iters[i] = 0;
+            v.ds_conv[i] = 0;
+        }
+    }
+}
+
+void launch_batch_setup(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_setup, dim3(v.nds < 4096 ? v.nds : 4096), dim3(256), 0, s, v);
+}
+
+// after iteration t: per-dataset e_t and c_t from the scans over its range,
+// then the stop rule c_t < delta*N_i*K, or t = T_max
+__global__ void k_batch_step(Views v, int t, int T_max, int K, double delta) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < v.nds; i += gridDim.x * blockDim.x) {
+        if (!v.active[i]) continue;
+        const uint32_t b = v.dsbase[i], e = v.dsbase[i + 1];
+        const int64_t ev = (int64_t)(v.poff[e] - v.poff[b]) / 2;
+        const int64_t ch = (int64_t)(v.chgoff[e] - v.chgoff[b]);
+        v.ds_stats[((size_t)i * T_max + (t - 1)) * 2] = ev;
+        v.ds_stats[((size_t)i * T_max + (t - 1)) * 2 + 1] = ch;
+        v.ds_iters[i] = t;
+        if ((double)ch < delta * (double)(e - b) * (double)K) {
+            v.ds_conv[i] = 1;
+            v.active[i] = 0u;
+        } else if (t >= T_max) {
+            v.active[i] = 0u;
+        }
+    }
+}
+
+void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_step, dim3((v.nds + 255) / 256), dim3(256), 0, s, v, t, T_max, K, delta);
+}
+
+// per-dataset outputs: rows sorted by (distance, local id)
+__global__ void k_batch_finalize(Views v) {
+    const int64_t NK = (int64_t)v.N * v.K;
+    const double rk = 1.0 / v.K;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)udiv((uint32_t)e, (uint32_t)v.K, rk), k = (int)(e - (int64_t)p * v.K);
+        const uint32_t i = v.ds[p];
+        const size_t o = (size_t)(p - (int)v.dsbase[i]) * v.K + k;
+        const uint64_t key = v.lkey[e];
+        v.out_ids[i][o] = (int32_t)(uint32_t)key;
+        v.out_dists[i][o] = __uint_as_float((uint32_t)(key >> 32));
+    }
+}
+
+void launch_batch_finalize(const Views& v, hipStream_t s) {
+    const int64_t NK = (int64_t)v.N * v.K;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v);
 }
 
 // ------------------------------------------------------------------ permutation (a7)

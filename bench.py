@@ -31,6 +31,8 @@ WORKLOADS = {
                        gen=lambda: __import__("synth").config(1)[0]),
     "blobs4m_d3": dict(workload="blobs4m_d3", N=4_000_000, d=3, K=15, rho=0.5, delta=0.001, max_iters=30, seed=2,
                        gen=lambda: __import__("synth").lowd_blobs(4_000_000, 2)),
+    "batch512": dict(workload="batch512", N=None, d=None, K=15, rho=1.0, delta=0.001, max_iters=30, seed=4,
+                     gen=lambda: __import__("synth").batched_datasets(512, 4)),
     "aniso200k_d960": dict(workload="aniso200k_d960", N=200_000, d=960, K=20, rho=0.5, delta=0.001, max_iters=30,
                            seed=3, gen=lambda: __import__("synth").anisotropic_clusters(200_000, 960, 3)),
 }
@@ -105,6 +107,113 @@ def traffic_record(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def bench_batch(args, w):
+    """512 independent datasets in one captured graph vs 512 sequential builds."""
+    import numpy as np
+    import torch
+    import paper_2112_06630_amd as knng
+    data = w["gen"]()
+    dev = torch.device("cuda:0")
+    Xs = [torch.from_numpy(X).to(dev) for X, _ in data]
+    seeds = [s for _, s in data]
+    t0 = time.perf_counter()
+    b = knng.Batch(Xs, seeds, w["K"], w["rho"], w["delta"], w["max_iters"])
+    plan_s = time.perf_counter() - t0
+    b.capture()
+    for _ in range(args.warmup):
+        b.launch()
+    b.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(b.stream)
+    for _ in range(args.steps):
+        b.launch()
+    ev1.record(b.stream)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    st = b.stats()
+    evals = int(sum(sum(e) for e in st["evals"]))
+    entries = dict(e.split(":") for e in b.tuning.split(","))
+    # the same builds one dataset at a time (same join paths)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_ids = []
+    for X, s in zip(Xs, seeds):
+        seq_ids.append(knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], s,
+                                  path=entries[str(X.shape[1])])[0])
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    identical = all(torch.equal(a, c) for a, c in zip(b.ids, seq_ids))
+    rec = None
+    if not args.no_recall:
+        tot, good = 0, 0.0
+        for X, ids in zip(Xs, b.ids):
+            rows = torch.arange(X.shape[0], device=dev)
+            tau = exact_kth(X, w["K"], rows)
+            good += recall_of(X, ids, tau, rows) * X.shape[0]
+            tot += X.shape[0]
+        rec = good / tot
+    out = {
+        "metric": "distance evals/sec", "value": round(evals / (ms_per_step / 1e3), 1), "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch512", "datasets": len(data), "N_total": int(sum(X.shape[0] for X in Xs)),
+                   "dims": sorted({int(X.shape[1]) for X in Xs}), "K": w["K"], "rho": w["rho"],
+                   "delta": w["delta"], "max_iters": w["max_iters"], "tuning": b.tuning},
+        "evals_per_build": evals, "recall": rec, "sequential_ms": round(seq_ms, 3),
+        "speedup_vs_sequential": round(seq_ms / ms_per_step, 2), "identical_to_sequential": identical,
+        "graph_device_ms": round(ev0.elapsed_time(ev1) / args.steps, 3), "plan_and_tune_s": round(plan_s, 3),
+        "iters_max": int(max(st["iters"])), "converged": int(sum(st["converged"])),
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
+    """Writes profiles/traffic.json: HBM bytes per launch of each knng kernel
+    from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the counter reads for the plain copy of
+    copy_mib MiB that bench.py --copy-probe-mib issues in the same run."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        rows = list(csv.DictReader(open(path)))
+        agg = collections.defaultdict(list)
+        probe = None
+        for r in rows:
+            if r.get("Counter_Name", counter) != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("knng::", "")
+            kib = float(r["Counter_Value"])
+            if "copyBuffer" in name and int(r["Grid_Size"]) >= (copy_mib << 7):
+                probe = kib
+            agg[name].append(kib)
+        return agg, probe
+
+    fetch, fprobe = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wprobe = per_kernel(write_csv, "WRITE_SIZE")
+    if not fprobe or not wprobe:
+        raise SystemExit("copy probe not found in the counter runs")
+    f_scale = copy_mib * 1024.0 / fprobe   # a copy reads copy_mib MiB
+    w_scale = copy_mib * 1024.0 / wprobe   # and writes copy_mib MiB
+    out = {"_scale": {"fetch": f_scale, "write": w_scale, "copy_mib": copy_mib}, "_command": command}
+    for k in sorted(set(fetch) | set(write)):
+        if not k.startswith("k_"):
+            continue
+        fb = sum(fetch.get(k, [0])) / max(1, len(fetch.get(k, [1]))) * 1024 * f_scale
+        wb = sum(write.get(k, [0])) / max(1, len(write.get(k, [1]))) * 1024 * w_scale
+        out[k] = {"source_hash": kernel_source_hash(), "bytes_per_launch": int(fb + wb),
+                  "fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
+                  "launches": len(fetch.get(k, []))}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    prev = json.load(open(path)) if os.path.exists(path) else {}
+    prev.update({k: v for k, v in out.items()})
+    json.dump(prev, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps({k: out[k] for k in out if not k.startswith("_")}, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +229,13 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the builds, copy this many MiB once (device to device) so that "
                          "HBM counters can be scaled by a kernel of known traffic")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize two rocprofv3 counter runs into profiles/traffic.json and exit")
+    ap.add_argument("--pmc-command", default="", help="the command the counter runs used (recorded)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe_mib or 1024, args.pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -131,6 +246,9 @@ def main():
     import paper_2112_06630_amd as knng
 
     w = WORKLOADS[args.workload]
+    if args.workload == "batch512":
+        bench_batch(args, w)
+        return
     Xnp = w["gen"]()
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)

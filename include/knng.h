@@ -54,10 +54,31 @@ typedef enum {
                              original rows and only rescored distances are stored (MFMA path) */
 } knng_precision;
 
+/*
+ * Join paths. AUTO takes the VALU direct form when d < 64 or ceil(rho*K) > 32,
+ * else the MFMA Gram form; on the MFMA side it would take the exact integer
+ * form when X qualifies (FP32 precision only; checked on the device at create).
+ *
+ * Exact integer form (KNNG_PATH_MFMA_I8). X qualifies when every value is an
+ * integer of magnitude <= 2^24 and max(X) - min(X) <= 255 over the whole input
+ * (8-bit pixel data, for instance), and d <= 32768. The rows are shifted by one
+ * constant (min(X) + 128) into int8; squared distances are shift invariant, so
+ * ||x'||^2 + ||y'||^2 - 2 x'.y' computed in int32 (int8 MFMA tiles, int32
+ * accumulation; no overflow for d <= 32768) is the exact squared distance, and
+ * the stored FP32 distance is its correctly rounded value. Wherever the FP32
+ * forms are exact (all partial sums below 2^24) the results are bit-identical
+ * to theirs. Requesting it for an input that does not qualify fails with
+ * KNNG_EINVAL at knng_create.
+ *
+ * In this release the exact integer form is disabled: a request for it fails
+ * with KNNG_EINVAL (at knng_workspace_bytes and knng_create) and AUTO never
+ * selects it.
+ */
 typedef enum {
-    KNNG_PATH_AUTO = 0,   /* VALU direct form at low d, MFMA Gram tiles at high d */
-    KNNG_PATH_VALU = 1,   /* sum_j (x_j - y_j)^2 on the vector ALUs */
-    KNNG_PATH_MFMA = 2    /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
+    KNNG_PATH_AUTO = 0,     /* see above */
+    KNNG_PATH_VALU = 1,     /* sum_j (x_j - y_j)^2 on the vector ALUs */
+    KNNG_PATH_MFMA = 2,     /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
+    KNNG_PATH_MFMA_I8 = 3   /* exact integer form: int8 MFMA tiles, int32 accumulation */
 } knng_path;
 
 typedef struct {

@@ -55,17 +55,19 @@ int32_t sample_cap(int32_t K, double rho) {
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Plan {
-    int path;        // resolved knng_path
+    int path;        // resolved knng_path (MFMA until the create-time check picks MFMA_I8)
+    int want_i8;     // 0: no, 1: if X qualifies, 2: required (KNNG_PATH_MFMA_I8)
     int reorder;
     int bf16;        // BF16-screened precision form
     int dp;
+    int dpi;         // int8 row length of the exact integer form
     int C;
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_ppos, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
-        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag;
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2;
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -79,25 +81,44 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (p->max_iters < 0 || p->max_iters > KNNG_MAX_ITERS)
         return fail(KNNG_EINVAL, "max_iters must be in [0, 64]");
     if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
-    if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA) return fail(KNNG_EINVAL, "unknown path");
+    if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_I8) return fail(KNNG_EINVAL, "unknown path");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
     return KNNG_OK;
 }
 
-knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
+// The exact integer form is switched off: its first run at 60000 x 784 ended
+// in a device fault whose cause has not been found. Requests fail with
+// KNNG_EINVAL and AUTO never selects it; the kernels stay in the library.
+constexpr bool kInt8FormEnabled = false;
+
+knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool allow_i8 = true) {
     knng_status s = validate(N, d, p);
     if (s != KNNG_OK) return s;
     const int K = p->K;
     P.C = sample_cap(K, p->rho);
     int path = p->path;
     P.bf16 = p->precision == KNNG_BF16_SCREEN ? 1 : 0;
+    P.want_i8 = 0;
+    if (!kInt8FormEnabled) allow_i8 = false;
+    if (path == KNNG_PATH_MFMA_I8) {
+        if (!kInt8FormEnabled) return fail(KNNG_EINVAL, "the exact integer form is disabled in this release");
+        if (!allow_i8) return fail(KNNG_EINVAL, "the exact integer form is not available here");
+        if (P.bf16) return fail(KNNG_EINVAL, "the exact integer form excludes the BF16-screened form");
+        if (d > kMaxI8Dim) return fail(KNNG_EINVAL, "the exact integer form needs d <= 32768");
+        P.want_i8 = 2;
+        path = KNNG_PATH_MFMA;
+    }
     if (P.bf16) {
         if (path == KNNG_PATH_VALU) return fail(KNNG_EINVAL, "the BF16-screened form runs on the MFMA path");
         path = KNNG_PATH_MFMA;
     }
-    if (path == KNNG_PATH_AUTO) path = (d >= 64 && 2 * P.C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
+    if (path == KNNG_PATH_AUTO) {
+        path = (d >= 64 && 2 * P.C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
+        if (path == KNNG_PATH_MFMA && !P.bf16 && allow_i8 && d <= kMaxI8Dim) P.want_i8 = 1;
+    }
     if (path == KNNG_PATH_MFMA && 2 * P.C > 64) return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
     P.path = path;
+    P.dpi = P.want_i8 ? (int)round_up(d, 64) : 0;
     P.reorder = p->reorder ? 1 : 0;
     P.dp = (int)(path == KNNG_PATH_MFMA ? round_up(d, 32) : round_up(d, 4));
     if (path == KNNG_PATH_VALU) {
@@ -143,6 +164,14 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
         if (p->reorder) {
             P.o_Xb2 = take((size_t)N * P.dp * 2);
             P.o_nb2 = take((size_t)N * 4);
+        }
+    }
+    if (P.want_i8) {
+        P.o_Xi = take((size_t)N * P.dpi);
+        P.o_ni = take((size_t)N * 4);
+        if (p->reorder) {
+            P.o_Xi2 = take((size_t)N * P.dpi);
+            P.o_ni2 = take((size_t)N * 4);
         }
     }
     if (p->reorder) {   // permutation scratch only when the permutation is on
@@ -221,6 +250,13 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
         v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
         v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
     }
+    v.dpi = P.dpi;
+    if (P.want_i8) {   // v.Xi stays null until the create-time check selects the form
+        if (P.reorder) {
+            v.Xi2 = reinterpret_cast<int8_t*>(b + P.o_Xi2);
+            v.ni2 = reinterpret_cast<int32_t*>(b + P.o_ni2);
+        }
+    }
     v.flag = reinterpret_cast<uint32_t*>(b + P.o_flag);
     return v;
 }
@@ -242,6 +278,7 @@ struct knng_ctx {
     int32_t d;
     hipStream_t stream;
     const float* dX;
+    void* ws;
     int t;               // iterations completed
     bool permuted;
     int perm_levels;
@@ -289,6 +326,10 @@ knng_status do_permute(knng_ctx* c) {
     std::swap(v.lpos, v.lpos2);
     std::swap(v.Xb, v.Xb2);
     std::swap(v.nb, v.nb2);
+    if (v.Xi) {
+        std::swap(v.Xi, v.Xi2);
+        std::swap(v.ni, v.ni2);
+    }
     launch_perm_posof(v, s);
     HIP_TRY(hipEventRecord(c->ev[5], s));
     HIP_TRY(hipGetLastError());
@@ -325,6 +366,8 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     HIP_TRY(hipEventRecord(c->ev[1], s));
     if (c->plan.bf16)
         launch_join_bf16(v, s);
+    else if (c->plan.path == KNNG_PATH_MFMA_I8)
+        launch_join_i8(v, s);
     else if (c->plan.path == KNNG_PATH_MFMA)
         launch_join_mfma(v, s);
     else
@@ -365,6 +408,36 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     return KNNG_OK;
 }
 
+int dist_mode(const knng_ctx* c) {
+    if (c->plan.path == KNNG_PATH_MFMA_I8) return kDistInt8;
+    return (c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16) ? kDistGram : kDistDirect;
+}
+
+// Exact integer form: check X on the device (integers, |x| <= 2^24, span <=
+// 255), then shift the rows into int8 and switch the join to the int8 tiles.
+knng_status select_int8(knng_ctx* c) {
+    Views& v = c->v;
+    launch_int_scan(c->dX, c->N * (int64_t)c->d, v.flag, c->stream);
+    HIP_TRY(hipGetLastError());
+    uint32_t fl[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(fl, v.flag + 8, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int32_t lo = (int32_t)fl[1], hi = (int32_t)fl[2];
+    const bool ok = fl[0] == 0u && (int64_t)hi - (int64_t)lo <= 255;
+    if (!ok) {
+        if (c->plan.want_i8 == 2)
+            return fail(KNNG_EINVAL, "the exact integer form needs integer X with max - min <= 255 and |x| <= 2^24");
+        return KNNG_OK;
+    }
+    char* b = static_cast<char*>(c->ws);
+    v.Xi = reinterpret_cast<int8_t*>(b + c->plan.o_Xi);
+    v.ni = reinterpret_cast<int32_t*>(b + c->plan.o_ni);
+    launch_make_i8(v, lo + 128, c->stream);
+    HIP_TRY(hipGetLastError());
+    c->plan.path = KNNG_PATH_MFMA_I8;
+    return KNNG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -402,6 +475,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     c->d = d;
     c->stream = static_cast<hipStream_t>(stream);
     c->dX = dX;
+    c->ws = d_ws;
     c->v = carve(P, N, d, params->K, d_ws);
     std::memset(&c->stats, 0, sizeof(c->stats));
     c->stats.path = P.path;
@@ -425,6 +499,14 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
         knng_destroy(c);
         return fail(KNNG_EINVAL, "X holds a NaN or an infinity");
     }
+    if (P.want_i8) {
+        knng_status is = select_int8(c);
+        if (is != KNNG_OK) {
+            knng_destroy(c);
+            return is;
+        }
+    }
+    c->stats.path = c->plan.path;
     *out = c;
     return KNNG_OK;
 }
@@ -432,7 +514,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
 knng_status knng_init_graph(knng_ctx* c) {
     if (!c) return fail(KNNG_EINVAL, "ctx is NULL");
     if (c->permuted) return fail(KNNG_EINVAL, "init after permutation is not supported");
-    launch_init(c->v, stream_state(c->p.seed, 1, 0), c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16, c->stream);
+    launch_init(c->v, stream_state(c->p.seed, 1, 0), dist_mode(c), c->stream);
     HIP_TRY(hipGetLastError());
     c->t = 0;
     c->has_graph = true;
@@ -445,7 +527,7 @@ knng_status knng_load_graph(knng_ctx* c, const int32_t* d_ids, const uint8_t* d_
     if (c->permuted) return fail(KNNG_EINVAL, "load after permutation is not supported");
     if (t < 0 || t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "t out of range");
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
-    launch_load_rows(c->v, d_ids, d_flags, c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16, c->stream);
+    launch_load_rows(c->v, d_ids, d_flags, dist_mode(c), c->stream);
     HIP_TRY(hipGetLastError());
     knng_status rs = read_counters(c);
     if (rs != KNNG_OK) return rs;
@@ -643,6 +725,7 @@ knng_status batch_validate(const knng_dataset* descs, int32_t n, const knng_para
     if (!p) return fail(KNNG_EINVAL, "params is NULL");
     if (p->reorder) return fail(KNNG_EINVAL, "the batched form runs without the permutation");
     if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "the batched form runs in FP32");
+    if (p->path == KNNG_PATH_MFMA_I8) return fail(KNNG_EINVAL, "the batched form has no exact integer form");
     if (p->max_iters < 1) return fail(KNNG_EINVAL, "the batched form needs max_iters >= 1");
     for (int i = 0; i < n; ++i) {
         if (!descs[i].dX || !descs[i].d_ids || !descs[i].d_dists) return fail(KNNG_EINVAL, "dataset pointer is NULL");
@@ -683,7 +766,7 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
         gp.path = g.path;
         gp.reorder = 0;
         Plan P{};
-        knng_status s = make_plan(g.N, g.d, &gp, P);
+        knng_status s = make_plan(g.N, g.d, &gp, P, false);
         if (s != KNNG_OK) return s;
         g.plan = P;
         g.off = total;
@@ -753,7 +836,7 @@ void batch_group_setup(const BatchGroup& g, hipStream_t s) {
     launch_fill_u64(v.counters, 0ull, kNumCounters, s);
     launch_batch_setup(v, s);
     if (g.path == KNNG_PATH_MFMA) launch_norms(v, s);
-    launch_init(v, 0, g.path == KNNG_PATH_MFMA, s);
+    launch_init(v, 0, g.path == KNNG_PATH_MFMA ? kDistGram : kDistDirect, s);
 }
 
 void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hipStream_t s) {

@@ -23,6 +23,17 @@ enum Counter : int {
     kNumCounters = 8
 };
 
+// How a kernel outside the join computes a distance: the same formula as the
+// join of the resolved path, so a pair gets one key wherever it is evaluated
+// (exactly so for the VALU and integer forms).
+enum DistMode : int {
+    kDistDirect = 0,   // sum_j (x_j - y_j)^2, FP32 (VALU path)
+    kDistGram = 1,     // FP32 Gram form (FP32 MFMA path)
+    kDistInt8 = 2      // exact int32 Gram form of the shifted int8 rows
+};
+
+constexpr int kMaxI8Dim = 32768;   // d * 255^2 and the int32 Gram terms stay below 2^31
+
 // Views of the caller's workspace, carved by the host.
 struct Views {
     int N, d, dp, K, C;
@@ -30,6 +41,9 @@ struct Views {
     float* nrm;         // [N] squared norms (Gram path)
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
     float* nb;          // [N] squared norms of the BF16 rows
+    int dpi;            // int8 row length (multiple of 64), exact integer form
+    int8_t* Xi;         // [N, dpi] rows shifted into int8 (exact integer form), else null
+    int32_t* ni;        // [N] squared norms of the int8 rows
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
@@ -82,6 +96,8 @@ struct Views {
     float* nrm2;        // [N]
     uint16_t* Xb2;      // [N, dp]
     float* nb2;         // [N]
+    int8_t* Xi2;        // [N, dpi]
+    int32_t* ni2;       // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
 };
@@ -94,8 +110,13 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
 void launch_norms(const Views& v, hipStream_t s);
-void launch_init(const Views& v, uint64_t st_init, int gram, hipStream_t s);
-void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int gram, hipStream_t s);
+void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s);
+void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int mode, hipStream_t s);
+// exact integer form: flag[8] |= 1 if some value is not an integer of
+// magnitude <= 2^24; flag[9] = min, flag[10] = max (int32) of the others
+void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t s);
+void launch_make_i8(const Views& v, int32_t shift, hipStream_t s);
+void launch_join_i8(const Views& v, hipStream_t s);
 void launch_rev_hist(const Views& v, hipStream_t s);
 // batched form
 void launch_batch_setup(const Views& v, hipStream_t s);

@@ -18,3 +18,11 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def pytest_runtest_setup(item):
+    # name each GPU test before it runs, unbuffered, so that a run that dies
+    # in a device call still shows which test it was in
+    if item.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"[start] {item.nodeid}\n")
+        sys.__stderr__.flush()

@@ -58,6 +58,8 @@ def _params(**kw):
     (100, 8, dict(max_iters=-1), "max_iters"),
     (100, 8, dict(max_iters=65), "max_iters"),
     (100, 784, dict(K=64, rho=1.0, path="mfma"), "MFMA"),
+    (100, 784, dict(path=4), "unknown path"),
+    (100, 784, dict(path="mfma_i8"), "disabled"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
     import paper_2112_06630_amd as knng
@@ -95,3 +97,20 @@ def test_workspace_grows_with_size():
     b = knng.workspace_bytes(2000, 8, _params())
     c = knng.workspace_bytes(2000, 784, _params(K=20))
     assert 0 < a < b < c
+
+
+def test_integer_form_workspace():
+    """The exact integer form is switched off: AUTO reserves no int8 rows."""
+    import paper_2112_06630_amd as knng
+    N, d = 3000, 784
+    assert knng.workspace_bytes(N, d, _params(K=20, path="auto")) == knng.workspace_bytes(N, d, _params(K=20, path="mfma"))
+    assert knng.workspace_bytes(N, 8, _params(path="auto")) == knng.workspace_bytes(N, 8, _params(path="valu"))
+
+
+def test_header_path_values_match_binding():
+    import paper_2112_06630_amd as knng
+    import re
+    text = open(HDR).read()
+    vals = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"(KNNG_PATH_\w+)\s*=\s*(\d+)", text))
+    assert vals == {"KNNG_PATH_AUTO": knng.PATH_AUTO, "KNNG_PATH_VALU": knng.PATH_VALU,
+                    "KNNG_PATH_MFMA": knng.PATH_MFMA, "KNNG_PATH_MFMA_I8": knng.PATH_MFMA_I8}

@@ -14,6 +14,11 @@ from parity import check_rows
 
 pytestmark = pytest.mark.gpu
 
+# The exact integer form (int8 MFMA) is switched off in the library: its first
+# GPU run ended in a device fault whose cause has not been found, so its
+# tests stay skipped until one is.
+I8_OFF = pytest.mark.skip(reason="exact integer form switched off (unresolved device fault)")
+
 
 @pytest.fixture(scope="module")
 def knng():
@@ -61,10 +66,94 @@ def test_build_integer_points_bitwise_mfma(knng, N, d, K, rho, hi, seed):
     assert st["path"] == knng.PATH_MFMA
 
 
-def test_image_like_subset_bitwise_mfma(knng):
+def test_image_like_subset_bitwise(knng):
     """784-d 0..255 integer data (image-shaped workload at N=3000): exact in FP32."""
     X = synth.image_like(3000, 1)
-    exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path="auto")
+    st = exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path="auto")
+    assert st["path"] == knng.PATH_MFMA
+
+
+# ----------------------------------------------------------------- exact integer form (int8 MFMA)
+
+@I8_OFF
+@pytest.mark.parametrize("N,d,K,rho,lo,hi,seed", [
+    (700, 64, 10, 1.0, 0, 255, 1),         # full 8-bit span
+    (600, 100, 20, 0.5, -1000, -745, 2),   # negative, shifted span 255
+    (900, 130, 16, 1.0, 3, 9, 3),          # narrow span, d not a multiple of 64
+    (400, 33, 12, 0.9, 100, 300, 4),       # d < 64 on request
+    (520, 257, 32, 1.0, -128, 127, 5),     # 2C = 64 columns, dpi = 320 (ragged k blocks)
+])
+def test_integer_form_bitwise(knng, N, d, K, rho, lo, hi, seed):
+    """Every distance is exact, so the graph, e_t and c_t equal the oracle's bit for bit."""
+    X = (synth.integer_points(N, d, hi - lo, seed) + np.float32(lo)).astype(np.float32)
+    st = exact_build(knng, X, K, rho, 0.001, 15, seed, path="mfma_i8")
+    assert st["path"] == knng.PATH_MFMA_I8
+
+
+@I8_OFF
+def test_integer_form_matches_fp32_paths(knng):
+    """Where FP32 is exact too, the three join forms give identical graphs."""
+    X = synth.integer_points(1200, 96, 40, 8)
+    out = {p: knng.build(dev(X), 12, 1.0, 0.001, 15, 8, path=p) for p in ("valu", "mfma", "mfma_i8")}
+    for p in ("mfma", "mfma_i8"):
+        assert torch.equal(out[p][0], out["valu"][0]) and torch.equal(out[p][1], out["valu"][1])
+        assert out[p][2]["changes"] == out["valu"][2]["changes"]
+
+
+@I8_OFF
+def test_integer_form_long_rows(knng):
+    """d = 2000 at span 255: distances reach 1.3e8 > 2^24, stored as the
+    correctly rounded exact value; parity with the FP64 oracle up to ties."""
+    X = synth.integer_points(1000, 2000, 255, 6)
+    ref = oracle.build_graph(X, 10, 1.0, 0.001, 12, 6)
+    ids, dists, st = knng.build(dev(X), 10, 1.0, 0.001, 12, 6, path="auto")
+    assert st["path"] == knng.PATH_MFMA_I8
+    d64 = oracle.list_dists(X, ids.cpu().numpy())
+    assert np.array_equal(dists.cpu().numpy(), d64.astype(np.float32))   # correctly rounded
+    res = check_rows(X, ids.cpu().numpy(), dists.cpu().numpy(), ref.ids, ref.dists)
+    assert res["exact_rows"] >= 1000 - 5
+
+
+@I8_OFF
+def test_integer_form_step_parity(knng):
+    """Load each oracle state G_t (distances recomputed in the integer form),
+    run one iteration, compare with the oracle's G_{t+1} bit for bit."""
+    X = synth.image_like(1500, 3)
+    K = 20
+    r = oracle.build_graph(X, K, 1.0, 0.0, 6, 5, keep_states=True)
+    for s, nxt, e, c in zip(r.states[:-1], r.states[1:], r.evals, r.changes):
+        ctx = knng.Context(dev(X), K, rho=1.0, seed=5, path="mfma_i8")
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        eg, cg = ctx.iterate()
+        assert (eg, cg) == (e, c)
+        g = ctx.export()
+        assert np.array_equal(g.ids.cpu().numpy(), nxt.ids)
+        assert np.array_equal(g.dists.cpu().numpy().astype(np.float64), nxt.dists)
+        ctx.close()
+
+
+@I8_OFF
+def test_integer_form_selection(knng):
+    """AUTO takes the integer form only for qualifying input; an explicit
+    request on other input is refused at create."""
+    base = synth.integer_points(300, 70, 255, 9)
+    _, _, st = knng.build(dev(base), 8, max_iters=2, path="auto")
+    assert st["path"] == knng.PATH_MFMA_I8
+    wide = base.copy()
+    wide[5, 5] = 256.0                      # span 256
+    frac = base.copy()
+    frac[7, 3] = 0.5                        # not an integer
+    big = base + np.float32(2 ** 24)        # span fine, magnitude above 2^24
+    for X in (wide, frac, big):
+        _, _, st = knng.build(dev(X), 8, max_iters=2, path="auto")
+        assert st["path"] == knng.PATH_MFMA
+        with pytest.raises(knng.KnngError) as e:
+            knng.build(dev(X), 8, max_iters=2, path="mfma_i8")
+        assert e.value.status == 1
+    _, _, st = knng.build(dev(base), 8, max_iters=2, path="auto", precision="bf16")
+    assert st["path"] == knng.PATH_MFMA
+    _, _, st = knng.build(dev(base[:, :8]), 8, max_iters=2, path="auto")
+    assert st["path"] == knng.PATH_VALU
 
 
 def test_init_matches_oracle(knng):
@@ -200,7 +289,7 @@ def test_deterministic_repeat(knng):
 
 # ----------------------------------------------------------------- permutation (Sec. 3.2)
 
-@pytest.mark.parametrize("path", ["valu", "mfma"])
+@pytest.mark.parametrize("path", ["valu", "mfma", pytest.param("mfma_i8", marks=I8_OFF)])
 def test_permutation_is_result_invisible_integer(knng, path):
     """Reordering changes storage only: ids, distances, e_t, c_t stay bitwise equal."""
     d = 8 if path == "valu" else 72

@@ -222,6 +222,7 @@ def main():
     ap.add_argument("--reorder", type=int, default=0)
     ap.add_argument("--workload", default="image60k_d784", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "bf16x3"])
     ap.add_argument("--recall-rows", type=int, default=100000,
                     help="query rows for recall (all rows when N is smaller; a seeded sample otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -253,12 +254,12 @@ def main():
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
     p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                         precision=args.precision)
+                         path=args.path, precision=args.precision)
     ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
     ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
     dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
     run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                             workspace=ws, out=(ids, dists), precision=args.precision)
+                             path=args.path, workspace=ws, out=(ids, dists), precision=args.precision)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -286,11 +287,12 @@ def main():
     join_ms = [np.median([s["join_ms"][i] for s in stats]) for i in range(s0["iters"])]
     flops = [e * 2 * w["d"] for e in s0["evals"]]
     achieved = sum(flops) / (sum(join_ms) / 1e3) / 1e12
-    kernel = "k_join_mfma" if s0["path"] == knng.PATH_MFMA else "k_join_valu"
+    kernel = {knng.PATH_MFMA: "k_join_mfma", knng.PATH_MFMA_BF16X3: "k_join_split"}.get(s0["path"], "k_join_valu")
     if args.precision == "bf16":
         kernel = "k_join_bf16"
     traffic = traffic_record(kernel)
-    peak = PEAK_BF16_MFMA_TFLOPS if args.precision == "bf16" else PEAK_FP32_MFMA_TFLOPS
+    # a contraction is priced at the peak of the instructions it runs on
+    peak = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kernel,
             "avg_launch_ms": round(sum(join_ms) / len(join_ms), 4),
@@ -308,7 +310,7 @@ def main():
                                                                                 replace=False))).to(dev)
         tau = exact_kth(X, w["K"], rows)
         ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                           precision=args.precision)
+                           path=args.path, precision=args.precision)
         ctx.init()
         curve = []
         for t in range(1, s0["iters"] + 1):
@@ -329,11 +331,11 @@ def main():
     out = {
         "metric": "distance evals/sec", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32" if args.precision == "bf16" else "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": {"k_join_bf16": "bf16+f32", "k_join_split": "bf16x3+f32"}.get(kernel, "f32"),
         "data": "synthetic",
         "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
-                   "reorder": bool(args.reorder), "path": "mfma" if s0["path"] == knng.PATH_MFMA else "valu",
+                   "reorder": bool(args.reorder), "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
                    "precision": args.precision},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
         "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),

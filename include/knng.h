@@ -56,8 +56,9 @@ typedef enum {
 
 /*
  * Join paths. AUTO takes the VALU direct form when d < 64 or ceil(rho*K) > 32,
- * else the MFMA Gram form; on the MFMA side it would take the exact integer
- * form when X qualifies (FP32 precision only; checked on the device at create).
+ * else (FP32 precision) the split-BF16 Gram form below; on the MFMA side it
+ * would take the exact integer form when X qualifies (checked on the device
+ * at create).
  *
  * Exact integer form (KNNG_PATH_MFMA_I8). X qualifies when every value is an
  * integer of magnitude <= 2^24 and max(X) - min(X) <= 255 over the whole input
@@ -74,11 +75,24 @@ typedef enum {
  * with KNNG_EINVAL (at knng_workspace_bytes and knng_create) and AUTO never
  * selects it.
  */
+/*
+ * Split-BF16 Gram form (KNNG_PATH_MFMA_BF16X3, what AUTO takes on the MFMA
+ * side in FP32 precision). Every FP32 value is written exactly as the sum of
+ * three BF16 values, x = x1 + x2 + x3 (x1 = bf16(x), x2 = bf16(x - x1),
+ * x3 = x - x1 - x2; Henry, Tang, Heinecke, "Leveraging the bfloat16 artificial
+ * intelligence datatype for higher-precision computations", ARITH 2019), and
+ * x.y is accumulated in FP32 on BF16 MFMA tiles from the six products
+ * xi*yj with i + j <= 4 (each exact in FP32). The three dropped products are
+ * below 2^-25 |x_k y_k| per term, so the distance keeps the error bound of the
+ * FP32 Gram form; where X holds integers of magnitude <= 256 with partial sums
+ * below 2^24 it is exact and bit-identical to the other forms.
+ */
 typedef enum {
-    KNNG_PATH_AUTO = 0,     /* see above */
-    KNNG_PATH_VALU = 1,     /* sum_j (x_j - y_j)^2 on the vector ALUs */
-    KNNG_PATH_MFMA = 2,     /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
-    KNNG_PATH_MFMA_I8 = 3   /* exact integer form: int8 MFMA tiles, int32 accumulation */
+    KNNG_PATH_AUTO = 0,         /* see above */
+    KNNG_PATH_VALU = 1,         /* sum_j (x_j - y_j)^2 on the vector ALUs */
+    KNNG_PATH_MFMA = 2,         /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
+    KNNG_PATH_MFMA_I8 = 3,      /* exact integer form: int8 MFMA tiles, int32 accumulation */
+    KNNG_PATH_MFMA_BF16X3 = 4   /* split-BF16 Gram form on BF16 MFMA tiles, FP32 accumulation */
 } knng_path;
 
 typedef struct {

@@ -19,13 +19,14 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["build", "Context", "Params", "workspace_bytes", "sample_cap", "KnngError", "LIB_PATH",
-           "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "PATH_MFMA_I8", "MAX_ITERS", "lib"]
+           "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "PATH_MFMA_I8", "PATH_MFMA_BF16X3", "MAX_ITERS", "lib"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknng.so")
 
-PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_I8 = 0, 1, 2, 3
-_PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_i8": PATH_MFMA_I8}
+PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_I8, PATH_MFMA_BF16X3 = 0, 1, 2, 3, 4
+_PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_i8": PATH_MFMA_I8,
+          "bf16x3": PATH_MFMA_BF16X3}
 MAX_ITERS = 64
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV = 0, 1, 2, 3, 4

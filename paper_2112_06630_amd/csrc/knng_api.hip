@@ -61,13 +61,14 @@ struct Plan {
     int bf16;        // BF16-screened precision form
     int dp;
     int dpi;         // int8 row length of the exact integer form
+    int split;       // split-BF16 copies of the rows
     int C;
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_ppos, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
-        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2;
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2, o_Xs, o_Xs2;
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -81,7 +82,7 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (p->max_iters < 0 || p->max_iters > KNNG_MAX_ITERS)
         return fail(KNNG_EINVAL, "max_iters must be in [0, 64]");
     if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
-    if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_I8) return fail(KNNG_EINVAL, "unknown path");
+    if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_BF16X3) return fail(KNNG_EINVAL, "unknown path");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
     return KNNG_OK;
 }
@@ -109,18 +110,21 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
         path = KNNG_PATH_MFMA;
     }
     if (P.bf16) {
-        if (path == KNNG_PATH_VALU) return fail(KNNG_EINVAL, "the BF16-screened form runs on the MFMA path");
+        if (path == KNNG_PATH_VALU || path == KNNG_PATH_MFMA_BF16X3)
+            return fail(KNNG_EINVAL, "the BF16-screened form runs on the FP32 MFMA path");
         path = KNNG_PATH_MFMA;
     }
     if (path == KNNG_PATH_AUTO) {
-        path = (d >= 64 && 2 * P.C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
-        if (path == KNNG_PATH_MFMA && !P.bf16 && allow_i8 && d <= kMaxI8Dim) P.want_i8 = 1;
+        path = (d >= 64 && 2 * P.C <= 64) ? (P.bf16 ? KNNG_PATH_MFMA : KNNG_PATH_MFMA_BF16X3) : KNNG_PATH_VALU;
+        if (path == KNNG_PATH_MFMA_BF16X3 && allow_i8 && d <= kMaxI8Dim) P.want_i8 = 1;
     }
-    if (path == KNNG_PATH_MFMA && 2 * P.C > 64) return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
+    if ((path == KNNG_PATH_MFMA || path == KNNG_PATH_MFMA_BF16X3) && 2 * P.C > 64)
+        return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
+    P.split = path == KNNG_PATH_MFMA_BF16X3 ? 1 : 0;
     P.path = path;
     P.dpi = P.want_i8 ? (int)round_up(d, 64) : 0;
     P.reorder = p->reorder ? 1 : 0;
-    P.dp = (int)(path == KNNG_PATH_MFMA ? round_up(d, 32) : round_up(d, 4));
+    P.dp = (int)(path != KNNG_PATH_VALU ? round_up(d, 32) : round_up(d, 4));
     if (path == KNNG_PATH_VALU) {
         Views tv{};
         tv.C = P.C;
@@ -165,6 +169,10 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
             P.o_Xb2 = take((size_t)N * P.dp * 2);
             P.o_nb2 = take((size_t)N * 4);
         }
+    }
+    if (P.split) {
+        P.o_Xs = take((size_t)3 * N * P.dp * 2);
+        if (p->reorder) P.o_Xs2 = take((size_t)3 * N * P.dp * 2);
     }
     if (P.want_i8) {
         P.o_Xi = take((size_t)N * P.dpi);
@@ -250,6 +258,10 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
         v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
         v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
     }
+    if (P.split) {
+        v.Xs = reinterpret_cast<uint16_t*>(b + P.o_Xs);
+        if (P.reorder) v.Xs2 = reinterpret_cast<uint16_t*>(b + P.o_Xs2);
+    }
     v.dpi = P.dpi;
     if (P.want_i8) {   // v.Xi stays null until the create-time check selects the form
         if (P.reorder) {
@@ -330,6 +342,7 @@ knng_status do_permute(knng_ctx* c) {
         std::swap(v.Xi, v.Xi2);
         std::swap(v.ni, v.ni2);
     }
+    if (v.Xs) std::swap(v.Xs, v.Xs2);
     launch_perm_posof(v, s);
     HIP_TRY(hipEventRecord(c->ev[5], s));
     HIP_TRY(hipGetLastError());
@@ -368,6 +381,8 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
         launch_join_bf16(v, s);
     else if (c->plan.path == KNNG_PATH_MFMA_I8)
         launch_join_i8(v, s);
+    else if (c->plan.path == KNNG_PATH_MFMA_BF16X3)
+        launch_join_split(v, s);
     else if (c->plan.path == KNNG_PATH_MFMA)
         launch_join_mfma(v, s);
     else
@@ -410,6 +425,7 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
 
 int dist_mode(const knng_ctx* c) {
     if (c->plan.path == KNNG_PATH_MFMA_I8) return kDistInt8;
+    if (c->plan.path == KNNG_PATH_MFMA_BF16X3) return kDistGram;
     return (c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16) ? kDistGram : kDistDirect;
 }
 
@@ -488,8 +504,10 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
         }
     }
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
+    launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
     launch_pad_rows(dX, c->v, c->stream);
-    if (P.path == KNNG_PATH_MFMA) launch_norms(c->v, c->stream);
+    if (P.path != KNNG_PATH_VALU) launch_norms(c->v, c->stream);
+    if (P.split) launch_make_split(c->v, c->stream);
     if (P.bf16) launch_make_bf16(c->v, c->stream);
     if (hipGetLastError() != hipSuccess || read_counters(c) != KNNG_OK) {
         knng_destroy(c);
@@ -699,6 +717,7 @@ int parse_tuned_path(const std::string& table, int d) {
             const std::string v = item.substr(c + 1);
             if (v == "valu") return KNNG_PATH_VALU;
             if (v == "mfma") return KNNG_PATH_MFMA;
+            if (v == "bf16x3") return KNNG_PATH_MFMA_BF16X3;
         }
         pos = end + 1;
     }
@@ -744,8 +763,8 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
     for (int i = 0; i < n; ++i) {
         const int d = descs[i].d;
         int path = p->path != KNNG_PATH_AUTO ? p->path : parse_tuned_path(tuning, d);
-        if (!path) path = (d >= 64 && 2 * C <= 64) ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
-        const int dp = (int)(path == KNNG_PATH_MFMA ? round_up(d, 32) : round_up(d, 4));
+        if (!path) path = (d >= 64 && 2 * C <= 64) ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
+        const int dp = (int)(path != KNNG_PATH_VALU ? round_up(d, 32) : round_up(d, 4));
         BatchGroup* g = nullptr;
         for (auto& x : groups)
             if (x.dp == dp && x.path == path && x.d == d) g = &x;
@@ -834,9 +853,11 @@ knng_status batch_upload(knng_batch* b, hipStream_t s) {
 void batch_group_setup(const BatchGroup& g, hipStream_t s) {
     const Views& v = g.v;
     launch_fill_u64(v.counters, 0ull, kNumCounters, s);
+    launch_fill_u32(v.nn, 0u, v.N, s);
     launch_batch_setup(v, s);
-    if (g.path == KNNG_PATH_MFMA) launch_norms(v, s);
-    launch_init(v, 0, g.path == KNNG_PATH_MFMA ? kDistGram : kDistDirect, s);
+    if (g.path != KNNG_PATH_VALU) launch_norms(v, s);
+    if (g.path == KNNG_PATH_MFMA_BF16X3) launch_make_split(v, s);
+    launch_init(v, 0, g.path != KNNG_PATH_VALU ? kDistGram : kDistDirect, s);
 }
 
 void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hipStream_t s) {
@@ -848,7 +869,9 @@ void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hip
     launch_rev_scatter(v, 0, t, s);
     launch_select(v, 0, t, s);
     launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
-    if (g.path == KNNG_PATH_MFMA)
+    if (g.path == KNNG_PATH_MFMA_BF16X3)
+        launch_join_split(v, s);
+    else if (g.path == KNNG_PATH_MFMA)
         launch_join_mfma(v, s);
     else
         launch_join_valu(v, s);
@@ -878,10 +901,10 @@ knng_status batch_autotune(knng_batch* b, hipStream_t s) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     for (int d : ds_seen) {
-        int best_path = d >= 64 && 2 * C <= 64 ? KNNG_PATH_MFMA : KNNG_PATH_VALU;
+        int best_path = d >= 64 && 2 * C <= 64 ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
         if (2 * C <= 64) {
             float best_ms = 1e30f;
-            for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA}) {
+            for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA, KNNG_PATH_MFMA_BF16X3}) {
                 knng_batch tb;
                 tb.p = b->p;
                 tb.p.path = path;
@@ -909,7 +932,8 @@ knng_status batch_autotune(knng_batch* b, hipStream_t s) {
             }
         }
         if (!table.empty()) table += ",";
-        table += std::to_string(d) + (best_path == KNNG_PATH_MFMA ? ":mfma" : ":valu");
+        table += std::to_string(d) + (best_path == KNNG_PATH_MFMA ? ":mfma"
+                                      : best_path == KNNG_PATH_MFMA_BF16X3 ? ":bf16x3" : ":valu");
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -923,9 +947,10 @@ extern "C" {
 
 size_t knng_batch_workspace_bytes(const knng_dataset* descs, int32_t n, const knng_params* params) {
     if (batch_validate(descs, n, params) != KNNG_OK) return 0;
-    // room for either join path of every group (the autotuner may pick either)
+    // room for any join path of every group (the autotuner may pick any): the
+    // split form needs the most of each group, so its uniform layout bounds a mix
     size_t best = 0;
-    for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA}) {
+    for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA, KNNG_PATH_MFMA_BF16X3}) {
         knng_params p = *params;
         if (params->path != KNNG_PATH_AUTO && params->path != path) continue;
         p.path = path;

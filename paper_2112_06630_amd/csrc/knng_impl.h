@@ -41,6 +41,7 @@ struct Views {
     float* nrm;         // [N] squared norms (Gram path)
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
     float* nb;          // [N] squared norms of the BF16 rows
+    uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
     int dpi;            // int8 row length (multiple of 64), exact integer form
     int8_t* Xi;         // [N, dpi] rows shifted into int8 (exact integer form), else null
     int32_t* ni;        // [N] squared norms of the int8 rows
@@ -97,6 +98,7 @@ struct Views {
     uint16_t* Xb2;      // [N, dp]
     float* nb2;         // [N]
     int8_t* Xi2;        // [N, dpi]
+    uint16_t* Xs2;      // [3, N, dp]
     int32_t* ni2;       // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
@@ -117,6 +119,8 @@ void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, 
 void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t s);
 void launch_make_i8(const Views& v, int32_t shift, hipStream_t s);
 void launch_join_i8(const Views& v, hipStream_t s);
+void launch_make_split(const Views& v, hipStream_t s);
+void launch_join_split(const Views& v, hipStream_t s);
 void launch_rev_hist(const Views& v, hipStream_t s);
 // batched form
 void launch_batch_setup(const Views& v, hipStream_t s);

@@ -981,8 +981,11 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0,
                 }
             }
         }
-        if (failed) {
-            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
+        if (failed) {   // reported; the owner samples nothing (its join is skipped)
+            if (lane == 0) {
+                atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
+                v.nn[u] = 0u;
+            }
             continue;
         }
         if (nsel) atomicAdd(&v.cap[npos], nnew - 1 + nold);
@@ -1071,7 +1074,11 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
 
 void launch_select(const Views& v, uint64_t st, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
-    if (2 * v.C <= 64)
+    // The threshold search needs a count in [2C, 64]; a member reached by both
+    // routes adds two entries of one weight, so the count can step over a
+    // window narrower than 3 (2C = 64 leaves one value). Caps above 30 take
+    // the rank path.
+    if (2 * v.C <= 60)
         hipLaunchKernelGGL(k_select_large_thr, dim3(grid_for(v.N, kSelLWaves, 4096)), dim3(256), 0, s, v, st, t);
     else
         hipLaunchKernelGGL(k_select_large, dim3(grid_for(v.N, kSelWaves, 4096)), dim3(256), 0, s, v, st, t);
@@ -1152,6 +1159,10 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
+        if (m > C2) {   // not a sampled neighbourhood: reported, never read
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
+            continue;
+        }
         const uint2* cs = v.cand + (size_t)u * C2;
         for (int i = lane; i < m; i += 64) {
             const uint2 c = cs[i];
@@ -1221,6 +1232,10 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
+        if (m > C2) {   // not a sampled neighbourhood: reported, never read
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
+            continue;
+        }
         const uint2* cs = v.cand + (size_t)u * C2;
         if (lane < m) {
             const uint2 c = cs[lane];
@@ -1328,6 +1343,10 @@ __global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
+        if (m > C2) {   // not a sampled neighbourhood: reported, never read
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
+            continue;
+        }
         const uint2* cs = v.cand + (size_t)u * C2;
         if (lane < m) {
             const uint2 c = cs[lane];
@@ -1513,6 +1532,10 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
         if (nnew == 0) continue;
+        if (m > C2) {   // not a sampled neighbourhood: reported, never read
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
+            continue;
+        }
         const uint2* cs = v.cand + (size_t)u * C2;
         if (lane < m) {
             const uint2 c = cs[lane];
@@ -1624,6 +1647,168 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
 
 void launch_join_bf16(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_join_bf16, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+}
+
+// ------------------------------------------------------------------ split-BF16 Gram form
+//
+// x = x1 + x2 + x3 exactly: x1 = bf16(x) (round to nearest even), r1 = x - x1
+// is exact in FP32 and has at most 16 significant bits, x2 = bf16(r1), and
+// r1 - x2 has at most 8 significant bits, so x3 = bf16(r1 - x2) = r1 - x2.
+// x.y = sum_{i,j} xi yj; the tiles accumulate the six products with i + j <= 4
+// (BF16 x BF16 is exact in FP32). The dropped x2y3 + x3y2 + x3y3 is below
+// 2^-25 |x_k y_k| per term (|x2| <= 2^-9 |x|, |x3| <= 2^-17 |x|).
+//
+// Symmetry. A pair is evaluated by several owners, as row or as column, and
+// the merge needs one key per pair. Three accumulators per tile, each taking
+// its two products in a fixed order per 32-dimension step:
+//   S = x2.y2 then x1.y1,   R = x1.y3 then x1.y2,   Q = x3.y1 then x2.y1.
+// Swapping the roles of x and y leaves S unchanged and exchanges R and Q
+// (the same products in the same order), so x.y = S + (R + Q) is the same
+// FP32 value either way.
+
+__global__ void k_make_split(Views v) {
+    const int64_t total = (int64_t)v.N * v.dp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = v.Xp[i];
+        const uint16_t b1 = bf16_rne(x);
+        const float r1 = x - bf16_to_f32(b1);
+        const uint16_t b2 = bf16_rne(r1);
+        const float r2 = r1 - bf16_to_f32(b2);
+        v.Xs[i] = b1;
+        v.Xs[total + i] = b2;
+        v.Xs[2 * total + i] = bf16_rne(r2);
+    }
+}
+
+void launch_make_split(const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_make_split, dim3(grid_for((int64_t)v.N * v.dp, 1024, 16384)), dim3(256), 0, s, v);
+}
+
+// The tiles of k_join_mfma on BF16 MFMA (v_mfma_f32_16x16x32_bf16): lane
+// (c = lane%16, g = lane/16) holds dims [k0 + 8g, k0 + 8g + 8) of member
+// 16*tile + c in each of the three planes; A and B take the same lane-to-k
+// map. Rows are new members only (nnew <= C <= 32: row tiles 0 and 1).
+// Epilogue as in the FP32 kernel.
+// MaxCT column tiles (m = 2C <= 16 MaxCT); rows are new members, nnew <= 32,
+// so row tiles 0 and 1 only: 2 MaxCT - 1 tiles.
+template <int MaxCT>
+__global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v) {
+    constexpr int kSplitTiles = 2 * MaxCT - 1;
+    __shared__ uint64_t s_thr[kJoinWaves][64];
+    __shared__ uint32_t s_oid[kJoinWaves][64];
+    __shared__ uint32_t s_pos[kJoinWaves][64];
+    __shared__ float s_nrm[kJoinWaves][64];
+    __shared__ uint32_t s_emit[kJoinWaves][3][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int C2 = 2 * v.C, dp = v.dp, K = v.K;
+    const size_t plane = (size_t)v.N * dp;
+    const int c16 = lane & 15, g = lane >> 4;
+    EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
+    emit_clear(el, 64);
+    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
+    for (int u = xr.next; u < xr.end; u += xr.step) {
+        const uint32_t nn = v.nn[u];
+        const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
+        if (nnew == 0) continue;
+        if (m > C2) {   // not a sampled neighbourhood: reported, never read
+            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
+            continue;
+        }
+        const uint2* cs = v.cand + (size_t)u * C2;
+        if (lane < m) {
+            const uint2 c = cs[lane];
+            s_oid[w][lane] = c.x;
+            s_pos[w][lane] = c.y;
+            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
+            s_nrm[w][lane] = v.nrm[c.y];
+        }
+        wave_sync();
+        const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
+        // lanes past the last member read member m-1; their outputs are never used
+        const uint16_t* rp[MaxCT];
+#pragma unroll
+        for (int ct = 0; ct < MaxCT; ++ct)
+            rp[ct] = v.Xs + (size_t)s_pos[w][min(ct * 16 + c16, m - 1)] * dp + g * 8;
+        floatx4 aS[kSplitTiles], aR[kSplitTiles], aQ[kSplitTiles];
+#pragma unroll
+        for (int t = 0; t < kSplitTiles; ++t) {
+            aS[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            aR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            aQ[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        for (int k0 = 0; k0 < dp; k0 += 32) {
+            bf16x8 f[3][MaxCT];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int ct = 0; ct < MaxCT; ++ct) {
+                    uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+                    if (ct < CT) raw = *reinterpret_cast<const uint4*>(rp[ct] + q * plane + k0);
+                    f[q][ct] = __builtin_bit_cast(bf16x8, raw);
+                }
+            // product kinds outer, tiles inner: consecutive instructions go to
+            // different accumulators
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                int t = 0;
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = rt; ct < MaxCT; ++ct, ++t) {
+                        if (!(rt < RT && ct < CT)) continue;
+                        switch (q) {
+                            case 0: aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[1][ct], aS[t], 0, 0, 0); break;
+                            case 1: aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[2][ct], aR[t], 0, 0, 0); break;
+                            case 2: aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[2][rt], f[0][ct], aQ[t], 0, 0, 0); break;
+                            case 3: aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[0][ct], aS[t], 0, 0, 0); break;
+                            case 4: aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[1][ct], aR[t], 0, 0, 0); break;
+                            default: aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[0][ct], aQ[t], 0, 0, 0); break;
+                        }
+                    }
+            }
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            int t = 0;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = rt; ct < MaxCT; ++ct, ++t) {
+                    if (!(rt < RT && ct < CT)) continue;
+                    const int j = ct * 16 + c16;
+                    if (j >= m) continue;
+                    const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
+                    const uint64_t tj = s_thr[w][j];
+                    const float nj = s_nrm[w][j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = rt * 16 + g * 4 + r;
+                        if (i >= nnew || (j < nnew && j <= i)) continue;
+                        const float dot = aS[t][r] + (aR[t][r] + aQ[t][r]);
+                        float D = (s_nrm[w][i] + nj) - 2.0f * dot;
+                        D = D > 0.f ? D : 0.f;
+                        const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
+                        const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
+                        if (pass == 0) {
+                            if (ki < s_thr[w][i]) emit_count(el, i);
+                            if (kj < tj) emit_count(el, j);
+                        } else {
+                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki, pj);
+                            if (kj < tj) emit_write(v, el, j, kj, s_pos[w][i]);
+                        }
+                    }
+                }
+            if (pass == 0) emit_reserve(v, el, s_pos[w], m);
+        }
+        wave_sync();
+        emit_clear(el, m);
+    }
+}
+
+void launch_join_split(const Views& v, hipStream_t s) {
+    if (2 * v.C <= 48)
+        hipLaunchKernelGGL(k_join_split<3>, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+    else
+        hipLaunchKernelGGL(k_join_split<4>, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
 }
 
 // ------------------------------------------------------------------ merge (a5)
@@ -1913,7 +2098,7 @@ __global__ void k_export_samples(Views v, int32_t* __restrict__ dnew, int32_t* _
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < v.N; p += gridDim.x * blockDim.x) {
         const int o = v.orig[p];
         const uint32_t nn = v.nn[p];
-        const int a = (int)(nn & 0xffffu), b = (int)(nn >> 16);
+        const int a = min((int)(nn & 0xffffu), C), b = min((int)(nn >> 16), C);   // cand holds 2C
         const uint2* cs = v.cand + (size_t)p * 2 * C;
         for (int i = 0; i < C; ++i) {
             dnew[(size_t)o * C + i] = i < a ? (int32_t)cs[i].x : -1;
@@ -2195,6 +2380,21 @@ __global__ void k_perm_rows_i8(Views v) {
     }
 }
 
+__global__ void k_perm_rows_split(Views v) {
+    const int dp8 = v.dp >> 3;   // 16-byte groups per plane row (dp % 32 == 0)
+    const int64_t per = (int64_t)v.N * dp8, total = 3 * per;
+    const size_t plane = (size_t)v.N * v.dp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(i / per);
+        const int64_t r = i - (int64_t)q * per;
+        const int p = (int)(r / dp8), c = (int)(r - (int64_t)p * dp8);
+        const int np = v.newpos[p];
+        if (np < 0 || np >= v.N) continue;  // reported by k_perm_rows
+        reinterpret_cast<uint4*>(v.Xs2 + q * plane + (size_t)np * v.dp)[c] =
+            reinterpret_cast<const uint4*>(v.Xs + q * plane + (size_t)p * v.dp)[c];
+    }
+}
+
 __global__ void k_perm_lists(Views v) {
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
@@ -2247,6 +2447,9 @@ void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s) {
     if (v.Xb)
         hipLaunchKernelGGL(k_perm_rows_bf16, dim3(grid_for((int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256), 0, s,
                            v);
+    if (v.Xs)
+        hipLaunchKernelGGL(k_perm_rows_split, dim3(grid_for(3 * (int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256),
+                           0, s, v);
     if (v.Xi)
         hipLaunchKernelGGL(k_perm_rows_i8, dim3(grid_for((int64_t)v.N * (v.dpi >> 4), 256, 16384)), dim3(256), 0, s,
                            v);

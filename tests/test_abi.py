@@ -58,7 +58,9 @@ def _params(**kw):
     (100, 8, dict(max_iters=-1), "max_iters"),
     (100, 8, dict(max_iters=65), "max_iters"),
     (100, 784, dict(K=64, rho=1.0, path="mfma"), "MFMA"),
-    (100, 784, dict(path=4), "unknown path"),
+    (100, 784, dict(path=5), "unknown path"),
+    (100, 784, dict(path="bf16x3", precision="bf16"), "FP32 MFMA"),
+    (100, 784, dict(K=64, rho=1.0, path="bf16x3"), "MFMA"),
     (100, 784, dict(path="mfma_i8"), "disabled"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
@@ -100,10 +102,15 @@ def test_workspace_grows_with_size():
 
 
 def test_integer_form_workspace():
-    """The exact integer form is switched off: AUTO reserves no int8 rows."""
+    """The exact integer form is switched off: AUTO reserves no int8 rows; at
+    high d it reserves the three BF16 planes of the split form (3 * N * dp * 2
+    bytes, dp = round_up(d, 32)) on top of the FP32 MFMA layout."""
     import paper_2112_06630_amd as knng
     N, d = 3000, 784
-    assert knng.workspace_bytes(N, d, _params(K=20, path="auto")) == knng.workspace_bytes(N, d, _params(K=20, path="mfma"))
+    au = knng.workspace_bytes(N, d, _params(K=20, path="auto"))
+    assert au == knng.workspace_bytes(N, d, _params(K=20, path="bf16x3"))
+    mf = knng.workspace_bytes(N, d, _params(K=20, path="mfma"))
+    assert 0 <= au - mf - 3 * N * 800 * 2 < 256
     assert knng.workspace_bytes(N, 8, _params(path="auto")) == knng.workspace_bytes(N, 8, _params(path="valu"))
 
 
@@ -113,4 +120,5 @@ def test_header_path_values_match_binding():
     text = open(HDR).read()
     vals = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"(KNNG_PATH_\w+)\s*=\s*(\d+)", text))
     assert vals == {"KNNG_PATH_AUTO": knng.PATH_AUTO, "KNNG_PATH_VALU": knng.PATH_VALU,
-                    "KNNG_PATH_MFMA": knng.PATH_MFMA, "KNNG_PATH_MFMA_I8": knng.PATH_MFMA_I8}
+                    "KNNG_PATH_MFMA": knng.PATH_MFMA, "KNNG_PATH_MFMA_I8": knng.PATH_MFMA_I8,
+                    "KNNG_PATH_MFMA_BF16X3": knng.PATH_MFMA_BF16X3}

@@ -38,12 +38,14 @@ def path_for(d):
     return {16: "valu", 64: "mfma", 128: "valu"}[d]
 
 
-def test_batch_equals_single_builds(knng):
+@pytest.mark.parametrize("table", [TABLE, "16:bf16x3,64:bf16x3,128:bf16x3", "16:mfma,64:valu,128:mfma"])
+def test_batch_equals_single_builds(knng, table):
     data = small_batch(24, 11)
     Xs = [dev(X) for X, _ in data]
     seeds = [s for _, s in data]
-    b = knng.Batch(Xs, seeds, 15, 1.0, 0.001, 30, tuning=TABLE)
-    assert b.tuning == TABLE
+    b = knng.Batch(Xs, seeds, 15, 1.0, 0.001, 30, tuning=table)
+    assert b.tuning == table
+    path_for = lambda d: dict(e.split(":") for e in table.split(","))[str(d)]
     b.execute()
     b.synchronize()
     st = b.stats()
@@ -55,12 +57,13 @@ def test_batch_equals_single_builds(knng):
     b.close()
 
 
-def test_batch_integer_data_matches_oracle(knng):
+@pytest.mark.parametrize("tuning", ["16:valu,64:mfma,128:mfma", "16:valu,64:bf16x3,128:bf16x3"])
+def test_batch_integer_data_matches_oracle(knng, tuning):
     rng = np.random.default_rng(3)
     data = [(synth.integer_points(int(n), int(d), 7, int(s)), int(s))
             for n, d, s in zip(rng.integers(60, 700, 6), [16, 16, 64, 64, 128, 128], rng.integers(0, 1000, 6))]
     Xs = [dev(X) for X, _ in data]
-    b = knng.Batch(Xs, [s for _, s in data], 10, 0.7, 0.001, 20, tuning="16:valu,64:mfma,128:mfma")
+    b = knng.Batch(Xs, [s for _, s in data], 10, 0.7, 0.001, 20, tuning=tuning)
     b.execute()
     b.synchronize()
     st = b.stats()
@@ -102,7 +105,7 @@ def test_batch_autotune_table(knng):
     table = b.tuning
     entries = dict(e.split(":") for e in table.split(","))
     assert set(entries) == {str(X.shape[1]) for X, _ in data}
-    assert set(entries.values()) <= {"valu", "mfma"}
+    assert set(entries.values()) <= {"valu", "mfma", "bf16x3"}
     b.execute()
     b.synchronize()
     for i, (X, s) in enumerate(data):

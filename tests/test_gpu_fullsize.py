@@ -1,8 +1,8 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times.
 
 image60k_d784 (60000 x 784 pixel integers, K=20, rho=1): every distance is an
-exact integer below 2^24 in FP32, so the whole GPU graph, e_t and c_t must
-equal the FP64 oracle's full build bit for bit (about 15 s of oracle on 8
+exact integer below 2^24 in FP32 and in the split-BF16 form, so the whole
+GPU graph, e_t and c_t must equal the FP64 oracle's full build bit for bit (about 15 s of oracle on 8
 host threads).
 
 blobs4m_d3 and aniso200k_d960 are too large for a full oracle build in a test;
@@ -38,14 +38,16 @@ def _dev(X):
     return torch.from_numpy(np.ascontiguousarray(X, np.float32)).to("cuda:0")
 
 
-@pytest.mark.parametrize("reorder", [False, True])
-def test_image60k_bitwise(knng, image60k, reorder):
-    """What the benchmark runs (AUTO: FP32 MFMA Gram tiles), with and without
-    the graph-ordered permutation."""
+@pytest.mark.parametrize("path,reorder,want", [
+    ("auto", False, 4),    # split-BF16 Gram tiles: what the benchmark runs
+    ("auto", True, 4),     # with the graph-ordered permutation
+    ("mfma", False, 2),    # FP32 Gram tiles
+])
+def test_image60k_bitwise(knng, image60k, path, reorder, want):
     X, p, ref = image60k
     ids, dists, st = knng.build(_dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"],
-                                path="auto", reorder=reorder)
-    assert st["path"] == knng.PATH_MFMA
+                                path=path, reorder=reorder)
+    assert st["path"] == want
     assert st["converged"]
     assert st["iters"] == ref.iters
     assert st["evals"] == ref.evals.tolist()
@@ -92,6 +94,6 @@ def test_blobs4m_sampled_rows(knng):
 def test_aniso200k_sampled_rows(knng):
     X, p = synth.config(4)
     ids, dists, st = knng.build(_dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
-    assert st["path"] == 2
+    assert st["path"] == knng.PATH_MFMA_BF16X3
     rows = np.random.default_rng(1).choice(X.shape[0], 128, replace=False)
     _check_sampled(X, ids.cpu().numpy(), dists.cpu().numpy(), rows, p["K"], 960, True, 0.5)

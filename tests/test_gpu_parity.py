@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from parity import check_rows
+from parity import check_rows, fp32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -61,16 +61,89 @@ def test_build_integer_points_bitwise_valu(knng, N, d, K, rho, hi, seed):
     (900, 130, 16, 1.0, 5, 3),
     (400, 33, 12, 0.9, 20, 4),
 ])
-def test_build_integer_points_bitwise_mfma(knng, N, d, K, rho, hi, seed):
-    st = exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 15, seed, path="mfma")
-    assert st["path"] == knng.PATH_MFMA
+@pytest.mark.parametrize("path", ["mfma", "bf16x3"])
+def test_build_integer_points_bitwise_mfma(knng, N, d, K, rho, hi, seed, path):
+    st = exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 15, seed, path=path)
+    assert st["path"] == (knng.PATH_MFMA if path == "mfma" else knng.PATH_MFMA_BF16X3)
 
 
-def test_image_like_subset_bitwise(knng):
-    """784-d 0..255 integer data (image-shaped workload at N=3000): exact in FP32."""
+@pytest.mark.parametrize("path,want", [("auto", 4), ("mfma", 2)])
+def test_image_like_subset_bitwise(knng, path, want):
+    """784-d 0..255 integer data (image-shaped workload at N=3000): exact in
+    FP32 and in the split-BF16 form (x1 = x, x2 = x3 = 0), which AUTO takes."""
     X = synth.image_like(3000, 1)
-    st = exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path="auto")
-    assert st["path"] == knng.PATH_MFMA
+    st = exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path=path)
+    assert st["path"] == want
+
+
+# ----------------------------------------------------------------- split-BF16 Gram form
+
+def _split_case(gen):
+    if gen == "aniso":
+        return synth.anisotropic_clusters(3000, 960, 3, 20), 20, 0.5, 3
+    if gen == "gauss":
+        return synth.gaussian_mixture(4000, 128, 12, 9), 16, 1.0, 9
+    return synth.gaussian_mixture(3000, 96, 10, 10), 32, 1.0, 10
+
+
+@pytest.mark.parametrize("gen", ["aniso", "gauss", "gauss_wide"])
+def test_split_form_step_parity(knng, gen):
+    """Continuous data, one GPU iteration from each oracle state G_t against
+    the oracle's G_{t+1}: ids equal up to near-ties, distances within the FP32
+    Gram-form bound, e_t exact. (Over a whole build an FP32 near-tie decided
+    differently from FP64 changes the later samples, so whole builds are
+    compared by the bound and by recall below.) A pair proposed by several
+    owners must carry one key, else the merge reports a duplicate id: this
+    also checks that the split-form distance is symmetric. gauss_wide has
+    2C = 64 columns (the four-column-tile kernel)."""
+    X, K, rho, seed = _split_case(gen)
+    dpad = (X.shape[1] + 31) // 32 * 32
+    r = oracle.build_graph(X, K, rho, 0.0, 6, seed, keep_states=True)
+    for s, nxt, e in zip(r.states[:-1], r.states[1:], r.evals):
+        ctx = knng.Context(dev(X), K, rho=rho, seed=seed, path="bf16x3")
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        eg, cg = ctx.iterate()
+        assert eg == e
+        g = ctx.export()
+        res = check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), nxt.ids, nxt.dists, dpad=dpad, gram=True)
+        assert res["exact_rows"] >= X.shape[0] - 10, (s.t, res)
+        ctx.close()
+
+
+@pytest.mark.parametrize("gen", ["aniso", "gauss", "gauss_wide"])
+def test_split_form_whole_build(knng, gen):
+    """Whole build: rows valid and sorted, stored distances within the FP32
+    Gram-form bound, recall as the oracle's (within 0.005)."""
+    X, K, rho, seed = _split_case(gen)
+    dpad = (X.shape[1] + 31) // 32 * 32
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, seed, path="auto")
+    assert st["path"] == knng.PATH_MFMA_BF16X3
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    D64, bound = fp32_bound(X, ids, dpad, True)
+    assert (np.abs(dists.astype(np.float64) - D64) <= bound).all()
+    assert all(len(set(r.tolist())) == K for r in ids)
+    assert not (ids == np.arange(X.shape[0])[:, None]).any()
+    assert ((dists[:, 1:] > dists[:, :-1]) | ((dists[:, 1:] == dists[:, :-1]) & (ids[:, 1:] > ids[:, :-1]))).all()
+    ref = oracle.build_graph(X, K, rho, 0.001, 30, seed)
+    ei, ed = oracle.bruteforce(X, K)
+    assert oracle.recall(X, ids, ed) >= oracle.recall(X, ref.ids, ed) - 0.005
+
+
+def test_split_form_wide_exponent_range(knng):
+    """Values spread over many binades (log-uniform magnitudes, random signs):
+    the split must stay exact term by term; step parity as above."""
+    rng = np.random.default_rng(12)
+    X = (rng.choice([-1.0, 1.0], (2500, 96)) * 10.0 ** rng.uniform(-6, 3, (2500, 96))).astype(np.float32)
+    X[:, :8] += rng.integers(0, 5, (2500, 1)).astype(np.float32) * 1000.0   # clustered on a few axes
+    r = oracle.build_graph(X, 12, 1.0, 0.0, 4, 4, keep_states=True)
+    for s, nxt in zip(r.states[:-1], r.states[1:]):
+        ctx = knng.Context(dev(X), 12, rho=1.0, seed=4, path="bf16x3")
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        ctx.iterate()
+        g = ctx.export()
+        res = check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), nxt.ids, nxt.dists, dpad=96, gram=True)
+        assert res["exact_rows"] >= 2500 - 10
+        ctx.close()
 
 
 # ----------------------------------------------------------------- exact integer form (int8 MFMA)
@@ -289,7 +362,7 @@ def test_deterministic_repeat(knng):
 
 # ----------------------------------------------------------------- permutation (Sec. 3.2)
 
-@pytest.mark.parametrize("path", ["valu", "mfma", pytest.param("mfma_i8", marks=I8_OFF)])
+@pytest.mark.parametrize("path", ["valu", "mfma", "bf16x3", pytest.param("mfma_i8", marks=I8_OFF)])
 def test_permutation_is_result_invisible_integer(knng, path):
     """Reordering changes storage only: ids, distances, e_t, c_t stay bitwise equal."""
     d = 8 if path == "valu" else 72

@@ -85,7 +85,11 @@ typedef enum {
  * xi*yj with i + j <= 4 (each exact in FP32). The three dropped products are
  * below 2^-25 |x_k y_k| per term, so the distance keeps the error bound of the
  * FP32 Gram form; where X holds integers of magnitude <= 256 with partial sums
- * below 2^24 it is exact and bit-identical to the other forms.
+ * below 2^24 it is exact and bit-identical to the other forms. When x3 = 0 for
+ * every element of X (values with at most 16 significant bits), or also
+ * x2 = 0 (values exact in BF16, such as 8-bit pixels), the join reads only the
+ * planes that are not all zero and skips the products that are exactly zero:
+ * the result is bit-identical to the three-plane evaluation (stats.planes).
  */
 typedef enum {
     KNNG_PATH_AUTO = 0,         /* see above */
@@ -116,7 +120,7 @@ typedef struct {
     int32_t path;                         /* path used (knng_path, resolved) */
     int32_t dpad;                         /* padded row length in floats */
     int32_t precision;                    /* knng_precision used */
-    int32_t reserved;
+    int32_t planes;                       /* split-BF16 form: BF16 planes the join reads (1..3), else 0 */
     int64_t evals[KNNG_MAX_ITERS];        /* e_t: distance evaluations of iteration t */
     int64_t changes[KNNG_MAX_ITERS];      /* c_t: ids that entered a list */
     int64_t proposals[KNNG_MAX_ITERS];    /* proposals that passed the snapshot filter */

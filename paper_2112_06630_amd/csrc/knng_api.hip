@@ -258,6 +258,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
         v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
         v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
     }
+    v.planes = 3;   // until the create-time count (single builds)
     if (P.split) {
         v.Xs = reinterpret_cast<uint16_t*>(b + P.o_Xs);
         if (P.reorder) v.Xs2 = reinterpret_cast<uint16_t*>(b + P.o_Xs2);
@@ -516,6 +517,11 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     if (c->hc[kCntNonFinite]) {
         knng_destroy(c);
         return fail(KNNG_EINVAL, "X holds a NaN or an infinity");
+    }
+    if (P.split) {
+        const uint64_t used = c->hc[kCntSplit];
+        c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
+        c->stats.planes = c->v.planes;
     }
     if (P.want_i8) {
         knng_status is = select_int8(c);

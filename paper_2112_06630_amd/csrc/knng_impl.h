@@ -18,6 +18,7 @@ enum Counter : int {
     kCntPairs2 = 2,      // 2 * e_t (sum of per-target proposal capacities)
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
+    kCntSplit = 5,       // split-BF16 copies: bit 0 some x2 != 0, bit 1 some x3 != 0
     kCntHubs = 6,        // targets whose proposal bucket is merged by a workgroup
     kCntRescored = 7,    // precision form: pairs that passed the BF16 screen and were rescored
     kNumCounters = 8
@@ -42,6 +43,7 @@ struct Views {
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
     float* nb;          // [N] squared norms of the BF16 rows
     uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
+    int planes;         // split form: leading planes the join reads (1..3; the rest are all zero)
     int dpi;            // int8 row length (multiple of 64), exact integer form
     int8_t* Xi;         // [N, dpi] rows shifted into int8 (exact integer form), else null
     int32_t* ni;        // [N] squared norms of the int8 rows

@@ -1666,18 +1666,27 @@ void launch_join_bf16(const Views& v, hipStream_t s) {
 // (the same products in the same order), so x.y = S + (R + Q) is the same
 // FP32 value either way.
 
+// Also records which planes hold a nonzero value (counter kCntSplit; one
+// atomic per wave): planes that are all zero contribute exact zeros and the
+// join skips them.
 __global__ void k_make_split(Views v) {
     const int64_t total = (int64_t)v.N * v.dp;
+    uint32_t used = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const float x = v.Xp[i];
         const uint16_t b1 = bf16_rne(x);
         const float r1 = x - bf16_to_f32(b1);
         const uint16_t b2 = bf16_rne(r1);
         const float r2 = r1 - bf16_to_f32(b2);
+        const uint16_t b3 = bf16_rne(r2);
         v.Xs[i] = b1;
         v.Xs[total + i] = b2;
-        v.Xs[2 * total + i] = bf16_rne(r2);
+        v.Xs[2 * total + i] = b3;
+        used |= (b2 ? 1u : 0u) | (b3 ? 2u : 0u);
     }
+    const uint64_t m1 = ballot((used & 1u) != 0), m2 = ballot((used & 2u) != 0);
+    const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u);
+    if (lane_id() == 0 && wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
 }
 
 void launch_make_split(const Views& v, hipStream_t s) {
@@ -1691,7 +1700,7 @@ void launch_make_split(const Views& v, hipStream_t s) {
 // Epilogue as in the FP32 kernel.
 // MaxCT column tiles (m = 2C <= 16 MaxCT); rows are new members, nnew <= 32,
 // so row tiles 0 and 1 only: 2 MaxCT - 1 tiles.
-template <int MaxCT>
+template <int MaxCT, int Planes>
 __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v) {
     constexpr int kSplitTiles = 2 * MaxCT - 1;
     __shared__ uint64_t s_thr[kJoinWaves][64];
@@ -1737,9 +1746,9 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
             aQ[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
         for (int k0 = 0; k0 < dp; k0 += 32) {
-            bf16x8 f[3][MaxCT];
+            bf16x8 f[Planes][MaxCT];
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
+            for (int q = 0; q < Planes; ++q)
 #pragma unroll
                 for (int ct = 0; ct < MaxCT; ++ct) {
                     uint4 raw = make_uint4(0u, 0u, 0u, 0u);
@@ -1756,14 +1765,17 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
 #pragma unroll
                     for (int ct = rt; ct < MaxCT; ++ct, ++t) {
                         if (!(rt < RT && ct < CT)) continue;
-                        switch (q) {
-                            case 0: aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[1][ct], aS[t], 0, 0, 0); break;
-                            case 1: aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[2][ct], aR[t], 0, 0, 0); break;
-                            case 2: aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[2][rt], f[0][ct], aQ[t], 0, 0, 0); break;
-                            case 3: aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[0][ct], aS[t], 0, 0, 0); break;
-                            case 4: aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[1][ct], aR[t], 0, 0, 0); break;
-                            default: aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[0][ct], aQ[t], 0, 0, 0); break;
+                        // products with an all-zero plane are exact zeros: skipped
+                        if constexpr (Planes >= 2) {
+                            if (q == 0) aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[1][ct], aS[t], 0, 0, 0);
+                            if (q == 4) aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[1][ct], aR[t], 0, 0, 0);
+                            if (q == 5) aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[1][rt], f[0][ct], aQ[t], 0, 0, 0);
                         }
+                        if constexpr (Planes >= 3) {
+                            if (q == 1) aR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[2][ct], aR[t], 0, 0, 0);
+                            if (q == 2) aQ[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[2][rt], f[0][ct], aQ[t], 0, 0, 0);
+                        }
+                        if (q == 3) aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[0][ct], aS[t], 0, 0, 0);
                     }
             }
         }
@@ -1783,7 +1795,7 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
                     for (int r = 0; r < 4; ++r) {
                         const int i = rt * 16 + g * 4 + r;
                         if (i >= nnew || (j < nnew && j <= i)) continue;
-                        const float dot = aS[t][r] + (aR[t][r] + aQ[t][r]);
+                        const float dot = Planes == 1 ? aS[t][r] + 0.0f : aS[t][r] + (aR[t][r] + aQ[t][r]);
                         float D = (s_nrm[w][i] + nj) - 2.0f * dot;
                         D = D > 0.f ? D : 0.f;
                         const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
@@ -1804,11 +1816,22 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
     }
 }
 
+template <int MaxCT>
+static void launch_join_split_ct(const Views& v, hipStream_t s) {
+    const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
+    if (v.planes == 1)
+        hipLaunchKernelGGL((k_join_split<MaxCT, 1>), g, dim3(256), 0, s, v);
+    else if (v.planes == 2)
+        hipLaunchKernelGGL((k_join_split<MaxCT, 2>), g, dim3(256), 0, s, v);
+    else
+        hipLaunchKernelGGL((k_join_split<MaxCT, 3>), g, dim3(256), 0, s, v);
+}
+
 void launch_join_split(const Views& v, hipStream_t s) {
     if (2 * v.C <= 48)
-        hipLaunchKernelGGL(k_join_split<3>, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+        launch_join_split_ct<3>(v, s);
     else
-        hipLaunchKernelGGL(k_join_split<4>, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+        launch_join_split_ct<4>(v, s);
 }
 
 // ------------------------------------------------------------------ merge (a5)

@@ -74,6 +74,35 @@ def test_image_like_subset_bitwise(knng, path, want):
     X = synth.image_like(3000, 1)
     st = exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path=path)
     assert st["path"] == want
+    assert st["planes"] == (1 if want == 4 else 0)   # pixels are exact in BF16: one plane
+
+
+@pytest.mark.parametrize("bits,planes", [(8, 1), (12, 2), (16, 2), (24, 3)])
+def test_split_plane_count(knng, bits, planes):
+    """Values with at most 8 significant bits need one BF16 plane, at most 16
+    two, else three: the join reads only planes that are not all zero."""
+    rng = np.random.default_rng(bits)
+    X = rng.integers(0, 2 ** bits, (300, 64)).astype(np.float32)
+    _, _, st = knng.build(dev(X), 8, max_iters=2, path="bf16x3")
+    assert st["planes"] == planes
+
+
+def test_split_two_planes_step_parity(knng):
+    """12-bit integers (two planes; FP32 sums round above 2^24): one GPU
+    iteration per oracle state, tie-aware parity with the Gram-form bound."""
+    X = np.random.default_rng(13).integers(0, 4096, (2000, 80)).astype(np.float32)
+    X[:1000] += 2048.0 * (np.arange(80) % 3 == 0)   # two coarse groups
+    r = oracle.build_graph(X, 12, 1.0, 0.0, 5, 2, keep_states=True)
+    for s, nxt, e in zip(r.states[:-1], r.states[1:], r.evals):
+        ctx = knng.Context(dev(X), 12, rho=1.0, seed=2, path="bf16x3")
+        assert ctx.stats()["planes"] == 2
+        ctx.load(torch.from_numpy(s.ids), torch.from_numpy(s.flags), s.t)
+        eg, _ = ctx.iterate()
+        assert eg == e
+        g = ctx.export()
+        res = check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), nxt.ids, nxt.dists, dpad=96, gram=True)
+        assert res["exact_rows"] >= 2000 - 10
+        ctx.close()
 
 
 # ----------------------------------------------------------------- split-BF16 Gram form

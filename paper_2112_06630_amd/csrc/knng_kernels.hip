@@ -143,24 +143,6 @@ __device__ __forceinline__ float dist_direct(const float* __restrict__ a, const 
     return (s0 + s1) + (s2 + s3);
 }
 
-// Gram form ||a||^2 + ||b||^2 - 2 a.b with the dot product in the same
-// four-partial-sum order; clamped at +0.
-__device__ __forceinline__ float dist_gram_valu(const float* __restrict__ a, const float* __restrict__ b,
-                                                int dp, float na, float nb) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    for (int j = 0; j < dp; j += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a + j);
-        const float4 y = *reinterpret_cast<const float4*>(b + j);
-        s0 = fmaf(x.x, y.x, s0);
-        s1 = fmaf(x.y, y.y, s1);
-        s2 = fmaf(x.z, y.z, s2);
-        s3 = fmaf(x.w, y.w, s3);
-    }
-    const float dot = (s0 + s1) + (s2 + s3);
-    const float D = (na + nb) - 2.0f * dot;
-    return D > 0.f ? D : 0.f;
-}
-
 // Exact integer form: int32 Gram form of two int8 rows (dpi % 16 == 0) with
 // four-way int8 dot products. Every term is exact, so the value is the exact
 // squared distance and its conversion the correctly rounded FP32 distance.
@@ -369,20 +351,80 @@ void launch_make_i8(const Views& v, int32_t shift, hipStream_t s) {
 
 constexpr int kRowWaves = 4;
 
+// 16-byte chunk c of a row as four or eight values, and their dot product
+// with another chunk (FP32 products and sums in a fixed order).
+__device__ __forceinline__ float chunk_dot(const float4 a, const float4 b, float s) {
+    s = fmaf(a.x, b.x, s);
+    s = fmaf(a.y, b.y, s);
+    s = fmaf(a.z, b.z, s);
+    return fmaf(a.w, b.w, s);
+}
+
+__device__ __forceinline__ float chunk_dot(const uint4 a, const uint4 b, float s) {
+    const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s = fmaf(__uint_as_float(av[q] << 16), __uint_as_float(bv[q] << 16), s);
+        s = fmaf(__uint_as_float(av[q] & 0xffff0000u), __uint_as_float(bv[q] & 0xffff0000u), s);
+    }
+    return s;
+}
+
+// Gram-form distances of row u to the K rows pid (lane k < K holds pid of
+// neighbour k), the wave streaming each row: lane l takes 16-byte chunks
+// l, l + 64, ..., four rows at a time; each row's lane sums are added by a
+// fixed xor tree. Returns lane k's distance. T = float4 (FP32 rows) or uint4
+// (one-plane BF16 rows, exact products).
+template <typename T>
+__device__ __forceinline__ float wave_gram_dists(const T* __restrict__ rows, int chunks, int u, uint32_t pid, int K,
+                                                 const float* __restrict__ nrm) {
+    const int lane = lane_id();
+    const T* a = rows + (size_t)u * chunks;
+    float mine = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const T* b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * chunks;
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int c = lane; c < chunks; c += 64) {
+            const T x = a[c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = chunk_dot(x, b[q][c], s[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o);
+            if (lane == k0 + q) {
+                const float D = (nrm[u] + nrm[pid]) - 2.0f * s[q];
+                mine = D > 0.f ? D : 0.f;
+            }
+        }
+    }
+    return mine;
+}
+
 // Lanes < K hold one entry each (position `pid` of the neighbour, NEW flag in
 // pf). Computes D against row u, ranks the K keys and writes the sorted row.
 __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, uint32_t pf, int mode) {
     const int lane = lane_id();
     const int K = v.K;
     uint64_t key = ~0ull;
+    float Dg = 0.f;
+    if (mode == kDistGram) {   // whole wave
+        if (v.Xs && v.planes == 1)
+            Dg = wave_gram_dists(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, u, pid, K, v.nrm);
+        else
+            Dg = wave_gram_dists(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, u, pid, K, v.nrm);
+    }
     if (lane < K) {
         float D;
         if (mode == kDistInt8) {
             D = dist_int8(v.Xi + (size_t)u * v.dpi, v.Xi + (size_t)pid * v.dpi, v.dpi, v.ni[u], v.ni[pid]);
+        } else if (mode == kDistGram) {
+            D = Dg;
         } else {
-            const float* a = v.Xp + (size_t)u * v.dp;
-            const float* b = v.Xp + (size_t)pid * v.dp;
-            D = mode == kDistGram ? dist_gram_valu(a, b, v.dp, v.nrm[u], v.nrm[pid]) : dist_direct(a, b, v.dp);
+            D = dist_direct(v.Xp + (size_t)u * v.dp, v.Xp + (size_t)pid * v.dp, v.dp);
         }
         key = key_of(D, (uint32_t)v.orig[pid]);
     }

@@ -7,8 +7,10 @@ intensities 0..255 (~80% zeros), K=20, rho=1, delta=0.001, seed 1, at most
 
 Prints one JSON line: evals/s (sum of e_t over the build / build time), the
 time to tie-aware recall 0.99, the roofline of the local-join kernel (its
-algorithmic flops e_t * 2d per launch over its event-timed duration), and the
-FP64 oracle timed on a bounded sample on the host cores.
+algorithmic bytes per launch -- member rows gathered per owner without reuse,
+member metadata and emitted proposals -- over its event-timed average launch,
+against HBM; its MFMA flop rate e_t * 2d beside it), and the FP64 oracle timed
+on a bounded sample on the host cores.
 """
 import argparse
 import hashlib
@@ -107,6 +109,26 @@ def traffic_record(kernel: str):
     return rec.get("bytes_per_launch")
 
 
+def member_counts_and_graphs(X, w, args, iters, keep_graphs):
+    """Replays the build through the step API (deterministic: the same
+    trajectory as the timed builds): per iteration, the members gathered by
+    the join (sum over owners with a new member of n_new + n_old) and, if
+    asked, the graph G_t."""
+    import paper_2112_06630_amd as knng
+    ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+                       path=args.path, precision=args.precision)
+    ctx.init()
+    members, graphs = [], []
+    for _ in range(iters):
+        ctx.iterate()
+        cnt = ctx.samples()[2].long()
+        members.append(int((cnt.sum(1) * (cnt[:, 0] > 0)).sum().item()))
+        if keep_graphs:
+            graphs.append(ctx.export().ids)
+    ctx.close()
+    return members, graphs
+
+
 def bench_batch(args, w):
     """512 independent datasets in one captured graph vs 512 sequential builds."""
     import numpy as np
@@ -185,7 +207,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
         for r in rows:
             if r.get("Counter_Name", counter) != counter:
                 continue
-            name = r["Kernel_Name"].split("(")[0].replace("knng::", "")
+            name = r["Kernel_Name"].split("(")[0].replace("knng::", "").replace("void ", "").split("<")[0]
             kib = float(r["Counter_Value"])
             if "copyBuffer" in name and int(r["Grid_Size"]) >= (copy_mib << 7):
                 probe = kib
@@ -282,23 +304,37 @@ def main():
         assert s["evals"] == stats[0]["evals"] and s["changes"] == stats[0]["changes"], "non-deterministic build"
     value = evals / (ms_per_step / 1e3)
 
-    # local-join roofline: algorithmic flops e_t * 2d per launch / event-timed duration
+    # local-join roofline. The join gathers the member rows of every owner
+    # with a new member: its algorithmic bytes per launch (no reuse across
+    # owners) are sum_u m_u * (row bytes + 20 B of member metadata: sample
+    # entry 8, snapshot K-th key 8, norm 4) + 12 B per emitted proposal (key 8,
+    # source 4). Row bytes: 2 d_pad per BF16 plane read (split form), 4 d_pad
+    # for FP32 rows. m_u per iteration comes from the step API, which replays
+    # the same deterministic trajectory (untimed).
     s0 = stats[len(stats) // 2]
-    join_ms = [np.median([s["join_ms"][i] for s in stats]) for i in range(s0["iters"])]
+    join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
     flops = [e * 2 * w["d"] for e in s0["evals"]]
-    achieved = sum(flops) / (sum(join_ms) / 1e3) / 1e12
     kernel = {knng.PATH_MFMA: "k_join_mfma", knng.PATH_MFMA_BF16X3: "k_join_split"}.get(s0["path"], "k_join_valu")
     if args.precision == "bf16":
         kernel = "k_join_bf16"
+    row_bytes = {"k_join_split": 2 * s0["dpad"] * max(1, s0["planes"]), "k_join_bf16": 2 * s0["dpad"]}.get(
+        kernel, 4 * s0["dpad"])
+    members, curve_ids = member_counts_and_graphs(X, w, args, s0["iters"], not args.no_recall)
+    jbytes = [m * (row_bytes + 20) + 12 * pr for m, pr in zip(members, s0["proposals"])]
+    achieved_bw = sum(jbytes) / (sum(join_ms) / 1e3) / 1e9
+    achieved_fl = sum(flops) / (sum(join_ms) / 1e3) / 1e12
     traffic = traffic_record(kernel)
-    # a contraction is priced at the peak of the instructions it runs on
-    peak = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kernel,
+    # the contraction itself, priced at the peak of the instructions it runs on (context)
+    peak_fl = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
+    roof = {"bound": "hbm", "achieved": round(achieved_bw, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved_bw / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel,
             "avg_launch_ms": round(sum(join_ms) / len(join_ms), 4),
-            "flops_per_launch": int(sum(flops) / len(flops))}
+            "bytes_per_launch": int(sum(jbytes) / len(jbytes)),
+            "members_per_launch": int(sum(members) / len(members)),
+            "mfma": {"achieved": round(achieved_fl, 3), "peak": peak_fl, "unit": "TFLOP/s",
+                     "frac": round(achieved_fl / peak_fl, 4), "flops_per_launch": int(sum(flops) / len(flops))}}
 
-    # time to recall 0.99: per-iteration graphs from the step API (same deterministic trajectory)
+    # time to recall 0.99: per-iteration graphs from the same step-API replay
     rec = None
     t99 = None
     if not args.no_recall:
@@ -309,15 +345,7 @@ def main():
             rows = torch.from_numpy(np.sort(np.random.default_rng(12345).choice(N, args.recall_rows,
                                                                                 replace=False))).to(dev)
         tau = exact_kth(X, w["K"], rows)
-        ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                           path=args.path, precision=args.precision)
-        ctx.init()
-        curve = []
-        for t in range(1, s0["iters"] + 1):
-            ctx.iterate()
-            r = recall_of(X, ctx.export().ids, tau, rows)
-            curve.append(r)
-        ctx.close()
+        curve = [recall_of(X, ids_t, tau, rows) for ids_t in curve_ids]
         rec = curve[-1]
         cum = s0["init_ms"] + s0["reorder_ms"]
         for t, r in enumerate(curve):

@@ -67,7 +67,7 @@ struct Plan {
     size_t total;
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
-        o_pkey, o_ppos, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
+        o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
         o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2, o_Xs, o_Xs2;
 };
 
@@ -158,7 +158,6 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     P.o_hubs = take((size_t)N * 4);
     P.o_poff = take(((size_t)N + 1) * 4);
     P.o_pkey = take((size_t)P.pmax * 8);
-    P.o_ppos = take((size_t)P.pmax * 4);
     P.o_scan = take(scan_tmp_words((int)N) * 4);
     P.o_counters = take(kNumCounters * 8);
     P.o_partial = take(partial_words() * 8);
@@ -230,7 +229,6 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.hubs = reinterpret_cast<uint32_t*>(b + P.o_hubs);
     v.poff = reinterpret_cast<uint32_t*>(b + P.o_poff);
     v.pkey = reinterpret_cast<uint64_t*>(b + P.o_pkey);
-    v.ppos = reinterpret_cast<uint32_t*>(b + P.o_ppos);
     v.scan_tmp = reinterpret_cast<uint32_t*>(b + P.o_scan);
     v.counters = reinterpret_cast<uint64_t*>(b + P.o_counters);
     v.partial = reinterpret_cast<uint64_t*>(b + P.o_partial);

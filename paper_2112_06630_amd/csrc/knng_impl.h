@@ -8,6 +8,7 @@ namespace knng {
 
 constexpr uint32_t kNewBit = 0x80000000u;   // flag bit in a list entry's position word
 constexpr uint32_t kPosMask = 0x7fffffffu;
+constexpr uint32_t kPosUnknown = 0xffffffffu;  // merge: NEW entry whose position is found from its id
 constexpr int kWave = 64;
 constexpr int kSelectStage = 512;           // pool entries a select wave stages in LDS
 
@@ -63,7 +64,6 @@ struct Views {
     uint32_t* poff;     // [N + 1] proposal bucket offsets
     uint32_t* pcnt;     // [N] proposal bucket cursors
     uint64_t* pkey;     // [Pmax] proposal keys
-    uint32_t* ppos;     // [Pmax] proposal source positions
     uint32_t* scan_tmp; // scan scratch
     uint64_t* counters; // [kNumCounters]
     uint64_t* partial;  // [partial_words()] per-block partial sums of the merge

@@ -1154,11 +1154,12 @@ __device__ __forceinline__ void emit_reserve(const Views& v, const EmitLds& e, c
     wave_sync();
 }
 
-__device__ __forceinline__ void emit_write(const Views& v, const EmitLds& e, int t, uint64_t key, uint32_t src) {
+// A proposal is its key alone: the merge finds the source position from the
+// id in the key (only for the few ids that enter a list).
+__device__ __forceinline__ void emit_write(const Views& v, const EmitLds& e, int t, uint64_t key) {
     const uint32_t slot = e.base[t] + atomicAdd(&e.cnt[t], 1u);
     if (slot < e.end[t]) {
         v.pkey[slot] = key;
-        v.ppos[slot] = src;
     } else {
         atomicOr((unsigned long long*)&v.counters[kCntError], 2ull);
     }
@@ -1232,8 +1233,8 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
                     if (ki < thr[i]) emit_count(el, i);
                     if (kj < thr[j]) emit_count(el, j);
                 } else {
-                    if (ki < thr[i]) emit_write(v, el, i, ki, opos[j]);
-                    if (kj < thr[j]) emit_write(v, el, j, kj, opos[i]);
+                    if (ki < thr[i]) emit_write(v, el, i, ki);
+                    if (kj < thr[j]) emit_write(v, el, j, kj);
                 }
             }
             if (pass == 0) emit_reserve(v, el, opos, m);
@@ -1331,7 +1332,7 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
                     if (!(rt < RT && ct < CT)) continue;
                     const int j = ct * 16 + c16;
                     if (j >= m) continue;
-                    const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
+                    const uint32_t oj = s_oid[w][j];
                     const uint64_t tj = s_thr[w][j];
                     const float nj = s_nrm[w][j];
 #pragma unroll
@@ -1346,8 +1347,8 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
                             if (ki < s_thr[w][i]) emit_count(el, i);
                             if (kj < tj) emit_count(el, j);
                         } else {
-                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki, pj);
-                            if (kj < tj) emit_write(v, el, j, kj, s_pos[w][i]);
+                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki);
+                            if (kj < tj) emit_write(v, el, j, kj);
                         }
                     }
                 }
@@ -1448,7 +1449,7 @@ __global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
                     if (!(rt < RT && ct < CT)) continue;
                     const int j = ct * 16 + c16;
                     if (j >= m) continue;
-                    const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
+                    const uint32_t oj = s_oid[w][j];
                     const uint64_t tj = s_thr[w][j];
                     const int32_t nj = s_nrm[w][j];
 #pragma unroll
@@ -1462,8 +1463,8 @@ __global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
                             if (ki < s_thr[w][i]) emit_count(el, i);
                             if (kj < tj) emit_count(el, j);
                         } else {
-                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki, pj);
-                            if (kj < tj) emit_write(v, el, j, kj, s_pos[w][i]);
+                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki);
+                            if (kj < tj) emit_write(v, el, j, kj);
                         }
                     }
                 }
@@ -1675,8 +1676,8 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
                     if (da && ka < s_thr[w][a]) emit_count(el, a);
                     if (db && kbb < s_thr[w][b]) emit_count(el, b);
                 } else {
-                    if (da && ka < s_thr[w][a]) emit_write(v, el, a, ka, s_pos[w][b]);
-                    if (db && kbb < s_thr[w][b]) emit_write(v, el, b, kbb, s_pos[w][a]);
+                    if (da && ka < s_thr[w][a]) emit_write(v, el, a, ka);
+                    if (db && kbb < s_thr[w][b]) emit_write(v, el, b, kbb);
                 }
             }
             if (pass == 0) emit_reserve(v, el, s_pos[w], m);
@@ -1830,7 +1831,7 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
                     if (!(rt < RT && ct < CT)) continue;
                     const int j = ct * 16 + c16;
                     if (j >= m) continue;
-                    const uint32_t oj = s_oid[w][j], pj = s_pos[w][j];
+                    const uint32_t oj = s_oid[w][j];
                     const uint64_t tj = s_thr[w][j];
                     const float nj = s_nrm[w][j];
 #pragma unroll
@@ -1846,8 +1847,8 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
                             if (ki < s_thr[w][i]) emit_count(el, i);
                             if (kj < tj) emit_count(el, j);
                         } else {
-                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki, pj);
-                            if (kj < tj) emit_write(v, el, j, kj, s_pos[w][i]);
+                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki);
+                            if (kj < tj) emit_write(v, el, j, kj);
                         }
                     }
                 }
@@ -1893,26 +1894,18 @@ constexpr int kHubBlocks = 512;
 // which leaves a bitonic sequence holding the 64 smallest keys, sorted again
 // by one half-cleaner pass; equal keys (one id proposed by two owners) are
 // then collapsed through LDS (sk, sp: 64 slots of this wave).
-__device__ void merge_chunks(const uint64_t* pks, const uint32_t* pps, uint32_t c0, uint32_t n, uint32_t stride,
+__device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint32_t stride,
                              int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth, bool& grown,
                              uint64_t* sk, uint32_t* sp) {
     const int lane = lane_id();
     uint64_t nk = ~0ull;
-    uint32_t np = 0;
-    if (c0 + (uint32_t)lane < n) {
-        nk = pks[c0 + lane];
-        np = pps[c0 + lane];
-    }
+    if (c0 + (uint32_t)lane < n) nk = pks[c0 + lane];
     for (; c0 < n; c0 += stride) {
         uint64_t pk = nk;
-        uint32_t pp = np | kNewBit;
+        uint32_t pp = kPosUnknown;   // NEW, position found when the id enters the list
         // next chunk in flight while this one is merged
         nk = ~0ull;
-        np = 0;
-        if (c0 + stride + (uint32_t)lane < n) {
-            nk = pks[c0 + stride + lane];
-            np = pps[c0 + stride + lane];
-        }
+        if (c0 + stride + (uint32_t)lane < n) nk = pks[c0 + stride + lane];
         bool ok = pk < kth;
         if (ballot(ok) == 0) continue;
         const uint32_t pid = (uint32_t)pk;
@@ -1988,9 +1981,16 @@ __device__ void merge_chunks(const uint64_t* pks, const uint32_t* pps, uint32_t 
 
 // Writes a merged row back; checks that no id appears twice (that would
 // mean two different keys for one pair) and counts ids not in the snapshot.
-__device__ __forceinline__ uint64_t finish_merged_row(const Views& v, size_t row, uint64_t key, uint32_t pf,
+// Entries that came from proposals get their position from the id: the
+// dataset's first position plus the id (batched form), else posof.
+__device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uint64_t key, uint32_t pf,
                                                       uint32_t snap) {
     const int lane = lane_id(), K = v.K;
+    const size_t row = (size_t)p * K;
+    if (lane < K && pf == kPosUnknown) {
+        const uint32_t id = (uint32_t)key;
+        pf = (v.ds ? v.dsbase[v.ds[p]] + id : (uint32_t)v.posof[id]) | kNewBit;
+    }
     bool twice = false, entered = lane < K;
     for (int k = 0; k < K; ++k) {
         const uint32_t ik = rl32((uint32_t)key, k);
@@ -2032,8 +2032,8 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
         bool grown = false;
-        merge_chunks(v.pkey + base, v.ppos + base, 0, n, 64, K, snap, key, pf, kth, grown, s_k[w], s_p[w]);
-        changes += finish_merged_row(v, row, key, pf, snap);
+        merge_chunks(v.pkey + base, 0, n, 64, K, snap, key, pf, kth, grown, s_k[w], s_p[w]);
+        changes += finish_merged_row(v, p, key, pf, snap);
         props += n;
     }
     // per-block partial sums (no same-address atomics); summed by k_finish_counters
@@ -2062,7 +2062,6 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
     __shared__ uint64_t s_k[kHubWaves][64];
     __shared__ uint32_t s_p[kHubWaves][64];
     __shared__ uint64_t s_lk[kHubWaves][64];
-    __shared__ uint32_t s_lp[kHubWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
     const int nh = (int)v.counters[kCntHubs];
@@ -2077,16 +2076,16 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
         bool grown = false;
-        merge_chunks(v.pkey + base, v.ppos + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth,
+        merge_chunks(v.pkey + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth,
                      grown, s_k[w], s_p[w]);
         s_lk[w][lane] = key;
-        s_lp[w][lane] = pf & kPosMask;  // merge_chunks marks folded entries NEW again
         __syncthreads();
         if (w == 0) {
-            // partial lists keep their flags: pass them with the NEW bit only where they had it
-            merge_chunks(&s_lk[1][0], &s_lp[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth, grown,
+            // the other partial lists: their snapshot ids are dropped by the fold, so
+            // every entry that gets through came from a proposal (NEW, position by id)
+            merge_chunks(&s_lk[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth, grown,
                          s_k[0], s_p[0]);
-            changes += finish_merged_row(v, row, key, pf, snap);
+            changes += finish_merged_row(v, p, key, pf, snap);
             props += n;
         }
         __syncthreads();

@@ -133,8 +133,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
             return fail(KNNG_EINVAL, "VALU path: 2*C rows of d floats do not fit the LDS stage; use the MFMA path");
     }
     const int64_t C = P.C;
-    const int64_t per_node = C * (C - 1) + 2 * C * C;  // 2 e(u) at most
-    P.pmax = N * per_node;
+    P.pmax = 2 * N * (int64_t)K * (2 * C - 1);   // sum of the bucket bounds (knng_kernels.hip, bucket_lo)
     if (P.pmax >= 0xffffffffLL) return fail(KNNG_EINVAL, "proposal capacity exceeds 2^32 slots");
     size_t off = 0;
     auto take = [&](size_t bytes) {

@@ -16,7 +16,7 @@ constexpr int kSelectStage = 512;           // pool entries a select wave stages
 enum Counter : int {
     kCntChanges = 0,     // c_t
     kCntProposals = 1,   // proposals that passed the snapshot filter
-    kCntPairs2 = 2,      // 2 * e_t (sum of per-target proposal capacities)
+    kCntPairs2 = 2,      // 2 * e_t
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
     kCntSplit = 5,       // split-BF16 copies: bit 0 some x2 != 0, bit 1 some x3 != 0
@@ -60,10 +60,10 @@ struct Views {
     uint32_t* nn;       // [N] n_new | n_old << 16
     uint32_t* big;      // [N] 1: the owner's pool has more than 64 entries
     uint32_t* hubs;     // [N] targets with large proposal buckets
-    uint32_t* cap;      // [N] upper bound of proposals per target
-    uint32_t* poff;     // [N + 1] proposal bucket offsets
-    uint32_t* pcnt;     // [N] proposal bucket cursors
-    uint64_t* pkey;     // [Pmax] proposal keys
+    uint32_t* cap;      // [N] pairs e(u) each owner joins this iteration
+    uint32_t* poff;     // [N + 1] exclusive scan of cap (e_t = poff[N])
+    uint32_t* pcnt;     // [N] proposal bucket cursors (buckets: bucket_lo)
+    uint64_t* pkey;     // [Pmax = 2 N K (2C - 1)] proposal keys, bucketed by target
     uint32_t* scan_tmp; // scan scratch
     uint64_t* counters; // [kNumCounters]
     uint64_t* partial;  // [partial_words()] per-block partial sums of the merge

@@ -122,6 +122,20 @@ __device__ __forceinline__ uint64_t sample_state(const Views& v, int p, uint64_t
     return v.ds ? v.st_table[(size_t)(t - 1) * v.nds + v.ds[p]] : st;
 }
 
+// e(u): pairs an owner joins, new x new and new x old (Sec. 2).
+__device__ __forceinline__ uint32_t owner_pairs(uint32_t nnew, uint32_t nold) {
+    return nnew * (nnew - (nnew ? 1u : 0u)) / 2u + nnew * nold;
+}
+
+// First proposal slot of target p. Only the members of p's pool can sample p
+// (the pool relation is symmetric: p is in pool(u) iff u is in pool(p)); there
+// are at most K + rdeg(p) of them and each proposes to p at most 2C - 1 times
+// (once per pair containing p), so bucket p holds (2C - 1)(K + rdeg(p))
+// slots, and the buckets of positions 0..p-1 hold (2C - 1)(K p + roff[p]).
+__device__ __forceinline__ uint32_t bucket_lo(const Views& v, int p) {
+    return (uint32_t)(2 * v.C - 1) * ((uint32_t)v.K * (uint32_t)p + v.roff[p]);
+}
+
 __device__ __forceinline__ uint64_t key_of(float D, uint32_t id) {
     return ((uint64_t)__float_as_uint(D) << 32) | id;
 }
@@ -843,7 +857,6 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
             if (!(ki >> 63)) {
                 if (rank < (uint32_t)C) {
                     cs[rank] = make_uint2(id, pos);
-                    if (nnew > 0) atomicAdd(&v.cap[pos], nnew - 1 + nold);
                     if (i < nf) v.lpos[(size_t)u * K + L.src[w][i]] = pos;  // flip NEW -> OLD
                 }
             } else {
@@ -851,11 +864,13 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
                 if (ro < (uint32_t)C && !((omask >> ro) & 1ull)) {
                     const uint32_t slot = nnew + ro - (uint32_t)__popcll(omask & ((1ull << ro) - 1ull));
                     cs[slot] = make_uint2(id, pos);
-                    if (nnew > 0) atomicAdd(&v.cap[pos], nnew);
                 }
             }
         }
-        if (lane == 0) v.nn[u] = nnew | (nold << 16);
+        if (lane == 0) {
+            v.nn[u] = nnew | (nold << 16);
+            v.cap[u] = owner_pairs(nnew, nold);
+        }
         wave_sync();
     }
 }
@@ -909,8 +924,6 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0,
         }
         uint32_t newid = 0xffffffffu;  // lane r < nnew: id of the sampled new member of rank r
         uint32_t nnew = 0, nold = 0;
-        bool nsel = false;             // this lane holds a sampled new member (position npos)
-        uint32_t npos = 0;
         uint32_t flip_idx = 0xffffffffu, flip_pos = 0;
         uint2* cs = v.cand + (size_t)u * 2 * C;
         bool failed = false;
@@ -1005,8 +1018,6 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0,
                 wave_sync();
                 newid = s_idx[w][lane];
                 wave_sync();
-                nsel = sel;
-                npos = pos;
             } else {
                 bool innew = false;
                 for (uint32_t k = 0; k < nnew; ++k) {
@@ -1017,22 +1028,22 @@ __global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0,
                 const bool removed = cand_old && innew;
                 const uint64_t mrem = ballot(removed);
                 nold = min(C, (uint32_t)__popcll(mv)) - (uint32_t)__popcll(mrem);
-                if (cand_old && !removed) {
-                    cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
-                    if (nnew > 0) atomicAdd(&v.cap[pos], nnew);
-                }
+                if (cand_old && !removed) cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
             }
         }
         if (failed) {   // reported; the owner samples nothing (its join is skipped)
             if (lane == 0) {
                 atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
                 v.nn[u] = 0u;
+                v.cap[u] = 0u;
             }
             continue;
         }
-        if (nsel) atomicAdd(&v.cap[npos], nnew - 1 + nold);
         if (flip_idx != 0xffffffffu) v.lpos[(size_t)u * K + flip_idx] = flip_pos;
-        if (lane == 0) v.nn[u] = nnew | (nold << 16);
+        if (lane == 0) {
+            v.nn[u] = nnew | (nold << 16);
+            v.cap[u] = owner_pairs(nnew, nold);
+        }
         wave_sync();
     }
 }
@@ -1051,6 +1062,7 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
             if (lane == 0) {
                 v.big[u] = 0u;
                 v.nn[u] = 0u;
+                v.cap[u] = 0u;
             }
             continue;
         }
@@ -1099,18 +1111,15 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
         const uint32_t nold = min(C, (uint32_t)__popcll(mold)) - (uint32_t)__popcll(mrem);
         uint2* cs = v.cand + (size_t)u * 2 * C;
         const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
-        if (seln) {
-            cs[rnew] = make_uint2(id, mpos);
-            atomicAdd(&v.cap[mpos], nnew - 1 + nold);
-        }
-        if (cold && !removed) {
-            cs[nnew + rold - mbcnt(mrem)] = make_uint2(id, mpos);
-            if (nnew > 0) atomicAdd(&v.cap[mpos], nnew);
-        }
+        if (seln) cs[rnew] = make_uint2(id, mpos);
+        if (cold && !removed) cs[nnew + rold - mbcnt(mrem)] = make_uint2(id, mpos);
         // forward NEW entries whose member was sampled new become OLD
         if (real && isnew && idx < (uint32_t)K && (seln || (dup && s1)))
             v.lpos[(size_t)u * K + idx] = mpos;
-        if (lane == 0) v.nn[u] = nnew | (nold << 16);
+        if (lane == 0) {
+            v.nn[u] = nnew | (nold << 16);
+            v.cap[u] = owner_pairs(nnew, nold);
+        }
     }
 }
 
@@ -1147,8 +1156,8 @@ __device__ __forceinline__ void emit_reserve(const Views& v, const EmitLds& e, c
     for (int t = lane_id(); t < m; t += 64) {
         const uint32_t c = e.cnt[t];
         const uint32_t pt = mpos[t];
-        e.base[t] = c ? v.poff[pt] + atomicAdd(&v.pcnt[pt], c) : 0u;
-        e.end[t] = v.poff[pt + 1];
+        e.base[t] = c ? bucket_lo(v, (int)pt) + atomicAdd(&v.pcnt[pt], c) : 0u;
+        e.end[t] = bucket_lo(v, (int)pt + 1);
         e.cnt[t] = 0u;
     }
     wave_sync();
@@ -2016,8 +2025,8 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
     const int K = v.K;
     uint64_t changes = 0, props = 0;
     for (int p = blockIdx.x * kMergeWaves + w; p < v.N; p += gridDim.x * kMergeWaves) {
-        const uint32_t base = v.poff[p];
-        const uint32_t n = min(v.pcnt[p], v.poff[p + 1] - base);
+        const uint32_t base = bucket_lo(v, p);
+        const uint32_t n = min(v.pcnt[p], bucket_lo(v, p + 1) - base);
         if (n == 0) continue;
         if (n > kHubProposals) {
             if (lane == 0) {
@@ -2068,8 +2077,8 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
     uint64_t changes = 0, props = 0;
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         const int p = (int)v.hubs[h];
-        const uint32_t base = v.poff[p];
-        const uint32_t n = min(v.pcnt[p], v.poff[p + 1] - base);
+        const uint32_t base = bucket_lo(v, p);
+        const uint32_t n = min(v.pcnt[p], bucket_lo(v, p + 1) - base);
         const size_t row = (size_t)p * K;
         uint64_t key = lane < K ? v.lkey[row + lane] : ~0ull;
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
@@ -2128,7 +2137,7 @@ __global__ __launch_bounds__(1024) void k_finish_counters(Views v) {
         }
         v.counters[kCntChanges] = sa;
         v.counters[kCntProposals] = sb;
-        v.counters[kCntPairs2] = v.poff[v.N];
+        v.counters[kCntPairs2] = 2ull * v.poff[v.N];
     }
 }
 
@@ -2226,7 +2235,7 @@ __global__ void k_batch_step(Views v, int t, int T_max, int K, double delta) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < v.nds; i += gridDim.x * blockDim.x) {
         if (!v.active[i]) continue;
         const uint32_t b = v.dsbase[i], e = v.dsbase[i + 1];
-        const int64_t ev = (int64_t)(v.poff[e] - v.poff[b]) / 2;
+        const int64_t ev = (int64_t)(v.poff[e] - v.poff[b]);
         const int64_t ch = (int64_t)(v.chgoff[e] - v.chgoff[b]);
         v.ds_stats[((size_t)i * T_max + (t - 1)) * 2] = ev;
         v.ds_stats[((size_t)i * T_max + (t - 1)) * 2 + 1] = ch;

@@ -373,7 +373,6 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
     launch_rev_scatter(v, st, t, s);
     launch_select(v, st, t, s);
-    launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
     if (c->plan.bf16)
         launch_join_bf16(v, s);
@@ -503,9 +502,11 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     }
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
     launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
-    launch_pad_rows(dX, c->v, c->stream);
-    if (P.path != KNNG_PATH_VALU) launch_norms(c->v, c->stream);
-    if (P.split) launch_make_split(c->v, c->stream);
+    if (P.path == KNNG_PATH_VALU) {
+        launch_pad_rows(dX, c->v, c->stream);
+    } else {
+        launch_prep(dX, c->v, P.split, c->stream);
+    }
     if (P.bf16) launch_make_bf16(c->v, c->stream);
     if (hipGetLastError() != hipSuccess || read_counters(c) != KNNG_OK) {
         knng_destroy(c);

@@ -122,6 +122,9 @@ void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t 
 void launch_make_i8(const Views& v, int32_t shift, hipStream_t s);
 void launch_join_i8(const Views& v, hipStream_t s);
 void launch_make_split(const Views& v, hipStream_t s);
+// one pass over X for the MFMA forms: padded rows, norms, identity positions,
+// finiteness check and (split != 0) the split-BF16 planes
+void launch_prep(const float* X, const Views& v, int split, hipStream_t s);
 void launch_join_split(const Views& v, hipStream_t s);
 void launch_rev_hist(const Views& v, hipStream_t s);
 // batched form

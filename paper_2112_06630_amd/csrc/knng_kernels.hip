@@ -174,18 +174,6 @@ __device__ __forceinline__ float dist_int8(const int8_t* __restrict__ a, const i
     return (float)(na + nb - 2 * dot);
 }
 
-__device__ __forceinline__ float sq_norm(const float* __restrict__ a, int dp) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    for (int j = 0; j < dp; j += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a + j);
-        s0 = fmaf(x.x, x.x, s0);
-        s1 = fmaf(x.y, x.y, s1);
-        s2 = fmaf(x.z, x.z, s2);
-        s3 = fmaf(x.w, x.w, s3);
-    }
-    return (s0 + s1) + (s2 + s3);
-}
-
 // q = a / b for 0 <= a < 2^31, 1 <= b, via a double reciprocal and one fix-up.
 __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t b, double rcp) {
     uint32_t q = (uint32_t)((double)a * rcp);
@@ -276,13 +264,30 @@ void launch_pad_rows(const float* X, const Views& v, hipStream_t s) {
                        v.dp, v.Xp, v.orig, v.posof, v.counters);
 }
 
-__global__ void k_norms(const float* __restrict__ Xp, int N, int dp, float* __restrict__ nrm) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < N; r += gridDim.x * blockDim.x)
-        nrm[r] = sq_norm(Xp + (size_t)r * dp, dp);
+// Squared norms of padded rows, one wave per row, in the order k_prep uses
+// (lane sums over j mod 4, then a fixed xor tree): one value per row
+// whichever kernel laid the rows out.
+__global__ __launch_bounds__(256) void k_norms(const float* __restrict__ Xp, int N, int dp, float* __restrict__ nrm) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    for (int r = blockIdx.x * 4 + w; r < N; r += gridDim.x * 4) {
+        const float* y = Xp + (size_t)r * dp;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (int j = 4 * lane; j < dp; j += 256) {
+            const float4 q = *reinterpret_cast<const float4*>(y + j);
+            s0 = fmaf(q.x, q.x, s0);
+            s1 = fmaf(q.y, q.y, s1);
+            s2 = fmaf(q.z, q.z, s2);
+            s3 = fmaf(q.w, q.w, s3);
+        }
+        float sn = (s0 + s1) + (s2 + s3);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o);
+        if (lane == 0) nrm[r] = sn;
+    }
 }
 
 void launch_norms(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_norms, dim3(grid_for(v.N, 256, 8192)), dim3(256), 0, s, v.Xp, v.N, v.dp, v.nrm);
+    hipLaunchKernelGGL(k_norms, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, v.Xp, v.N, v.dp, v.nrm);
 }
 
 // Exact integer form, input check: one pass over X, block-level reduction,
@@ -1745,6 +1750,76 @@ void launch_make_split(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_make_split, dim3(grid_for((int64_t)v.N * v.dp, 1024, 16384)), dim3(256), 0, s, v);
 }
 
+// Layout of the MFMA forms in one pass over X, one wave per row: the padded
+// FP32 row, its squared norm (lane sums over j mod 4, then a fixed xor tree),
+// identity positions, the finiteness check and, for the split form, the three
+// BF16 planes with the used-plane record of k_make_split.
+__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views v, int split) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int d = v.d, dp = v.dp;
+    const int64_t total = (int64_t)v.N * dp;
+    bool bad = false;
+    uint32_t used = 0;
+    for (int r = blockIdx.x * 4 + w; r < v.N; r += gridDim.x * 4) {
+        const float* x = X + (size_t)r * d;
+        float* y = v.Xp + (size_t)r * dp;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (int j = 4 * lane; j < dp; j += 256) {
+            float4 q;
+            q.x = j < d ? x[j] : 0.f;
+            q.y = j + 1 < d ? x[j + 1] : 0.f;
+            q.z = j + 2 < d ? x[j + 2] : 0.f;
+            q.w = j + 3 < d ? x[j + 3] : 0.f;
+            bad |= ((__float_as_uint(q.x) | 0u) & 0x7f800000u) == 0x7f800000u ||
+                   (__float_as_uint(q.y) & 0x7f800000u) == 0x7f800000u ||
+                   (__float_as_uint(q.z) & 0x7f800000u) == 0x7f800000u ||
+                   (__float_as_uint(q.w) & 0x7f800000u) == 0x7f800000u;
+            *reinterpret_cast<float4*>(y + j) = q;
+            s0 = fmaf(q.x, q.x, s0);
+            s1 = fmaf(q.y, q.y, s1);
+            s2 = fmaf(q.z, q.z, s2);
+            s3 = fmaf(q.w, q.w, s3);
+            if (split) {
+                const float e[4] = {q.x, q.y, q.z, q.w};
+                uint16_t b1[4], b2[4], b3[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    b1[c] = bf16_rne(e[c]);
+                    const float r1 = e[c] - bf16_to_f32(b1[c]);
+                    b2[c] = bf16_rne(r1);
+                    b3[c] = bf16_rne(r1 - bf16_to_f32(b2[c]));
+                    used |= (b2[c] ? 1u : 0u) | (b3[c] ? 2u : 0u);
+                }
+                const size_t at = (size_t)r * dp + j;
+                *reinterpret_cast<uint2*>(v.Xs + at) =
+                    make_uint2(b1[0] | ((uint32_t)b1[1] << 16), b1[2] | ((uint32_t)b1[3] << 16));
+                *reinterpret_cast<uint2*>(v.Xs + total + at) =
+                    make_uint2(b2[0] | ((uint32_t)b2[1] << 16), b2[2] | ((uint32_t)b2[3] << 16));
+                *reinterpret_cast<uint2*>(v.Xs + 2 * total + at) =
+                    make_uint2(b3[0] | ((uint32_t)b3[1] << 16), b3[2] | ((uint32_t)b3[3] << 16));
+            }
+        }
+        float sn = (s0 + s1) + (s2 + s3);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o);
+        if (lane == 0) {
+            v.nrm[r] = sn;
+            v.orig[r] = r;
+            v.posof[r] = r;
+        }
+    }
+    const uint64_t m1 = ballot((used & 1u) != 0), m2 = ballot((used & 2u) != 0), mb = ballot(bad);
+    if (lane == 0) {
+        const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u);
+        if (wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
+        if (mb) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
+    }
+}
+
+void launch_prep(const float* X, const Views& v, int split, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, X, v, split);
+}
+
 // The tiles of k_join_mfma on BF16 MFMA (v_mfma_f32_16x16x32_bf16): lane
 // (c = lane%16, g = lane/16) holds dims [k0 + 8g, k0 + 8g + 8) of member
 // 16*tile + c in each of the three planes; A and B take the same lane-to-k
@@ -2023,8 +2098,9 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
     __shared__ uint32_t s_p[kMergeWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
-    uint64_t changes = 0, props = 0;
+    uint64_t changes = 0, props = 0, pairs = 0;
     for (int p = blockIdx.x * kMergeWaves + w; p < v.N; p += gridDim.x * kMergeWaves) {
+        pairs += v.cap[p];   // e(u) of owner p: e_t without a scan
         const uint32_t base = bucket_lo(v, p);
         const uint32_t n = min(v.pcnt[p], bucket_lo(v, p + 1) - base);
         if (n == 0) continue;
@@ -2046,20 +2122,23 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         props += n;
     }
     // per-block partial sums (no same-address atomics); summed by k_finish_counters
-    __shared__ uint64_t s_red[kMergeWaves][2];
+    __shared__ uint64_t s_red[kMergeWaves][3];
     if (lane == 0) {
         s_red[w][0] = changes;
         s_red[w][1] = props;
+        s_red[w][2] = pairs;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t a = 0, b = 0;
+        uint64_t a = 0, b = 0, c = 0;
         for (int i = 0; i < kMergeWaves; ++i) {
             a += s_red[i][0];
             b += s_red[i][1];
+            c += s_red[i][2];
         }
-        v.partial[2 * blockIdx.x] = a;
-        v.partial[2 * blockIdx.x + 1] = b;
+        v.partial[3 * blockIdx.x] = a;
+        v.partial[3 * blockIdx.x + 1] = b;
+        v.partial[3 * blockIdx.x + 2] = c;
     }
 }
 
@@ -2100,8 +2179,9 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
         __syncthreads();
     }
     if (w == 0 && lane == 0) {
-        v.partial[2 * (kMergeBlocks + blockIdx.x)] = changes;
-        v.partial[2 * (kMergeBlocks + blockIdx.x) + 1] = props;
+        v.partial[3 * (kMergeBlocks + blockIdx.x)] = changes;
+        v.partial[3 * (kMergeBlocks + blockIdx.x) + 1] = props;
+        v.partial[3 * (kMergeBlocks + blockIdx.x) + 2] = 0;
     }
 }
 
@@ -2110,34 +2190,38 @@ void launch_merge(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_merge_hubs, dim3(kHubBlocks), dim3(1024), 0, s, v);
 }
 
-size_t partial_words() { return 2 * (size_t)(kMergeBlocks + kHubBlocks); }
+size_t partial_words() { return 3 * (size_t)(kMergeBlocks + kHubBlocks); }
 
 __global__ __launch_bounds__(1024) void k_finish_counters(Views v) {
-    __shared__ uint64_t s_a[16], s_b[16];
+    __shared__ uint64_t s_a[16], s_b[16], s_c[16];
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
-    uint64_t a = 0, b = 0;
+    uint64_t a = 0, b = 0, c = 0;
     for (int i = t; i < kMergeBlocks + kHubBlocks; i += 1024) {
-        a += v.partial[2 * i];
-        b += v.partial[2 * i + 1];
+        a += v.partial[3 * i];
+        b += v.partial[3 * i + 1];
+        c += v.partial[3 * i + 2];
     }
     for (int o = 32; o > 0; o >>= 1) {
         a += shfl_xor64(a, o);
         b += shfl_xor64(b, o);
+        c += shfl_xor64(c, o);
     }
     if (lane == 0) {
         s_a[w] = a;
         s_b[w] = b;
+        s_c[w] = c;
     }
     __syncthreads();
     if (t == 0) {
-        uint64_t sa = 0, sb = 0;
+        uint64_t sa = 0, sb = 0, sc = 0;
         for (int i = 0; i < 16; ++i) {
             sa += s_a[i];
             sb += s_b[i];
+            sc += s_c[i];
         }
         v.counters[kCntChanges] = sa;
         v.counters[kCntProposals] = sb;
-        v.counters[kCntPairs2] = 2ull * v.poff[v.N];
+        v.counters[kCntPairs2] = 2ull * sc;
     }
 }
 

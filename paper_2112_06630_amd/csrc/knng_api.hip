@@ -62,13 +62,14 @@ struct Plan {
     int dp;
     int dpi;         // int8 row length of the exact integer form
     int split;       // split-BF16 copies of the rows
+    int rev_shift, rev_S, rev_B, rev_E;   // counting-sort reverse bucketing (rev_S = 0: atomics)
     int C;
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
-        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2, o_Xs, o_Xs2;
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp;
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -196,6 +197,25 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
         P.o_nrm2 = take((size_t)N * 4);
         P.o_orig2 = take((size_t)N * 4);
     }
+    // counting-sort reverse bucketing: super-buckets of 2^shift positions, at
+    // most kRevMaxS of them, blocks of E entries (at most 1024 blocks)
+    P.rev_S = 0;
+    for (int sh = 8; sh <= kRevMaxShift; ++sh) {
+        const int64_t S = (N + (1LL << sh) - 1) >> sh;
+        if (S <= kRevMaxS) {
+            int64_t E = 4096;
+            while ((NK + E - 1) / E > 1024) E *= 2;
+            P.rev_shift = sh;
+            P.rev_S = (int)S;
+            P.rev_E = (int)E;
+            P.rev_B = (int)((NK + E - 1) / E);
+            const size_t cells = (size_t)P.rev_S * P.rev_B;
+            P.o_rev_h = take(cells * 4);
+            P.o_rev_hs = take((cells + 1) * 4);
+            P.o_rev_tmp = take(scan_tmp_words((int)cells) * 4);
+            break;
+        }
+    }
     P.o_flag = take(64);
     P.total = off;
     return KNNG_OK;
@@ -266,6 +286,15 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
             v.Xi2 = reinterpret_cast<int8_t*>(b + P.o_Xi2);
             v.ni2 = reinterpret_cast<int32_t*>(b + P.o_ni2);
         }
+    }
+    if (P.rev_S) {
+        v.rev_shift = P.rev_shift;
+        v.rev_S = P.rev_S;
+        v.rev_B = P.rev_B;
+        v.rev_E = P.rev_E;
+        v.rev_h = reinterpret_cast<uint32_t*>(b + P.o_rev_h);
+        v.rev_hs = reinterpret_cast<uint32_t*>(b + P.o_rev_hs);
+        v.rev_tmp = reinterpret_cast<uint32_t*>(b + P.o_rev_tmp);
     }
     v.flag = reinterpret_cast<uint32_t*>(b + P.o_flag);
     return v;
@@ -369,9 +398,13 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
     launch_fill_u64(v.counters, 0ull, kNumCounters, s);
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_rev_hist(v, s);
-    launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
-    launch_rev_scatter(v, st, t, s);
+    if (v.rev_S) {
+        launch_rev_partition(v, st, t, s);
+    } else {
+        launch_rev_hist(v, s);
+        launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
+        launch_rev_scatter(v, st, t, s);
+    }
     launch_select(v, st, t, s);
     HIP_TRY(hipEventRecord(c->ev[1], s));
     if (c->plan.bf16)
@@ -868,9 +901,13 @@ void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hip
     const Views& v = g.v;
     launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
     launch_fill_u32(v.chg, 0u, (int64_t)v.N, s);
-    launch_rev_hist(v, s);
-    launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
-    launch_rev_scatter(v, 0, t, s);
+    if (v.rev_S) {
+        launch_rev_partition(v, 0, t, s);
+    } else {
+        launch_rev_hist(v, s);
+        launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
+        launch_rev_scatter(v, 0, t, s);
+    }
     launch_select(v, 0, t, s);
     launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
     if (g.path == KNNG_PATH_MFMA_BF16X3)

@@ -56,6 +56,14 @@ struct Views {
     uint32_t* roff;     // [N + 1] reverse bucket offsets
     uint32_t* rcur;     // [N] reverse bucket cursors
     uint4* rev;         // [N * K] reverse entries {w, orig src, pos src | flag, 0}
+    // counting-sort reverse bucketing (rev_S = 0: per-entry atomics instead)
+    int rev_shift;      // super-bucket = 2^rev_shift consecutive target positions
+    int rev_S;          // super-buckets
+    int rev_B;          // blocks of rev_E list entries
+    int rev_E;
+    uint32_t* rev_h;    // [rev_S * rev_B] counts, super-bucket major
+    uint32_t* rev_hs;   // [rev_S * rev_B + 1] their exclusive scan
+    uint32_t* rev_tmp;  // scan scratch
     uint2* cand;        // [N, 2C] sampled members {orig, pos}: new then old
     uint32_t* nn;       // [N] n_new | n_old << 16
     uint32_t* big;      // [N] 1: the owner's pool has more than 64 entries
@@ -134,6 +142,10 @@ void launch_batch_finalize(const Views& v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t val, int64_t n, hipStream_t s);
 void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
 void launch_rev_scatter(const Views& v, uint64_t st_sample, int t, hipStream_t s);
+// reverse buckets (roff, rev) by the counting sort; staging in the proposal buffer
+void launch_rev_partition(const Views& v, uint64_t st_sample, int t, hipStream_t s);
+constexpr int kRevMaxS = 8192;    // super-buckets (LDS counters of one block)
+constexpr int kRevMaxShift = 12;  // largest super-bucket: 4096 positions
 void launch_select(const Views& v, uint64_t st_sample, int t, hipStream_t s);
 void launch_join_valu(const Views& v, hipStream_t s);
 void launch_join_mfma(const Views& v, hipStream_t s);

@@ -641,6 +641,103 @@ void launch_rev_scatter(const Views& v, uint64_t st, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_rev_scatter, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v, st, t);
 }
 
+// Reverse lists by a counting sort with block-private counters (no global
+// atomics). Targets are grouped in super-buckets of R = 2^shift consecutive
+// positions. (1) each block counts its chunk of E list entries per
+// super-bucket in LDS -> H[s][b]; (2) exclusive scan of H (s-major) gives each
+// (super-bucket, block) its output range, and the start of super-bucket s is
+// the number of entries with smaller targets; (3) each block writes its
+// entries (target, w, source) into those ranges of a staging array; (4) one
+// block per super-bucket counts its targets in LDS, writes their bucket
+// offsets roff and places the entries. Orders inside a range depend on LDS
+// atomic order only, and every reader of a bucket sorts it by key.
+__global__ __launch_bounds__(1024) void k_rev_count(Views v) {
+    extern __shared__ uint32_t s_cnt[];
+    const int S = v.rev_S, B = gridDim.x;
+    const int64_t NK = (int64_t)v.N * v.K;
+    const int64_t e0 = (int64_t)blockIdx.x * v.rev_E, e1 = min(NK, e0 + v.rev_E);
+    for (int i = threadIdx.x; i < S; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    const double rk = 1.0 / v.K;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        if (v.ds && !pos_active(v, (int)udiv((uint32_t)e, (uint32_t)v.K, rk))) continue;
+        atomicAdd(&s_cnt[(v.lpos[e] & kPosMask) >> v.rev_shift], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < S; i += blockDim.x) v.rev_h[(size_t)i * B + blockIdx.x] = s_cnt[i];
+}
+
+__global__ __launch_bounds__(1024) void k_rev_part(Views v, uint64_t st0, int t) {
+    extern __shared__ uint32_t s_cur[];
+    const int S = v.rev_S, B = gridDim.x;
+    const int64_t NK = (int64_t)v.N * v.K;
+    const int64_t e0 = (int64_t)blockIdx.x * v.rev_E, e1 = min(NK, e0 + v.rev_E);
+    for (int i = threadIdx.x; i < S; i += blockDim.x) s_cur[i] = v.rev_hs[(size_t)i * B + blockIdx.x];
+    __syncthreads();
+    const double rk = 1.0 / v.K;
+    uint4* stage = reinterpret_cast<uint4*>(v.pkey);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int u = (int)udiv((uint32_t)e, (uint32_t)v.K, rk);
+        if (v.ds && !pos_active(v, u)) continue;
+        const uint64_t st = sample_state(v, u, st0, t);
+        const uint32_t pf = v.lpos[e];
+        const uint32_t tp = pf & kPosMask;
+        const uint32_t ou = (uint32_t)v.orig[u];
+        const uint32_t w = pair_weight(st, ou, (uint32_t)v.lkey[e]);
+        const uint32_t slot = atomicAdd(&s_cur[tp >> v.rev_shift], 1u);
+        stage[slot] = make_uint4(tp, w, ou, (uint32_t)u | (pf & kNewBit));
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_rev_bucket(Views v) {
+    extern __shared__ uint32_t s_loc[];   // [R] counts, then cursors
+    __shared__ uint32_t s_w[16];
+    const int R = 1 << v.rev_shift, B = v.rev_B;
+    const int sb = blockIdx.x, t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    const uint32_t lo = (uint32_t)sb << v.rev_shift;
+    const uint32_t a = v.rev_hs[(size_t)sb * B], b = v.rev_hs[(size_t)(sb + 1) * B];
+    const uint4* stage = reinterpret_cast<const uint4*>(v.pkey);
+    for (int i = t; i < R; i += 1024) s_loc[i] = 0u;
+    __syncthreads();
+    for (uint32_t e = a + t; e < b; e += 1024) atomicAdd(&s_loc[stage[e].x - lo], 1u);
+    __syncthreads();
+    // exclusive scan of the R counts: each thread owns R/1024 consecutive ones
+    const int per = R >> 10 > 0 ? R >> 10 : 1;
+    const int i0 = t * per;
+    uint32_t sum = 0;
+    for (int q = 0; q < per; ++q)
+        if (i0 + q < R) sum += s_loc[i0 + q];
+    const uint32_t inc = wave_incl_scan(sum);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t run = a + inc - sum;
+    for (int i = 0; i < w; ++i) run += s_w[i];
+    for (int q = 0; q < per; ++q) {
+        const int i = i0 + q;
+        if (i < R) {
+            const uint32_t c = s_loc[i];
+            if (lo + (uint32_t)i < (uint32_t)v.N) v.roff[lo + i] = run;
+            s_loc[i] = run;
+            run += c;
+        }
+    }
+    if (sb == (int)gridDim.x - 1 && t == 0) v.roff[v.N] = b;
+    __syncthreads();
+    for (uint32_t e = a + t; e < b; e += 1024) {
+        const uint4 x = stage[e];
+        const uint32_t slot = atomicAdd(&s_loc[x.x - lo], 1u);
+        v.rev[slot] = make_uint4(x.y, x.z, x.w, 0u);
+    }
+}
+
+void launch_rev_partition(const Views& v, uint64_t st, int t, hipStream_t s) {
+    const size_t lds_s = (size_t)v.rev_S * 4;
+    hipLaunchKernelGGL(k_rev_count, dim3(v.rev_B), dim3(1024), lds_s, s, v);
+    launch_scan(v.rev_h, v.rev_hs, v.rev_S * v.rev_B, v.rev_tmp, s);
+    hipLaunchKernelGGL(k_rev_part, dim3(v.rev_B), dim3(1024), lds_s, s, v, st, t);
+    hipLaunchKernelGGL(k_rev_bucket, dim3(v.rev_S), dim3(1024), ((size_t)4 << v.rev_shift), s, v);
+}
+
 // ------------------------------------------------------------------ select (a2)
 //
 // Pool of owner u: its K forward entries then its reverse bucket. The select

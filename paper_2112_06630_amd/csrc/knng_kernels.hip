@@ -64,9 +64,30 @@ __device__ __forceinline__ void wave_sync() {
     asm volatile("" ::: "memory");
 }
 
+// Value of lane (lane ^ m). Distances inside a row of 16 lanes use DPP moves
+// in the vector ALU (quad permutations; row mirror i -> i^15 and half mirror
+// i -> i^7 within a row, composed: 4 = half mirror then quad reverse (i^7^3),
+// 8 = mirror then half mirror (i^15^7)); 16 and 32 go through the LDS
+// crossbar. m is a compile-time constant after the sorting loops unroll.
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int m) {
+    switch (m) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: {
+            const int y = __builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);          // row_half_mirror
+            return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x1B, 0xF, 0xF, false);              // quad_perm [3,2,1,0]
+        }
+        case 8: {
+            const int y = __builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);          // row_mirror
+            return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x141, 0xF, 0xF, false);             // row_half_mirror
+        }
+        default: return (uint32_t)__shfl_xor((int)x, m);
+    }
+}
+
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
+    const uint32_t lo = xor_lanes((uint32_t)x, m);
+    const uint32_t hi = xor_lanes((uint32_t)(x >> 32), m);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -88,7 +109,7 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
 __device__ __forceinline__ void cmpx(uint64_t& k, uint32_t& v, int j, bool asc) {
     const int lane = lane_id();
     const uint64_t ok = shfl_xor64(k, j);
-    const uint32_t ov = (uint32_t)__shfl_xor((int)v, j);
+    const uint32_t ov = xor_lanes(v, j);
     const bool low = (lane & j) == 0;
     const bool sw = (asc == low) ? (ok < k) : (ok > k);
     if (sw) {
@@ -2066,17 +2087,34 @@ constexpr int kHubWaves = 16;
 constexpr int kMergeBlocks = 4096;      // partial-sum slots of k_merge
 constexpr int kHubBlocks = 512;
 
+// Folds a chunk sorted ascending (pk, pp) into the list (key, pf): the
+// reversed chunk and the list give, lane by lane, the smaller key; that
+// bitonic sequence holds the 64 smallest keys of both and one half-cleaner
+// pass sorts it.
+__device__ __forceinline__ void fold_sorted(uint64_t pk, uint32_t pp, uint64_t& key, uint32_t& pf) {
+    const int lane = lane_id();
+    const uint64_t rk = shfl64(pk, 63 - lane);
+    const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
+    if (rk < key) {
+        key = rk;
+        pf = rp;
+    }
+    wave_bitonic_clean(key, pf);
+}
+
 // Folds proposals src[c0 .. n) (chunks of 64, every `stride` elements) into
 // the list held one entry per lane in (key, pf), ascending, +inf beyond K.
 // A proposal is dropped when it is not below the current K-th key, or its id
-// is in the snapshot list or already in the list. A chunk with few
-// survivors inserts them one by one (ballot rank, shift up); a larger one is
-// sorted (bitonic), reversed and folded into the list with a lane-wise min,
-// which leaves a bitonic sequence holding the 64 smallest keys, sorted again
-// by one half-cleaner pass; equal keys (one id proposed by two owners) are
-// then collapsed through LDS (sk, sp: 64 slots of this wave).
+// is in the snapshot list; an id already taken from another proposal carries
+// the same key (one key per pair) and is dropped as a repeat. A chunk with
+// few survivors inserts them one by one (ballot rank, shift up); a larger one
+// is sorted (bitonic) and folded into the list (fold_sorted). Repeated keys
+// would each take a slot of the 64 smallest, so when one lands among the
+// first K the fold is redone from the list as it was, with every chunk key
+// that repeats its neighbour or a list key (binary search in LDS) removed
+// and the rest compacted in order (sk, sp: 64 slots of this wave).
 __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint32_t stride,
-                             int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth, bool& grown,
+                             int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth,
                              uint64_t* sk, uint32_t* sp) {
     const int lane = lane_id();
     uint64_t nk = ~0ull;
@@ -2090,20 +2128,12 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
         bool ok = pk < kth;
         if (ballot(ok) == 0) continue;
         const uint32_t pid = (uint32_t)pk;
-        for (int k = 0; k < K; ++k) {
-            const uint32_t sidk = rl32(snap, k);
-            ok &= sidk != pid;
-        }
-        if (grown) {
-            const uint32_t cur = (uint32_t)key;
-            for (int k = 0; k < K; ++k) {
-                const uint32_t cidk = rl32(cur, k);
-                ok &= cidk != pid;
-            }
-        }
+        // ids of the snapshot list are ignored; an id that entered from an
+        // earlier proposal comes back with the same key (every join form gives
+        // a pair one key), so the duplicate check below catches it
+        for (int k = 0; k < K; ++k) ok &= rl32(snap, k) != pid;
         uint64_t mask = ballot(ok);
         if (mask == 0) continue;
-        grown = true;
         if (__popcll(mask) <= 4) {
             while (mask) {
                 const int j = __ffsll((long long)mask) - 1;
@@ -2128,28 +2158,33 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
         } else {
             if (!ok) pk = ~0ull;
             wave_sort(pk, pp);
-            const uint64_t rk = shfl64(pk, 63 - lane);
-            const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
-            if (rk < key) {
-                key = rk;
-                pf = rp;
-            }
-            wave_bitonic_clean(key, pf);
+            const uint64_t k0 = key;
+            const uint32_t f0 = pf;
+            fold_sorted(pk, pp, key, pf);
             const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
-            const bool dupk = lane > 0 && key != ~0ull && prevk == key;
-            const uint64_t dm = ballot(dupk);
-            if (dm) {
+            if (ballot(lane > 0 && lane < K && key != ~0ull && prevk == key)) {
+                sk[lane] = k0;
+                wave_sync();
+                int lo = 0;   // keys of the list below pk (at most 63)
+                for (int st = 32; st > 0; st >>= 1) lo += sk[lo + st - 1] < pk ? st : 0;
+                const uint64_t prevp = shfl_up64(pk, 1);
+                const bool keep = pk != ~0ull && sk[lo] != pk && !(lane > 0 && prevp == pk);
+                const uint64_t km = ballot(keep);
+                wave_sync();
                 sk[lane] = ~0ull;
                 wave_sync();
-                if (!dupk) {
-                    const uint32_t to = (uint32_t)lane - mbcnt(dm);
-                    sk[to] = key;
-                    sp[to] = pf;
+                if (keep) {
+                    const uint32_t to = mbcnt(km);
+                    sk[to] = pk;
+                    sp[to] = pp;
                 }
                 wave_sync();
-                key = sk[lane];
-                pf = sp[lane];
+                pk = sk[lane];
+                pp = sp[lane];
                 wave_sync();
+                key = k0;
+                pf = f0;
+                fold_sorted(pk, pp, key, pf);
             }
             if (lane >= K) {
                 key = ~0ull;
@@ -2161,16 +2196,22 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
 }
 
 // Writes a merged row back; checks that no id appears twice (that would
-// mean two different keys for one pair) and counts ids not in the snapshot.
-// Entries that came from proposals get their position from the id: the
-// dataset's first position plus the id (batched form), else posof.
+// mean two different keys for one pair), that every id names a point of the
+// dataset, and counts ids not in the snapshot. Entries that came from
+// proposals get their position from the id: the dataset's first position
+// plus the id (batched form), else posof.
 __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uint64_t key, uint32_t pf,
                                                       uint32_t snap) {
     const int lane = lane_id(), K = v.K;
     const size_t row = (size_t)p * K;
+    const uint32_t base = v.ds ? v.dsbase[v.ds[p]] : 0u;
+    const uint32_t npts = v.ds ? v.dsbase[v.ds[p] + 1] - base : (uint32_t)v.N;
+    const bool lost = lane < K && (uint32_t)key >= npts;
+    if (ballot(lost) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 512ull);
+    if (lost) pf = kNewBit;   // position 0: the build reports the error after this iteration
     if (lane < K && pf == kPosUnknown) {
         const uint32_t id = (uint32_t)key;
-        pf = (v.ds ? v.dsbase[v.ds[p]] + id : (uint32_t)v.posof[id]) | kNewBit;
+        pf = (v.ds ? base + id : (uint32_t)v.posof[id]) | kNewBit;
     }
     bool twice = false, entered = lane < K;
     for (int k = 0; k < K; ++k) {
@@ -2213,8 +2254,7 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
-        bool grown = false;
-        merge_chunks(v.pkey + base, 0, n, 64, K, snap, key, pf, kth, grown, s_k[w], s_p[w]);
+        merge_chunks(v.pkey + base, 0, n, 64, K, snap, key, pf, kth, s_k[w], s_p[w]);
         changes += finish_merged_row(v, p, key, pf, snap);
         props += n;
     }
@@ -2260,15 +2300,14 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
-        bool grown = false;
         merge_chunks(v.pkey + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth,
-                     grown, s_k[w], s_p[w]);
+                     s_k[w], s_p[w]);
         s_lk[w][lane] = key;
         __syncthreads();
         if (w == 0) {
             // the other partial lists: their snapshot ids are dropped by the fold, so
             // every entry that gets through came from a proposal (NEW, position by id)
-            merge_chunks(&s_lk[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth, grown,
+            merge_chunks(&s_lk[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth,
                          s_k[0], s_p[0]);
             changes += finish_merged_row(v, p, key, pf, snap);
             props += n;

@@ -337,9 +337,17 @@ def test_duplicate_points_and_small_K(knng):
     exact_build(knng, X, 9, 0.05, 0.0, 8, 2)
 
 
-def test_max_K_valu(knng):
-    X = synth.integer_points(400, 4, 50, 8)
-    exact_build(knng, X, 64, 1.0, 0.001, 6, 8, path="valu")
+@pytest.mark.parametrize("path,N,d,K,rho,hi,seed", [
+    ("valu", 400, 4, 64, 1.0, 50, 8),
+    ("valu", 300, 3, 63, 1.0, 6, 12),
+    ("mfma", 500, 64, 64, 0.5, 7, 13),
+    ("bf16x3", 500, 64, 64, 0.5, 7, 14),
+])
+def test_max_K(knng, path, N, d, K, rho, hi, seed):
+    """K = 63 and 64 leave (almost) no spare lane in the merge's 64-wide fold: a
+    pair proposed again (by another owner, or after its id entered from an
+    earlier chunk) must not cost the list an entry."""
+    exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 6, seed, path=path)
 
 
 def test_zero_iterations_returns_init(knng):

@@ -2087,17 +2087,33 @@ constexpr int kHubWaves = 16;
 constexpr int kMergeBlocks = 4096;      // partial-sum slots of k_merge
 constexpr int kHubBlocks = 512;
 
-// Folds a chunk sorted ascending (pk, pp) into the list (key, pf): the
-// reversed chunk and the list give, lane by lane, the smaller key; that
-// bitonic sequence holds the 64 smallest keys of both and one half-cleaner
-// pass sorts it.
-__device__ __forceinline__ void fold_sorted(uint64_t pk, uint32_t pp, uint64_t& key, uint32_t& pf) {
+// Ascending bitonic sort of 64 keys, one per lane.
+__device__ __forceinline__ void wave_sort_keys(uint64_t& k) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            // selects, not branches: the smaller key to the lower lane of an
+            // ascending block, the larger to its upper lane
+            const uint64_t o = shfl_xor64(k, j);
+            const bool lt = o < k;
+            const uint64_t mn = lt ? o : k, mx = lt ? k : o;
+            k = (((lane & j) == 0) == ((lane & size) == 0)) ? mn : mx;
+        }
+    }
+}
+
+// Folds proposal keys sorted ascending into the list (key, pf): the reversed
+// keys and the list give, lane by lane, the smaller key; that bitonic
+// sequence holds the 64 smallest keys of both and one half-cleaner pass
+// sorts it. Entries taken from the proposals find their position from the id.
+__device__ __forceinline__ void fold_sorted(uint64_t pk, uint64_t& key, uint32_t& pf) {
     const int lane = lane_id();
     const uint64_t rk = shfl64(pk, 63 - lane);
-    const uint32_t rp = (uint32_t)__shfl((int)pp, 63 - lane);
     if (rk < key) {
         key = rk;
-        pf = rp;
+        pf = kPosUnknown;
     }
     wave_bitonic_clean(key, pf);
 }
@@ -2105,33 +2121,40 @@ __device__ __forceinline__ void fold_sorted(uint64_t pk, uint32_t pp, uint64_t& 
 // Folds proposals src[c0 .. n) (chunks of 64, every `stride` elements) into
 // the list held one entry per lane in (key, pf), ascending, +inf beyond K.
 // A proposal is dropped when it is not below the current K-th key, or its id
-// is in the snapshot list; an id already taken from another proposal carries
-// the same key (one key per pair) and is dropped as a repeat. A chunk with
+// is in the snapshot list (snap: ids, lanes < K; compared by id, since the
+// list's keys may come from the initial graph, whose distances are summed in
+// another order than the join's). An id already taken from another proposal
+// carries the same key (the join gives a pair one key) and is dropped as a
+// repeat. A chunk with
 // few survivors inserts them one by one (ballot rank, shift up); a larger one
 // is sorted (bitonic) and folded into the list (fold_sorted). Repeated keys
 // would each take a slot of the 64 smallest, so when one lands among the
 // first K the fold is redone from the list as it was, with every chunk key
 // that repeats its neighbour or a list key (binary search in LDS) removed
-// and the rest compacted in order (sk, sp: 64 slots of this wave).
+// and the rest compacted in order (sk: 64 slots of this wave).
 __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint32_t stride,
                              int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth,
-                             uint64_t* sk, uint32_t* sp) {
+                             uint64_t* sk) {
     const int lane = lane_id();
     uint64_t nk = ~0ull;
     if (c0 + (uint32_t)lane < n) nk = pks[c0 + lane];
     for (; c0 < n; c0 += stride) {
-        uint64_t pk = nk;
-        uint32_t pp = kPosUnknown;   // NEW, position found when the id enters the list
+        uint64_t pk = nk;   // NEW entries: the position is found when the id enters the list
         // next chunk in flight while this one is merged
         nk = ~0ull;
         if (c0 + stride + (uint32_t)lane < n) nk = pks[c0 + stride + lane];
         bool ok = pk < kth;
         if (ballot(ok) == 0) continue;
+        // ids are below 2^31, so (a ^ b) - 1 has bit 31 set exactly when a == b:
+        // lane-local arithmetic, no lane-mask work per snapshot entry
         const uint32_t pid = (uint32_t)pk;
-        // ids of the snapshot list are ignored; an id that entered from an
-        // earlier proposal comes back with the same key (every join form gives
-        // a pair one key), so the duplicate check below catches it
-        for (int k = 0; k < K; ++k) ok &= rl32(snap, k) != pid;
+        uint32_t hit = 0u;
+        int k = 0;
+        for (; k + 4 <= K; k += 4)
+            hit |= ((rl32(snap, k) ^ pid) - 1u) | ((rl32(snap, k + 1) ^ pid) - 1u) |
+                   ((rl32(snap, k + 2) ^ pid) - 1u) | ((rl32(snap, k + 3) ^ pid) - 1u);
+        for (; k < K; ++k) hit |= (rl32(snap, k) ^ pid) - 1u;
+        ok &= (hit >> 31) == 0u;
         uint64_t mask = ballot(ok);
         if (mask == 0) continue;
         if (__popcll(mask) <= 4) {
@@ -2141,7 +2164,6 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
                 const uint64_t x = rl64(pk, j);
                 if (x >= kth) continue;
                 if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;  // same id, same key
-                const uint32_t xp = rl32(pp, j);
                 const int at = __popcll(ballot(lane < K && key < x));
                 const uint64_t ku = shfl_up64(key, 1);
                 const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
@@ -2151,16 +2173,16 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
                 }
                 if (lane == at) {
                     key = x;
-                    pf = xp;
+                    pf = kPosUnknown;
                 }
                 kth = rl64(key, K - 1);
             }
         } else {
             if (!ok) pk = ~0ull;
-            wave_sort(pk, pp);
+            wave_sort_keys(pk);
             const uint64_t k0 = key;
             const uint32_t f0 = pf;
-            fold_sorted(pk, pp, key, pf);
+            fold_sorted(pk, key, pf);
             const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
             if (ballot(lane > 0 && lane < K && key != ~0ull && prevk == key)) {
                 sk[lane] = k0;
@@ -2173,18 +2195,13 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
                 wave_sync();
                 sk[lane] = ~0ull;
                 wave_sync();
-                if (keep) {
-                    const uint32_t to = mbcnt(km);
-                    sk[to] = pk;
-                    sp[to] = pp;
-                }
+                if (keep) sk[mbcnt(km)] = pk;
                 wave_sync();
                 pk = sk[lane];
-                pp = sp[lane];
                 wave_sync();
                 key = k0;
                 pf = f0;
-                fold_sorted(pk, pp, key, pf);
+                fold_sorted(pk, key, pf);
             }
             if (lane >= K) {
                 key = ~0ull;
@@ -2195,15 +2212,17 @@ __device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint3
     }
 }
 
-// Writes a merged row back; checks that no id appears twice (that would
-// mean two different keys for one pair), that every id names a point of the
-// dataset, and counts ids not in the snapshot. Entries that came from
-// proposals get their position from the id: the dataset's first position
-// plus the id (batched form), else posof.
-__device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uint64_t key, uint32_t pf,
-                                                      uint32_t snap) {
+// Writes a merged row back; checks that every id names a point of the
+// dataset and that no id appears twice (that would mean two different keys
+// for one pair; the entries kept from the snapshot are distinct, so only
+// those that entered are compared), and counts the entered ids (c_t). An
+// entry entered exactly when it came from a proposal (position word
+// kPosUnknown); it gets its position from the id: the dataset's first
+// position plus the id (batched form), else posof.
+__device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uint64_t key, uint32_t pf) {
     const int lane = lane_id(), K = v.K;
     const size_t row = (size_t)p * K;
+    const uint64_t em = ballot(lane < K && pf == kPosUnknown);
     const uint32_t base = v.ds ? v.dsbase[v.ds[p]] : 0u;
     const uint32_t npts = v.ds ? v.dsbase[v.ds[p] + 1] - base : (uint32_t)v.N;
     const bool lost = lane < K && (uint32_t)key >= npts;
@@ -2213,19 +2232,18 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
         const uint32_t id = (uint32_t)key;
         pf = (v.ds ? base + id : (uint32_t)v.posof[id]) | kNewBit;
     }
-    bool twice = false, entered = lane < K;
-    for (int k = 0; k < K; ++k) {
-        const uint32_t ik = rl32((uint32_t)key, k);
-        const uint32_t sk = rl32(snap, k);
-        twice |= lane < K && k != lane && ik == (uint32_t)key;
-        entered &= sk != (uint32_t)key;
+    bool twice = false;
+    for (uint64_t m = em; m; m &= m - 1) {
+        const int e = __ffsll((long long)m) - 1;
+        const uint32_t ie = rl32((uint32_t)key, e);
+        twice |= lane < K && lane != e && (uint32_t)key == ie;
     }
     if (ballot(twice) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 8ull);
     if (lane < K) {
         v.lkey[row + lane] = key;
         v.lpos[row + lane] = pf;
     }
-    const uint64_t c = (uint64_t)__popcll(ballot(entered));
+    const uint64_t c = (uint64_t)__popcll(em);
     if (v.chg && lane == 0) v.chg[row / K] = (uint32_t)c;   // batched form: changes per target
     return c;
 }
@@ -2233,7 +2251,6 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
 // One wave per target; buckets above kHubProposals go to k_merge_hubs.
 __global__ __launch_bounds__(256) void k_merge(Views v) {
     __shared__ uint64_t s_k[kMergeWaves][64];
-    __shared__ uint32_t s_p[kMergeWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
     uint64_t changes = 0, props = 0, pairs = 0;
@@ -2254,8 +2271,8 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
-        merge_chunks(v.pkey + base, 0, n, 64, K, snap, key, pf, kth, s_k[w], s_p[w]);
-        changes += finish_merged_row(v, p, key, pf, snap);
+        merge_chunks(v.pkey + base, 0, n, 64, K, snap, key, pf, kth, s_k[w]);
+        changes += finish_merged_row(v, p, key, pf);
         props += n;
     }
     // per-block partial sums (no same-address atomics); summed by k_finish_counters
@@ -2285,7 +2302,6 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
 // since the K smallest of a union are the K smallest of the partial results.
 __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
     __shared__ uint64_t s_k[kHubWaves][64];
-    __shared__ uint32_t s_p[kHubWaves][64];
     __shared__ uint64_t s_lk[kHubWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
@@ -2300,16 +2316,14 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
         const uint32_t snap = lane < K ? (uint32_t)key : 0xffffffffu;
         uint64_t kth = rl64(key, K - 1);
-        merge_chunks(v.pkey + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth,
-                     s_k[w], s_p[w]);
+        merge_chunks(v.pkey + base, (uint32_t)w * 64, n, kHubWaves * 64, K, snap, key, pf, kth, s_k[w]);
         s_lk[w][lane] = key;
         __syncthreads();
         if (w == 0) {
             // the other partial lists: their snapshot ids are dropped by the fold, so
             // every entry that gets through came from a proposal (NEW, position by id)
-            merge_chunks(&s_lk[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth,
-                         s_k[0], s_p[0]);
-            changes += finish_merged_row(v, p, key, pf, snap);
+            merge_chunks(&s_lk[1][0], 0, (kHubWaves - 1) * 64, 64, K, snap, key, pf, kth, s_k[0]);
+            changes += finish_merged_row(v, p, key, pf);
             props += n;
         }
         __syncthreads();

@@ -1023,163 +1023,160 @@ __device__ __forceinline__ void pool_read(const Views& v, uint64_t st, int u, ui
     }
 }
 
-constexpr int kSelLWaves = 4;
-
-__global__ __launch_bounds__(256) void k_select_large_thr(Views v, uint64_t st0, int t) {
-    __shared__ uint64_t s_key[kSelLWaves][64];
-    __shared__ uint32_t s_idx[kSelLWaves][64];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+// One owner whose pool has more than 64 entries (s_key, s_idx: 64 LDS slots
+// of the calling wave).
+__device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint32_t rb, int P, uint32_t ou,
+                                       uint64_t* s_key, uint32_t* s_idx) {
+    const int lane = lane_id();
     const int K = v.K;
     const uint32_t C = (uint32_t)v.C;
-    for (int u = blockIdx.x * kSelLWaves + w; u < v.N; u += gridDim.x * kSelLWaves) {
-        if (!v.big[u]) continue;
-        const uint64_t st = sample_state(v, u, st0, t);
-        const uint32_t rb = v.roff[u];
-        const int P = K + (int)(v.roff[u + 1] - rb);
-        const uint32_t ou = (uint32_t)v.orig[u];
-        uint32_t tot[2] = {0u, 0u};
+    uint32_t tot[2] = {0u, 0u};
+    for (int i0 = 0; i0 < P; i0 += 64) {
+        const int i = i0 + lane;
+        uint32_t wt = 0, id = 0, pf = 0;
+        if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+        tot[0] += __popcll(ballot(i < P && (pf & kNewBit)));
+        tot[1] += __popcll(ballot(i < P && !(pf & kNewBit)));
+    }
+    uint32_t newid = 0xffffffffu;  // lane r < nnew: id of the sampled new member of rank r
+    uint32_t nnew = 0, nold = 0;
+    uint32_t flip_idx = 0xffffffffu, flip_pos = 0;
+    uint2* cs = v.cand + (size_t)u * 2 * C;
+    bool failed = false;
+    for (int f = 0; f < 2; ++f) {
+        // ---- threshold ----
+        uint32_t T = 0xffffffffu;
+        if (tot[f] > 64) {
+            const uint32_t need = 2 * C;
+            uint64_t lo = 0, hi = 0xffffffffull;
+            uint64_t t = ((uint64_t)((need + 64) / 2) << 32) / tot[f];
+            bool found = false;
+            for (int it = 0; it < 48 && !found; ++it) {
+                uint32_t cnt = 0;
+                for (int i0 = 0; i0 < P; i0 += 64) {
+                    const int i = i0 + lane;
+                    uint32_t wt = 0, id = 0, pf = 0;
+                    if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+                    const bool isf = ((pf & kNewBit) ? 0 : 1) == f;
+                    cnt += __popcll(ballot(i < P && isf && wt <= (uint32_t)t));
+                }
+                if (cnt >= need && cnt <= 64) {
+                    found = true;
+                } else {
+                    if (cnt < need) lo = t; else hi = t;
+                    t = lo + (hi - lo) / 2;
+                    if (hi - lo <= 1) break;
+                }
+            }
+            if (!found) {
+                failed = true;
+                break;
+            }
+            T = (uint32_t)t;
+        }
+        // ---- gather the survivors of flag f ----
+        uint32_t n = 0;
+        s_key[lane] = ~0ull;
+        wave_sync();
         for (int i0 = 0; i0 < P; i0 += 64) {
             const int i = i0 + lane;
             uint32_t wt = 0, id = 0, pf = 0;
             if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
-            tot[0] += __popcll(ballot(i < P && (pf & kNewBit)));
-            tot[1] += __popcll(ballot(i < P && !(pf & kNewBit)));
-        }
-        uint32_t newid = 0xffffffffu;  // lane r < nnew: id of the sampled new member of rank r
-        uint32_t nnew = 0, nold = 0;
-        uint32_t flip_idx = 0xffffffffu, flip_pos = 0;
-        uint2* cs = v.cand + (size_t)u * 2 * C;
-        bool failed = false;
-        for (int f = 0; f < 2; ++f) {
-            // ---- threshold ----
-            uint32_t T = 0xffffffffu;
-            if (tot[f] > 64) {
-                const uint32_t need = 2 * C;
-                uint64_t lo = 0, hi = 0xffffffffull;
-                uint64_t t = ((uint64_t)((need + 64) / 2) << 32) / tot[f];
-                bool found = false;
-                for (int it = 0; it < 48 && !found; ++it) {
-                    uint32_t cnt = 0;
-                    for (int i0 = 0; i0 < P; i0 += 64) {
-                        const int i = i0 + lane;
-                        uint32_t wt = 0, id = 0, pf = 0;
-                        if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
-                        const bool isf = ((pf & kNewBit) ? 0 : 1) == f;
-                        cnt += __popcll(ballot(i < P && isf && wt <= (uint32_t)t));
-                    }
-                    if (cnt >= need && cnt <= 64) {
-                        found = true;
-                    } else {
-                        if (cnt < need) lo = t; else hi = t;
-                        t = lo + (hi - lo) / 2;
-                        if (hi - lo <= 1) break;
-                    }
-                }
-                if (!found) {
-                    failed = true;
-                    break;
-                }
-                T = (uint32_t)t;
+            const bool surv = i < P && (((pf & kNewBit) ? 0 : 1) == f) && wt <= T;
+            const uint64_t m = ballot(surv);
+            const uint32_t slot = n + mbcnt(m);
+            if (surv && slot < 64) {
+                s_key[slot] = sel_key(wt, id, pf);
+                s_idx[slot] = (uint32_t)i;
             }
-            // ---- gather the survivors of flag f ----
-            uint32_t n = 0;
-            s_key[w][lane] = ~0ull;
-            wave_sync();
-            for (int i0 = 0; i0 < P; i0 += 64) {
-                const int i = i0 + lane;
-                uint32_t wt = 0, id = 0, pf = 0;
-                if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
-                const bool surv = i < P && (((pf & kNewBit) ? 0 : 1) == f) && wt <= T;
-                const uint64_t m = ballot(surv);
-                const uint32_t slot = n + mbcnt(m);
-                if (surv && slot < 64) {
-                    s_key[w][slot] = sel_key(wt, id, pf);
-                    s_idx[w][slot] = (uint32_t)i;
-                }
-                n += (uint32_t)__popcll(m);
-            }
-            wave_sync();
-            if (n > 64) {
-                failed = true;
-                break;
-            }
-            uint64_t key = s_key[w][lane];
-            uint32_t idx = (uint32_t)lane < n ? s_idx[w][lane] : 0xffffffffu;
-            wave_sync();
-            wave_sort(key, idx);
-            const uint64_t p1 = shfl_up64(key, 1);
-            const bool real = key != ~0ull;
-            const bool dup = real && lane >= 1 && p1 == key;
-            const bool valid = real && !dup;
-            const uint64_t mv = ballot(valid);
-            const uint32_t r = mbcnt(mv);
-            const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
-            uint32_t pos = 0;
-            if (valid && r < C) {
-                uint32_t wt2, id2, pf2;
-                pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
-                pos = pf2 & kPosMask;
-            }
-            if (f == 0) {
-                const bool sel = valid && r < C;
-                const int s1 = __shfl_up(sel ? 1 : 0, 1);
-                nnew = min(C, (uint32_t)__popcll(mv));
-                if (sel) cs[r] = make_uint2(id, pos);
-                // forward NEW entries of sampled members flip to OLD once the OLD
-                // pass (which reads the flags as sampled) is done; the forward copy
-                // may be the duplicate (second) one
-                if (idx < (uint32_t)K && (sel || (dup && s1))) {
-                    uint32_t wt2, id2, pf2;
-                    pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
-                    flip_idx = idx;
-                    flip_pos = pf2 & kPosMask;
-                }
-                // sampled new ids to lanes 0..nnew-1 (they are the first valid lanes in order)
-                s_idx[w][lane] = 0xffffffffu;
-                wave_sync();
-                if (sel) s_idx[w][r] = id;
-                wave_sync();
-                newid = s_idx[w][lane];
-                wave_sync();
-            } else {
-                bool innew = false;
-                for (uint32_t k = 0; k < nnew; ++k) {
-                    const uint32_t nk = rl32(newid, (int)k);
-                    innew |= nk == id;
-                }
-                const bool cand_old = valid && r < C;
-                const bool removed = cand_old && innew;
-                const uint64_t mrem = ballot(removed);
-                nold = min(C, (uint32_t)__popcll(mv)) - (uint32_t)__popcll(mrem);
-                if (cand_old && !removed) cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
-            }
-        }
-        if (failed) {   // reported; the owner samples nothing (its join is skipped)
-            if (lane == 0) {
-                atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
-                v.nn[u] = 0u;
-                v.cap[u] = 0u;
-            }
-            continue;
-        }
-        if (flip_idx != 0xffffffffu) v.lpos[(size_t)u * K + flip_idx] = flip_pos;
-        if (lane == 0) {
-            v.nn[u] = nnew | (nold << 16);
-            v.cap[u] = owner_pairs(nnew, nold);
+            n += (uint32_t)__popcll(m);
         }
         wave_sync();
+        if (n > 64) {
+            failed = true;
+            break;
+        }
+        uint64_t key = s_key[lane];
+        uint32_t idx = (uint32_t)lane < n ? s_idx[lane] : 0xffffffffu;
+        wave_sync();
+        wave_sort(key, idx);
+        const uint64_t p1 = shfl_up64(key, 1);
+        const bool real = key != ~0ull;
+        const bool dup = real && lane >= 1 && p1 == key;
+        const bool valid = real && !dup;
+        const uint64_t mv = ballot(valid);
+        const uint32_t r = mbcnt(mv);
+        const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
+        uint32_t pos = 0;
+        if (valid && r < C) {
+            uint32_t wt2, id2, pf2;
+            pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
+            pos = pf2 & kPosMask;
+        }
+        if (f == 0) {
+            const bool sel = valid && r < C;
+            const int s1 = __shfl_up(sel ? 1 : 0, 1);
+            nnew = min(C, (uint32_t)__popcll(mv));
+            if (sel) cs[r] = make_uint2(id, pos);
+            // forward NEW entries of sampled members flip to OLD once the OLD
+            // pass (which reads the flags as sampled) is done; the forward copy
+            // may be the duplicate (second) one
+            if (idx < (uint32_t)K && (sel || (dup && s1))) {
+                uint32_t wt2, id2, pf2;
+                pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
+                flip_idx = idx;
+                flip_pos = pf2 & kPosMask;
+            }
+            // sampled new ids to lanes 0..nnew-1 (they are the first valid lanes in order)
+            s_idx[lane] = 0xffffffffu;
+            wave_sync();
+            if (sel) s_idx[r] = id;
+            wave_sync();
+            newid = s_idx[lane];
+            wave_sync();
+        } else {
+            bool innew = false;
+            for (uint32_t k = 0; k < nnew; ++k) {
+                const uint32_t nk = rl32(newid, (int)k);
+                innew |= nk == id;
+            }
+            const bool cand_old = valid && r < C;
+            const bool removed = cand_old && innew;
+            const uint64_t mrem = ballot(removed);
+            nold = min(C, (uint32_t)__popcll(mv)) - (uint32_t)__popcll(mrem);
+            if (cand_old && !removed) cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
+        }
     }
+    if (failed) {   // reported; the owner samples nothing (its join is skipped)
+        if (lane == 0) {
+            atomicOr((unsigned long long*)&v.counters[kCntError], 16ull);
+            v.nn[u] = 0u;
+            v.cap[u] = 0u;
+        }
+        return;
+    }
+    if (flip_idx != 0xffffffffu) v.lpos[(size_t)u * K + flip_idx] = flip_pos;
+    if (lane == 0) {
+        v.nn[u] = nnew | (nold << 16);
+        v.cap[u] = owner_pairs(nnew, nold);
+    }
+    wave_sync();
 }
 
 // Pools of at most 64 entries, one per lane, in registers. Select key
 // (w << 32) | (id << 1) | old: sorting it puts the two copies of a member
 // reached by both routes with the same flag next to each other (the second
 // is a duplicate), and a member's NEW entry right before its OLD entry.
-// Ranks per flag are ballot prefix counts over the sorted lanes.
+// Ranks per flag are ballot prefix counts over the sorted lanes. Larger pools
+// take the threshold select in the same wave when 2C <= 60 (their latency
+// hides behind the small pools), else k_select_large (big[u] = 1).
 __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int t) {
+    __shared__ uint64_t s_key[kSelWaves][64];
+    __shared__ uint32_t s_idx[kSelWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int N = v.N, K = v.K;
     const uint32_t C = (uint32_t)v.C;
+    const bool thr_inline = 2 * v.C <= 60;
     for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
         if (v.ds && !pos_active(v, u)) {   // finished dataset: nothing sampled, nothing joined
             if (lane == 0) {
@@ -1192,9 +1189,12 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
         const uint64_t st = sample_state(v, u, st0, t);
         const uint32_t rb = v.roff[u];
         const int P = K + (int)(v.roff[u + 1] - rb);
-        if (lane == 0) v.big[u] = P > 64 ? 1u : 0u;
-        if (P > 64) continue;
+        if (lane == 0) v.big[u] = P > 64 && !thr_inline ? 1u : 0u;
         const uint32_t ou = (uint32_t)v.orig[u];
+        if (P > 64) {
+            if (thr_inline) select_large_thr_owner(v, st, u, rb, P, ou, s_key[w], s_idx[w]);
+            continue;
+        }
         uint64_t key = ~0ull;
         uint32_t pos = 0;
         if (lane < P) {
@@ -1248,13 +1248,11 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
 
 void launch_select(const Views& v, uint64_t st, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
-    // The threshold search needs a count in [2C, 64]; a member reached by both
-    // routes adds two entries of one weight, so the count can step over a
-    // window narrower than 3 (2C = 64 leaves one value). Caps above 30 take
-    // the rank path.
-    if (2 * v.C <= 60)
-        hipLaunchKernelGGL(k_select_large_thr, dim3(grid_for(v.N, kSelLWaves, 4096)), dim3(256), 0, s, v, st, t);
-    else
+    // The threshold search (inside k_select_small) needs a count in [2C, 64];
+    // a member reached by both routes adds two entries of one weight, so the
+    // count can step over a window narrower than 3 (2C = 64 leaves one
+    // value). Caps above 30 take the rank path.
+    if (2 * v.C > 60)
         hipLaunchKernelGGL(k_select_large, dim3(grid_for(v.N, kSelWaves, 4096)), dim3(256), 0, s, v, st, t);
 }
 

@@ -553,6 +553,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
         const uint64_t used = c->hc[kCntSplit];
         c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
         c->stats.planes = c->v.planes;
+        if (c->v.planes > 1 || P.want_i8) launch_prep_rest(dX, c->v, c->stream);
     }
     if (P.want_i8) {
         knng_status is = select_int8(c);

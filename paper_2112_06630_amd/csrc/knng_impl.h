@@ -133,6 +133,9 @@ void launch_make_split(const Views& v, hipStream_t s);
 // one pass over X for the MFMA forms: padded rows, norms, identity positions,
 // finiteness check and (split != 0) the split-BF16 planes
 void launch_prep(const float* X, const Views& v, int split, hipStream_t s);
+// split form with planes > 1 (or a reader of the FP32 rows): padded FP32 rows
+// and planes 2 and 3
+void launch_prep_rest(const float* X, const Views& v, hipStream_t s);
 void launch_join_split(const Views& v, hipStream_t s);
 void launch_rev_hist(const Views& v, hipStream_t s);
 // batched form

@@ -1866,14 +1866,16 @@ void launch_make_split(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_make_split, dim3(grid_for((int64_t)v.N * v.dp, 1024, 16384)), dim3(256), 0, s, v);
 }
 
-// Layout of the MFMA forms in one pass over X, one wave per row: the padded
-// FP32 row, its squared norm (lane sums over j mod 4, then a fixed xor tree),
-// identity positions, the finiteness check and, for the split form, the three
-// BF16 planes with the used-plane record of k_make_split.
+// Layout of the MFMA forms in one pass over X, one wave per row: the squared
+// norm (lane sums over j mod 4, then a fixed xor tree), identity positions,
+// the finiteness check, and either the padded FP32 row (FP32 tiles) or, for
+// the split form, the first BF16 plane and the used-plane record of
+// k_make_split. The FP32 row and planes 2 and 3 of the split form are
+// written by k_prep_rest only when a later plane is used (no reader needs
+// them otherwise).
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views v, int split) {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int d = v.d, dp = v.dp;
-    const int64_t total = (int64_t)v.N * dp;
     bool bad = false;
     uint32_t used = 0;
     for (int r = blockIdx.x * 4 + w; r < v.N; r += gridDim.x * 4) {
@@ -1890,29 +1892,25 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
                    (__float_as_uint(q.y) & 0x7f800000u) == 0x7f800000u ||
                    (__float_as_uint(q.z) & 0x7f800000u) == 0x7f800000u ||
                    (__float_as_uint(q.w) & 0x7f800000u) == 0x7f800000u;
-            *reinterpret_cast<float4*>(y + j) = q;
             s0 = fmaf(q.x, q.x, s0);
             s1 = fmaf(q.y, q.y, s1);
             s2 = fmaf(q.z, q.z, s2);
             s3 = fmaf(q.w, q.w, s3);
             if (split) {
                 const float e[4] = {q.x, q.y, q.z, q.w};
-                uint16_t b1[4], b2[4], b3[4];
+                uint16_t b1[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     b1[c] = bf16_rne(e[c]);
                     const float r1 = e[c] - bf16_to_f32(b1[c]);
-                    b2[c] = bf16_rne(r1);
-                    b3[c] = bf16_rne(r1 - bf16_to_f32(b2[c]));
-                    used |= (b2[c] ? 1u : 0u) | (b3[c] ? 2u : 0u);
+                    const uint16_t b2 = bf16_rne(r1);
+                    const uint16_t b3 = bf16_rne(r1 - bf16_to_f32(b2));
+                    used |= (b2 ? 1u : 0u) | (b3 ? 2u : 0u);
                 }
-                const size_t at = (size_t)r * dp + j;
-                *reinterpret_cast<uint2*>(v.Xs + at) =
+                *reinterpret_cast<uint2*>(v.Xs + (size_t)r * dp + j) =
                     make_uint2(b1[0] | ((uint32_t)b1[1] << 16), b1[2] | ((uint32_t)b1[3] << 16));
-                *reinterpret_cast<uint2*>(v.Xs + total + at) =
-                    make_uint2(b2[0] | ((uint32_t)b2[1] << 16), b2[2] | ((uint32_t)b2[3] << 16));
-                *reinterpret_cast<uint2*>(v.Xs + 2 * total + at) =
-                    make_uint2(b3[0] | ((uint32_t)b3[1] << 16), b3[2] | ((uint32_t)b3[3] << 16));
+            } else {
+                *reinterpret_cast<float4*>(y + j) = q;
             }
         }
         float sn = (s0 + s1) + (s2 + s3);
@@ -1934,6 +1932,43 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
 
 void launch_prep(const float* X, const Views& v, int split, hipStream_t s) {
     hipLaunchKernelGGL(k_prep, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, X, v, split);
+}
+
+// Split form with a later plane in use: the padded FP32 rows and planes 2
+// and 3 (plane 1 is already written by k_prep).
+__global__ __launch_bounds__(256) void k_prep_rest(const float* __restrict__ X, Views v) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int d = v.d, dp = v.dp;
+    const int64_t total = (int64_t)v.N * dp;
+    for (int r = blockIdx.x * 4 + w; r < v.N; r += gridDim.x * 4) {
+        const float* x = X + (size_t)r * d;
+        float* y = v.Xp + (size_t)r * dp;
+        for (int j = 4 * lane; j < dp; j += 256) {
+            float4 q;
+            q.x = j < d ? x[j] : 0.f;
+            q.y = j + 1 < d ? x[j + 1] : 0.f;
+            q.z = j + 2 < d ? x[j + 2] : 0.f;
+            q.w = j + 3 < d ? x[j + 3] : 0.f;
+            *reinterpret_cast<float4*>(y + j) = q;
+            const float e[4] = {q.x, q.y, q.z, q.w};
+            uint16_t b2[4], b3[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float r1 = e[c] - bf16_to_f32(bf16_rne(e[c]));
+                b2[c] = bf16_rne(r1);
+                b3[c] = bf16_rne(r1 - bf16_to_f32(b2[c]));
+            }
+            const size_t at = (size_t)r * dp + j;
+            *reinterpret_cast<uint2*>(v.Xs + total + at) =
+                make_uint2(b2[0] | ((uint32_t)b2[1] << 16), b2[2] | ((uint32_t)b2[3] << 16));
+            *reinterpret_cast<uint2*>(v.Xs + 2 * total + at) =
+                make_uint2(b3[0] | ((uint32_t)b3[1] << 16), b3[2] | ((uint32_t)b3[3] << 16));
+        }
+    }
+}
+
+void launch_prep_rest(const float* X, const Views& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_rest, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, X, v);
 }
 
 // The tiles of k_join_mfma on BF16 MFMA (v_mfma_f32_16x16x32_bf16): lane
@@ -2643,8 +2678,12 @@ __global__ void k_perm_newpos(Views v) {
         v.newpos[c] = (int32_t)(v.offs[c] + v.size[c] - 1u);
 }
 
+// FP32 rows are moved unless the split form uses one plane (then nothing
+// reads them and they were never written).
+__device__ __forceinline__ bool fp32_rows_used(const Views& v) { return !(v.Xs && v.planes == 1); }
+
 __global__ void k_perm_rows(Views v) {
-    const int dp4 = v.dp >> 2;
+    const int dp4 = fp32_rows_used(v) ? v.dp >> 2 : 1;
     const int64_t total = (int64_t)v.N * dp4;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int p = (int)(i / dp4), c = (int)(i - (int64_t)p * dp4);
@@ -2653,7 +2692,9 @@ __global__ void k_perm_rows(Views v) {
             atomicOr((unsigned long long*)&v.counters[kCntError], 64ull);
             continue;
         }
-        reinterpret_cast<float4*>(v.Xp2 + (size_t)q * v.dp)[c] = reinterpret_cast<const float4*>(v.Xp + (size_t)p * v.dp)[c];
+        if (fp32_rows_used(v))
+            reinterpret_cast<float4*>(v.Xp2 + (size_t)q * v.dp)[c] =
+                reinterpret_cast<const float4*>(v.Xp + (size_t)p * v.dp)[c];
         if (c == 0) {
             v.orig2[q] = v.orig[p];
             v.nrm2[q] = v.nrm[p];
@@ -2687,7 +2728,7 @@ __global__ void k_perm_rows_i8(Views v) {
 
 __global__ void k_perm_rows_split(Views v) {
     const int dp8 = v.dp >> 3;   // 16-byte groups per plane row (dp % 32 == 0)
-    const int64_t per = (int64_t)v.N * dp8, total = 3 * per;
+    const int64_t per = (int64_t)v.N * dp8, total = (int64_t)v.planes * per;   // planes in use
     const size_t plane = (size_t)v.N * v.dp;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(i / per);

@@ -15,6 +15,7 @@
 #include <utility>
 #include <vector>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "knng.h"
@@ -323,11 +324,47 @@ struct knng_ctx {
     int perm_levels;
     bool has_graph;
     knng_stats stats;
-    hipEvent_t ev[6];
+    hipEvent_t ev[10];   // phase events of odd (0..3) and even (6..9) iterations; 4, 5: permutation
     uint64_t hc[kNumCounters];
+    uint64_t* hslot;     // pinned: the counters of iteration t at hslot[t * kNumCounters]
+    uint64_t* dslot;     // the same memory as the device addresses it
 };
 
 namespace {
+
+// Pinned counter slots (a few KB each, mapped into the device's address
+// space), kept for reuse across contexts so a build pays no host allocation.
+constexpr size_t kSlotBytes = (size_t)(KNNG_MAX_ITERS + 1) * kNumCounters * sizeof(uint64_t);
+std::mutex g_slot_mu;
+std::vector<std::pair<uint64_t*, uint64_t*>> g_slot_free;   // {host, device}
+
+bool slot_take(uint64_t** host, uint64_t** dev) {
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        if (!g_slot_free.empty()) {
+            *host = g_slot_free.back().first;
+            *dev = g_slot_free.back().second;
+            g_slot_free.pop_back();
+            return true;
+        }
+    }
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, kSlotBytes, hipHostMallocMapped) != hipSuccess) return false;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+        (void)hipHostFree(h);
+        return false;
+    }
+    std::memset(h, 0, kSlotBytes);
+    *host = static_cast<uint64_t*>(h);
+    *dev = static_cast<uint64_t*>(d);
+    return true;
+}
+
+void slot_give(uint64_t* host, uint64_t* dev) {
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_slot_free.emplace_back(host, dev);
+}
 
 knng_status read_counters(knng_ctx* c) {
     HIP_TRY(hipMemcpyAsync(c->hc, c->v.counters, sizeof(c->hc), hipMemcpyDeviceToHost, c->stream));
@@ -388,42 +425,50 @@ knng_status do_permute(knng_ctx* c) {
     return KNNG_OK;
 }
 
-knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
-    if (!c->has_graph) return fail(KNNG_EINVAL, "no graph: call knng_init_graph or knng_load_graph first");
-    if (c->t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "iteration limit of the statistics reached");
+hipEvent_t* phase_events(knng_ctx* c, int t) { return (t & 1) ? &c->ev[0] : &c->ev[6]; }
+
+// Enqueues iteration t (sampling, join, merge). thr >= 0: the device records
+// whether the stop rule held (changes < thr) so that an iteration enqueued
+// ahead of the host's decision returns at once.
+knng_status enqueue_iteration(knng_ctx* c, int t, double thr) {
     const Views& v = c->v;
     hipStream_t s = c->stream;
-    const int t = c->t + 1;
+    hipEvent_t* E = phase_events(c, t);
     const uint64_t st = stream_state(c->p.seed, 2, (uint64_t)t);
     launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
     launch_fill_u64(v.counters, 0ull, kNumCounters, s);
-    HIP_TRY(hipEventRecord(c->ev[0], s));
+    // phase events: start of sampling (E0), start / end of the join (E1,
+    // E2), end of the merge (E3), stamped by the dispatches themselves
     if (v.rev_S) {
-        launch_rev_partition(v, st, t, s);
+        launch_rev_partition(v, st, t, s, E[0]);
     } else {
-        launch_rev_hist(v, s);
+        launch_rev_hist(v, s, E[0]);
         launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
         launch_rev_scatter(v, st, t, s);
     }
     launch_select(v, st, t, s);
-    HIP_TRY(hipEventRecord(c->ev[1], s));
     if (c->plan.bf16)
-        launch_join_bf16(v, s);
+        launch_join_bf16(v, s, E[1], E[2]);
     else if (c->plan.path == KNNG_PATH_MFMA_I8)
-        launch_join_i8(v, s);
+        launch_join_i8(v, s, E[1], E[2]);
     else if (c->plan.path == KNNG_PATH_MFMA_BF16X3)
-        launch_join_split(v, s);
+        launch_join_split(v, s, E[1], E[2]);
     else if (c->plan.path == KNNG_PATH_MFMA)
-        launch_join_mfma(v, s);
+        launch_join_mfma(v, s, E[1], E[2]);
     else
-        launch_join_valu(v, s);
-    HIP_TRY(hipEventRecord(c->ev[2], s));
+        launch_join_valu(v, s, E[1], E[2]);
     launch_merge(v, s);
-    launch_finish_counters(v, s);
-    HIP_TRY(hipEventRecord(c->ev[3], s));
+    launch_finish_counters(v, s, E[3], c->dslot + (size_t)t * kNumCounters, thr);
     HIP_TRY(hipGetLastError());
-    knng_status st2 = read_counters(c);
-    if (st2 != KNNG_OK) return st2;
+    return KNNG_OK;
+}
+
+// Waits for iteration t (enqueued last but possibly one) and records its
+// statistics.
+knng_status finish_iteration(knng_ctx* c, int t, int64_t* evals, int64_t* changes) {
+    hipEvent_t* E = phase_events(c, t);
+    HIP_TRY(hipEventSynchronize(E[3]));
+    std::memcpy(c->hc, c->hslot + (size_t)t * kNumCounters, sizeof(c->hc));
     if (c->hc[kCntError]) {
         char buf[96];
         snprintf(buf, sizeof buf, "device invariant failed in iteration %d (code %llu)", t,
@@ -438,18 +483,29 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
     S.changes[i] = ch;
     S.proposals[i] = (int64_t)c->hc[kCntProposals];
     S.rescored[i] = (int64_t)c->hc[kCntRescored];
-    S.sample_ms[i] = ms_between(c->ev[0], c->ev[1]);
-    S.join_ms[i] = ms_between(c->ev[1], c->ev[2]);
-    S.merge_ms[i] = ms_between(c->ev[2], c->ev[3]);
-    S.iter_ms[i] = ms_between(c->ev[0], c->ev[3]);
+    S.sample_ms[i] = ms_between(E[0], E[1]);
+    S.join_ms[i] = ms_between(E[1], E[2]);
+    S.merge_ms[i] = ms_between(E[2], E[3]);
+    S.iter_ms[i] = ms_between(E[0], E[3]);
     S.iters = t;
     c->t = t;
-    if (t == 1 && c->p.reorder && !c->permuted) {
-        knng_status ps = do_permute(c);
-        if (ps != KNNG_OK) return ps;
-    }
     if (evals) *evals = e;
     if (changes) *changes = ch;
+    return KNNG_OK;
+}
+
+bool permute_after(const knng_ctx* c, int t) { return t == 1 && c->p.reorder && !c->permuted; }
+
+// One iteration, host-driven (step API): no look-ahead.
+knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
+    if (!c->has_graph) return fail(KNNG_EINVAL, "no graph: call knng_init_graph or knng_load_graph first");
+    if (c->t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "iteration limit of the statistics reached");
+    const int t = c->t + 1;
+    knng_status st = enqueue_iteration(c, t, -1.0);
+    if (st != KNNG_OK) return st;
+    st = finish_iteration(c, t, evals, changes);
+    if (st != KNNG_OK) return st;
+    if (permute_after(c, t)) return do_permute(c);
     return KNNG_OK;
 }
 
@@ -533,8 +589,14 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
             return fail(KNNG_EDEVICE, "hipEventCreate failed");
         }
     }
+    if (!slot_take(&c->hslot, &c->dslot)) {
+        knng_destroy(c);
+        return fail(KNNG_EDEVICE, "pinned counter slots: hipHostMalloc failed");
+    }
+    c->v.stop = c->v.flag + kStopFlag;
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
     launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
+    launch_fill_u32(c->v.stop, 0u, 1, c->stream);
     if (P.path == KNNG_PATH_VALU) {
         launch_pad_rows(dX, c->v, c->stream);
     } else {
@@ -570,6 +632,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
 knng_status knng_init_graph(knng_ctx* c) {
     if (!c) return fail(KNNG_EINVAL, "ctx is NULL");
     if (c->permuted) return fail(KNNG_EINVAL, "init after permutation is not supported");
+    launch_fill_u32(c->v.stop, 0u, 1, c->stream);
     launch_init(c->v, stream_state(c->p.seed, 1, 0), dist_mode(c), c->stream);
     HIP_TRY(hipGetLastError());
     c->t = 0;
@@ -583,6 +646,7 @@ knng_status knng_load_graph(knng_ctx* c, const int32_t* d_ids, const uint8_t* d_
     if (c->permuted) return fail(KNNG_EINVAL, "load after permutation is not supported");
     if (t < 0 || t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "t out of range");
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
+    launch_fill_u32(c->v.stop, 0u, 1, c->stream);
     launch_load_rows(c->v, d_ids, d_flags, dist_mode(c), c->stream);
     HIP_TRY(hipGetLastError());
     knng_status rs = read_counters(c);
@@ -634,6 +698,10 @@ knng_status knng_get_stats(const knng_ctx* c, knng_stats* stats) {
 
 void knng_destroy(knng_ctx* c) {
     if (!c) return;
+    if (c->hslot) {
+        (void)hipStreamSynchronize(c->stream);   // no kernel of this context writes the slots any more
+        slot_give(c->hslot, c->dslot);
+    }
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;
@@ -663,12 +731,22 @@ knng_status knng_build(const float* dX, int64_t N, int32_t d, const knng_params*
     if (s != KNNG_OK) { cleanup(); return s; }
     (void)hipEventRecord(e1, c->stream);
     const double thr = (double)params->delta * (double)N * (double)params->K;
+    const int T = std::min(params->max_iters, KNNG_MAX_ITERS);
     bool conv = false;
-    for (int it = 0; it < params->max_iters; ++it) {
+    // One iteration ahead: iteration t + 1 is enqueued before the host reads
+    // iteration t's counters, and returns at once on the device if t met the
+    // stop rule (the same test, c_t < delta N K, on both sides). Not across
+    // the permutation after iteration 1.
+    if (T > 0 && (s = enqueue_iteration(c, 1, thr)) != KNNG_OK) { cleanup(); return s; }
+    for (int t = 1; t <= T; ++t) {
+        const bool ahead = t < T && !permute_after(c, t);
+        if (ahead && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) { cleanup(); return s; }
         int64_t e = 0, ch = 0;
-        s = do_iterate(c, &e, &ch);
+        s = finish_iteration(c, t, &e, &ch);
+        if (s == KNNG_OK && permute_after(c, t)) s = do_permute(c);
         if (s != KNNG_OK) { cleanup(); return s; }
         if ((double)ch < thr) { conv = true; break; }
+        if (!ahead && t < T && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) { cleanup(); return s; }
     }
     launch_finalize(c->v, d_ids, d_dists, nullptr, c->stream);
     (void)hipEventRecord(e2, c->stream);

@@ -112,12 +112,17 @@ struct Views {
     int32_t* ni2;       // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
+    uint32_t* stop;     // single build: set when the stop rule held (or a device
+                        // invariant failed); the kernels of an iteration enqueued
+                        // ahead then return at once. Null in the batched form.
 };
 
 size_t scan_tmp_words(int n);
 size_t partial_words();
 
-// kernels (launchers; all enqueue on `s`)
+// kernels (launchers; all enqueue on `s`). Launchers that bound a timed phase
+// take optional events e0 / e1, stamped at the start / end of their first /
+// last kernel by the dispatch itself (no marker packets between kernels).
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
@@ -128,7 +133,7 @@ void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, 
 // magnitude <= 2^24; flag[9] = min, flag[10] = max (int32) of the others
 void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t s);
 void launch_make_i8(const Views& v, int32_t shift, hipStream_t s);
-void launch_join_i8(const Views& v, hipStream_t s);
+void launch_join_i8(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_make_split(const Views& v, hipStream_t s);
 // one pass over X for the MFMA forms: padded rows, norms, identity positions,
 // finiteness check and (split != 0) the split-BF16 planes
@@ -136,8 +141,8 @@ void launch_prep(const float* X, const Views& v, int split, hipStream_t s);
 // split form with planes > 1 (or a reader of the FP32 rows): padded FP32 rows
 // and planes 2 and 3
 void launch_prep_rest(const float* X, const Views& v, hipStream_t s);
-void launch_join_split(const Views& v, hipStream_t s);
-void launch_rev_hist(const Views& v, hipStream_t s);
+void launch_join_split(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_rev_hist(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr);
 // batched form
 void launch_batch_setup(const Views& v, hipStream_t s);
 void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s);
@@ -146,16 +151,20 @@ void launch_fill_i32(int32_t* p, int32_t val, int64_t n, hipStream_t s);
 void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
 void launch_rev_scatter(const Views& v, uint64_t st_sample, int t, hipStream_t s);
 // reverse buckets (roff, rev) by the counting sort; staging in the proposal buffer
-void launch_rev_partition(const Views& v, uint64_t st_sample, int t, hipStream_t s);
+void launch_rev_partition(const Views& v, uint64_t st_sample, int t, hipStream_t s, hipEvent_t e0 = nullptr);
 constexpr int kRevMaxS = 8192;    // super-buckets (LDS counters of one block)
 constexpr int kRevMaxShift = 12;  // largest super-bucket: 4096 positions
 void launch_select(const Views& v, uint64_t st_sample, int t, hipStream_t s);
-void launch_join_valu(const Views& v, hipStream_t s);
-void launch_join_mfma(const Views& v, hipStream_t s);
+void launch_join_valu(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_make_bf16(const Views& v, hipStream_t s);
-void launch_join_bf16(const Views& v, hipStream_t s);
+void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_merge(const Views& v, hipStream_t s);
-void launch_finish_counters(const Views& v, hipStream_t s);
+// Sums the merge's partials into the counters; slot (host-visible, may be
+// null) receives a copy of all counters; thr >= 0 sets *v.stop when
+// changes < thr or a device invariant failed.
+void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr);
+constexpr int kStopFlag = 12;   // index of the stop word in the device flags
 void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);
 void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t* counts, hipStream_t s);
 int perm_levels_max();

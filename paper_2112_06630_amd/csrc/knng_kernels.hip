@@ -16,6 +16,8 @@
 // atomic or scheduling order.
 #include <climits>
 
+#include <hip/hip_ext.h>
+
 #include "knng_impl.h"
 
 namespace knng {
@@ -134,6 +136,10 @@ __device__ __forceinline__ void wave_bitonic_clean(uint64_t& k, uint32_t& v) {
     for (int j = 32; j > 0; j >>= 1) cmpx(k, v, j, true);
 }
 
+// An iteration enqueued ahead of the host's stop decision returns at once
+// when the previous iteration met the stop rule.
+__device__ __forceinline__ bool stopped(const Views& v) { return v.stop && *v.stop != 0u; }
+
 // Batched form: position p belongs to dataset ds[p]; a single build has no
 // dataset table and every position is active.
 __device__ __forceinline__ bool pos_active(const Views& v, int p) { return !v.ds || v.active[v.ds[p]] != 0u; }
@@ -225,6 +231,16 @@ static inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
     if (g < 1) g = 1;
     if (g > cap) g = cap;
     return (int)g;
+}
+
+// Launch with optional start / stop events recorded by the dispatch packet.
+template <typename... P, typename... A>
+static void launch_timed(void (*kernel)(P...), dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, A... args) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, g, b, (uint32_t)lds, s, e0, e1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, lds, s, args...);
 }
 
 // ------------------------------------------------------------------ fills
@@ -626,6 +642,7 @@ void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStr
 // ------------------------------------------------------------------ reverse lists (a2)
 
 __global__ void k_rev_hist(Views v) {
+    if (stopped(v)) return;
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
@@ -634,13 +651,14 @@ __global__ void k_rev_hist(Views v) {
     }
 }
 
-void launch_rev_hist(const Views& v, hipStream_t s) {
+void launch_rev_hist(const Views& v, hipStream_t s, hipEvent_t e0) {
     const int64_t NK = (int64_t)v.N * v.K;
-    hipLaunchKernelGGL(k_rev_hist, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, v);
+    launch_timed(k_rev_hist, dim3(grid_for(NK, 256, 1 << 16)), dim3(256), 0, s, e0, nullptr, v);
 }
 
 // Each edge u->v (flag f) becomes the reverse entry {w, orig u, pos u | f} of v.
 __global__ void k_rev_scatter(Views v, uint64_t st0, int t) {
+    if (stopped(v)) return;
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < NK; e += (int64_t)gridDim.x * blockDim.x) {
@@ -673,6 +691,7 @@ void launch_rev_scatter(const Views& v, uint64_t st, int t, hipStream_t s) {
 // offsets roff and places the entries. Orders inside a range depend on LDS
 // atomic order only, and every reader of a bucket sorts it by key.
 __global__ __launch_bounds__(1024) void k_rev_count(Views v) {
+    if (stopped(v)) return;
     extern __shared__ uint32_t s_cnt[];
     const int S = v.rev_S, B = gridDim.x;
     const int64_t NK = (int64_t)v.N * v.K;
@@ -689,6 +708,7 @@ __global__ __launch_bounds__(1024) void k_rev_count(Views v) {
 }
 
 __global__ __launch_bounds__(1024) void k_rev_part(Views v, uint64_t st0, int t) {
+    if (stopped(v)) return;
     extern __shared__ uint32_t s_cur[];
     const int S = v.rev_S, B = gridDim.x;
     const int64_t NK = (int64_t)v.N * v.K;
@@ -711,6 +731,7 @@ __global__ __launch_bounds__(1024) void k_rev_part(Views v, uint64_t st0, int t)
 }
 
 __global__ __launch_bounds__(1024) void k_rev_bucket(Views v) {
+    if (stopped(v)) return;
     extern __shared__ uint32_t s_loc[];   // [R] counts, then cursors
     __shared__ uint32_t s_w[16];
     const int R = 1 << v.rev_shift, B = v.rev_B;
@@ -751,9 +772,9 @@ __global__ __launch_bounds__(1024) void k_rev_bucket(Views v) {
     }
 }
 
-void launch_rev_partition(const Views& v, uint64_t st, int t, hipStream_t s) {
+void launch_rev_partition(const Views& v, uint64_t st, int t, hipStream_t s, hipEvent_t e0) {
     const size_t lds_s = (size_t)v.rev_S * 4;
-    hipLaunchKernelGGL(k_rev_count, dim3(v.rev_B), dim3(1024), lds_s, s, v);
+    launch_timed(k_rev_count, dim3(v.rev_B), dim3(1024), lds_s, s, e0, nullptr, v);
     launch_scan(v.rev_h, v.rev_hs, v.rev_S * v.rev_B, v.rev_tmp, s);
     hipLaunchKernelGGL(k_rev_part, dim3(v.rev_B), dim3(1024), lds_s, s, v, st, t);
     hipLaunchKernelGGL(k_rev_bucket, dim3(v.rev_S), dim3(1024), ((size_t)4 << v.rev_shift), s, v);
@@ -863,6 +884,7 @@ __device__ void select_radix_thresholds(const Views& v, uint64_t st, int u, uint
 // staged in LDS (after a radix prefilter when they exceed the stage), ranks
 // by counting over the stage.
 __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int t) {
+    if (stopped(v)) return;
     __shared__ SelLds L;
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K, C = v.C;
@@ -1171,6 +1193,7 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
 // take the threshold select in the same wave when 2C <= 60 (their latency
 // hides behind the small pools), else k_select_large (big[u] = 1).
 __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int t) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_key[kSelWaves][64];
     __shared__ uint32_t s_idx[kSelWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -1316,6 +1339,7 @@ bool join_valu_fits(const Views& v) { return join_valu_wave_bytes(v) * kJoinWave
 // once to count proposals per member, once (recomputing the cheap low-d
 // distance) to write them.
 __global__ __launch_bounds__(256) void k_join_valu(Views v) {
+    if (stopped(v)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int C2 = 2 * v.C, dp = v.dp, dp4 = dp >> 2, K = v.K;
@@ -1374,9 +1398,9 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
     }
 }
 
-void launch_join_valu(const Views& v, hipStream_t s) {
+void launch_join_valu(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = join_valu_wave_bytes(v) * kJoinWaves;
-    hipLaunchKernelGGL(k_join_valu, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), lds, s, v);
+    launch_timed(k_join_valu, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), lds, s, e0, e1, v);
 }
 
 // High-d local join on FP32 MFMA (v_mfma_f32_16x16x4f32): per owner, the
@@ -1390,6 +1414,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxCT = 4;   // m = 2C <= 64
 
 __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
@@ -1501,6 +1526,7 @@ typedef int int32x4 __attribute__((ext_vector_type(4)));
 constexpr int kI8Ahead = 2;   // 64-byte steps loaded before their instructions
 
 __global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
@@ -1605,12 +1631,12 @@ __global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
     }
 }
 
-void launch_join_i8(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_join_i8, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+void launch_join_i8(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed(k_join_i8, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
 }
 
-void launch_join_mfma(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_join_mfma, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed(k_join_mfma, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
 }
 
 // ------------------------------------------------------------------ precision form (a9)
@@ -1684,6 +1710,7 @@ __device__ __forceinline__ float dist_wave(const float* __restrict__ a, const fl
 constexpr int kBfMaxSurv = 3 * 32 * 32 / 2;   // survivor pairs per owner <= e(u) <= C(C-1)/2 + C^2 < 1.5 C^2, C <= 32
 
 __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
@@ -1818,8 +1845,8 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     if (lane == 0 && rescored) atomicAdd((unsigned long long*)&v.counters[kCntRescored], (unsigned long long)rescored);
 }
 
-void launch_join_bf16(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_join_bf16, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, v);
+void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    launch_timed(k_join_bf16, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
 }
 
 // ------------------------------------------------------------------ split-BF16 Gram form
@@ -1980,6 +2007,7 @@ void launch_prep_rest(const float* X, const Views& v, hipStream_t s) {
 // so row tiles 0 and 1 only: 2 MaxCT - 1 tiles.
 template <int MaxCT, int Planes>
 __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v) {
+    if (stopped(v)) return;
     constexpr int kSplitTiles = 2 * MaxCT - 1;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
@@ -2095,21 +2123,21 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
 }
 
 template <int MaxCT>
-static void launch_join_split_ct(const Views& v, hipStream_t s) {
+static void launch_join_split_ct(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
     if (v.planes == 1)
-        hipLaunchKernelGGL((k_join_split<MaxCT, 1>), g, dim3(256), 0, s, v);
+        launch_timed(k_join_split<MaxCT, 1>, g, dim3(256), 0, s, e0, e1, v);
     else if (v.planes == 2)
-        hipLaunchKernelGGL((k_join_split<MaxCT, 2>), g, dim3(256), 0, s, v);
+        launch_timed(k_join_split<MaxCT, 2>, g, dim3(256), 0, s, e0, e1, v);
     else
-        hipLaunchKernelGGL((k_join_split<MaxCT, 3>), g, dim3(256), 0, s, v);
+        launch_timed(k_join_split<MaxCT, 3>, g, dim3(256), 0, s, e0, e1, v);
 }
 
-void launch_join_split(const Views& v, hipStream_t s) {
+void launch_join_split(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (2 * v.C <= 48)
-        launch_join_split_ct<3>(v, s);
+        launch_join_split_ct<3>(v, s, e0, e1);
     else
-        launch_join_split_ct<4>(v, s);
+        launch_join_split_ct<4>(v, s, e0, e1);
 }
 
 // ------------------------------------------------------------------ merge (a5)
@@ -2283,6 +2311,7 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
 
 // One wave per target; buckets above kHubProposals go to k_merge_hubs.
 __global__ __launch_bounds__(256) void k_merge(Views v) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_k[kMergeWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int K = v.K;
@@ -2334,6 +2363,7 @@ __global__ __launch_bounds__(256) void k_merge(Views v) {
 // partial lists (from LDS) into its own. Equal to folding the whole bucket,
 // since the K smallest of a union are the K smallest of the partial results.
 __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_k[kHubWaves][64];
     __shared__ uint64_t s_lk[kHubWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -2375,7 +2405,8 @@ void launch_merge(const Views& v, hipStream_t s) {
 
 size_t partial_words() { return 3 * (size_t)(kMergeBlocks + kHubBlocks); }
 
-__global__ __launch_bounds__(1024) void k_finish_counters(Views v) {
+__global__ __launch_bounds__(1024) void k_finish_counters(Views v, uint64_t* slot, double thr) {
+    if (stopped(v)) return;
     __shared__ uint64_t s_a[16], s_b[16], s_c[16];
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     uint64_t a = 0, b = 0, c = 0;
@@ -2405,11 +2436,19 @@ __global__ __launch_bounds__(1024) void k_finish_counters(Views v) {
         v.counters[kCntChanges] = sa;
         v.counters[kCntProposals] = sb;
         v.counters[kCntPairs2] = 2ull * sc;
+        if (slot) {
+            for (int i = 0; i < kNumCounters; ++i) slot[i] = v.counters[i];
+            __threadfence_system();
+        }
+        if (thr >= 0.0 && v.stop) {
+            const bool met = (double)sa < thr || v.counters[kCntError] != 0ull;
+            *v.stop = met ? 1u : 0u;
+        }
     }
 }
 
-void launch_finish_counters(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(1024), 0, s, v);
+void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr) {
+    launch_timed(k_finish_counters, dim3(1), dim3(1024), 0, s, nullptr, e1, v, slot, thr);
 }
 
 // ------------------------------------------------------------------ finalize (a8)

@@ -350,6 +350,22 @@ def test_max_K(knng, path, N, d, K, rho, hi, seed):
     exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 6, seed, path=path)
 
 
+@pytest.mark.parametrize("T", [1, 2, 3])
+@pytest.mark.parametrize("path", ["valu", "bf16x3"])
+def test_iteration_cap(knng, T, path):
+    """delta = 0 never stops early here: the build runs exactly T iterations
+    (the iteration enqueued ahead of the host's decision is never issued
+    past T) and equals the oracle's T-iteration graph."""
+    X = synth.integer_points(700, 64, 9, 21)
+    ref = oracle.build_graph(X, 10, 1.0, 0.0, T, 21)
+    assert ref.iters == T and ref.changes[-1] > 0
+    ids, dists, st = knng.build(dev(X), 10, 1.0, 0.0, T, 21, path=path)
+    assert st["iters"] == T and not st["converged"]
+    assert st["evals"] == ref.evals.tolist() and st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)
+
+
 def test_zero_iterations_returns_init(knng):
     X, _ = synth.config(1, N=500)
     ids, dists, st = knng.build(dev(X), 10, 1.0, 0.001, 0, 4)

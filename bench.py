@@ -196,7 +196,10 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
     """Writes profiles/traffic.json: HBM bytes per launch of each knng kernel
     from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch), each scaled by what the counter reads for the plain copy of
-    copy_mib MiB that bench.py --copy-probe-mib issues in the same run."""
+    copy_mib MiB that bench.py --copy-probe-mib issues in the same run.
+    Dispatches of the iteration a build enqueues ahead of its stop decision
+    return at once; those (fetch below 1% of the kernel's largest) are left
+    out of the per-launch figures."""
     import csv
     import collections
 
@@ -220,19 +223,21 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
         raise SystemExit("copy probe not found in the counter runs")
     f_scale = copy_mib * 1024.0 / fprobe   # a copy reads copy_mib MiB
     w_scale = copy_mib * 1024.0 / wprobe   # and writes copy_mib MiB
-    out = {"_scale": {"fetch": f_scale, "write": w_scale, "copy_mib": copy_mib}, "_command": command}
+    out = {"_scale": {"fetch": f_scale, "write": w_scale, "copy_mib": copy_mib,
+                      "probe_fetch_kib": fprobe, "probe_write_kib": wprobe}, "_command": command}
     for k in sorted(set(fetch) | set(write)):
         if not k.startswith("k_"):
             continue
-        fb = sum(fetch.get(k, [0])) / max(1, len(fetch.get(k, [1]))) * 1024 * f_scale
-        wb = sum(write.get(k, [0])) / max(1, len(write.get(k, [1]))) * 1024 * w_scale
+        fl, wl = fetch.get(k, []), write.get(k, [])
+        keep_f = [x for x in fl if x >= 0.01 * max(fl)] if fl else []
+        keep_w = [y for x, y in zip(fl, wl) if x >= 0.01 * max(fl)] if fl and len(fl) == len(wl) else wl
+        fb = sum(keep_f) / max(1, len(keep_f)) * 1024 * f_scale
+        wb = sum(keep_w) / max(1, len(keep_w)) * 1024 * w_scale
         out[k] = {"source_hash": kernel_source_hash(), "bytes_per_launch": int(fb + wb),
                   "fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
-                  "launches": len(fetch.get(k, []))}
+                  "launches": len(keep_f), "early_exits": len(fl) - len(keep_f)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    prev = json.load(open(path)) if os.path.exists(path) else {}
-    prev.update({k: v for k, v in out.items()})
-    json.dump(prev, open(path, "w"), indent=1, sort_keys=True)
+    json.dump(out, open(path, "w"), indent=1, sort_keys=True)
     print(json.dumps({k: out[k] for k in out if not k.startswith("_")}, indent=1))
 
 

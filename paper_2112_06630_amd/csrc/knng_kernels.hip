@@ -2179,97 +2179,137 @@ __device__ __forceinline__ void fold_sorted(uint64_t pk, uint64_t& key, uint32_t
     wave_bitonic_clean(key, pf);
 }
 
-// Folds proposals src[c0 .. n) (chunks of 64, every `stride` elements) into
-// the list held one entry per lane in (key, pf), ascending, +inf beyond K.
-// A proposal is dropped when it is not below the current K-th key, or its id
-// is in the snapshot list (snap: ids, lanes < K; compared by id, since the
-// list's keys may come from the initial graph, whose distances are summed in
-// another order than the join's). An id already taken from another proposal
-// carries the same key (the join gives a pair one key) and is dropped as a
-// repeat. A chunk with
-// few survivors inserts them one by one (ballot rank, shift up); a larger one
-// is sorted (bitonic) and folded into the list (fold_sorted). Repeated keys
-// would each take a slot of the 64 smallest, so when one lands among the
-// first K the fold is redone from the list as it was, with every chunk key
-// that repeats its neighbour or a list key (binary search in LDS) removed
-// and the rest compacted in order (sk: 64 slots of this wave).
-__device__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint32_t stride,
-                             int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth,
-                             uint64_t* sk) {
+constexpr int kInsertMax = 4;   // proposals merged one by one rather than sorted
+
+// Merges proposals q (lanes in qm; each below kth when it was taken and not
+// a snapshot id; +inf in the other lanes) into the list held one entry per
+// lane in (key, pf), ascending, +inf beyond K. A few are inserted one by one
+// (ballot rank, shift up), skipping any no longer below the K-th key or whose
+// id is already in the list (same pair, same key: the join gives a pair one
+// key). More are sorted (bitonic) and folded into the list (fold_sorted).
+// Repeated keys would each take a slot of the 64 smallest, so when one lands
+// among the first K the fold is redone from the list as it was, with every
+// key that repeats its neighbour or a list key (binary search in LDS)
+// removed and the rest compacted in order (sk: 64 slots of this wave).
+__device__ __forceinline__ void merge_pending(uint64_t q, uint64_t qm, int K, uint64_t& key, uint32_t& pf,
+                                              uint64_t& kth, uint64_t* sk) {
     const int lane = lane_id();
-    uint64_t nk = ~0ull;
-    if (c0 + (uint32_t)lane < n) nk = pks[c0 + lane];
-    for (; c0 < n; c0 += stride) {
-        uint64_t pk = nk;   // NEW entries: the position is found when the id enters the list
-        // next chunk in flight while this one is merged
-        nk = ~0ull;
-        if (c0 + stride + (uint32_t)lane < n) nk = pks[c0 + stride + lane];
-        bool ok = pk < kth;
-        if (ballot(ok) == 0) continue;
-        // ids are below 2^31, so (a ^ b) - 1 has bit 31 set exactly when a == b:
-        // lane-local arithmetic, no lane-mask work per snapshot entry
-        const uint32_t pid = (uint32_t)pk;
-        uint32_t hit = 0u;
-        int k = 0;
-        for (; k + 4 <= K; k += 4)
-            hit |= ((rl32(snap, k) ^ pid) - 1u) | ((rl32(snap, k + 1) ^ pid) - 1u) |
-                   ((rl32(snap, k + 2) ^ pid) - 1u) | ((rl32(snap, k + 3) ^ pid) - 1u);
-        for (; k < K; ++k) hit |= (rl32(snap, k) ^ pid) - 1u;
-        ok &= (hit >> 31) == 0u;
-        uint64_t mask = ballot(ok);
-        if (mask == 0) continue;
-        if (__popcll(mask) <= 4) {
-            while (mask) {
-                const int j = __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
-                const uint64_t x = rl64(pk, j);
-                if (x >= kth) continue;
-                if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;  // same id, same key
-                const int at = __popcll(ballot(lane < K && key < x));
-                const uint64_t ku = shfl_up64(key, 1);
-                const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
-                if (lane > at && lane < K) {
-                    key = ku;
-                    pf = pu;
-                }
-                if (lane == at) {
-                    key = x;
-                    pf = kPosUnknown;
-                }
-                kth = rl64(key, K - 1);
+    if (__popcll(qm) <= kInsertMax) {
+        while (qm) {
+            const int j = __ffsll((long long)qm) - 1;
+            qm &= qm - 1;
+            const uint64_t x = rl64(q, j);
+            if (x >= kth) continue;
+            if (ballot(lane < K && (uint32_t)key == (uint32_t)x)) continue;
+            const int at = __popcll(ballot(lane < K && key < x));
+            const uint64_t ku = shfl_up64(key, 1);
+            const uint32_t pu = (uint32_t)__shfl_up((int)pf, 1);
+            if (lane > at && lane < K) {
+                key = ku;
+                pf = pu;
             }
-        } else {
-            if (!ok) pk = ~0ull;
-            wave_sort_keys(pk);
-            const uint64_t k0 = key;
-            const uint32_t f0 = pf;
-            fold_sorted(pk, key, pf);
-            const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
-            if (ballot(lane > 0 && lane < K && key != ~0ull && prevk == key)) {
-                sk[lane] = k0;
-                wave_sync();
-                int lo = 0;   // keys of the list below pk (at most 63)
-                for (int st = 32; st > 0; st >>= 1) lo += sk[lo + st - 1] < pk ? st : 0;
-                const uint64_t prevp = shfl_up64(pk, 1);
-                const bool keep = pk != ~0ull && sk[lo] != pk && !(lane > 0 && prevp == pk);
-                const uint64_t km = ballot(keep);
-                wave_sync();
-                sk[lane] = ~0ull;
-                wave_sync();
-                if (keep) sk[mbcnt(km)] = pk;
-                wave_sync();
-                pk = sk[lane];
-                wave_sync();
-                key = k0;
-                pf = f0;
-                fold_sorted(pk, key, pf);
-            }
-            if (lane >= K) {
-                key = ~0ull;
-                pf = 0u;
+            if (lane == at) {
+                key = x;
+                pf = kPosUnknown;
             }
             kth = rl64(key, K - 1);
         }
+        return;
+    }
+    wave_sort_keys(q);
+    const uint64_t k0 = key;
+    const uint32_t f0 = pf;
+    fold_sorted(q, key, pf);
+    const uint64_t prevk = shfl_up64(key, 1);  // all lanes take part in the shuffle
+    if (ballot(lane > 0 && lane < K && key != ~0ull && prevk == key)) {
+        sk[lane] = k0;
+        wave_sync();
+        int lo = 0;   // keys of the list below q (at most 63)
+        for (int st = 32; st > 0; st >>= 1) lo += sk[lo + st - 1] < q ? st : 0;
+        const uint64_t prevq = shfl_up64(q, 1);
+        const bool keep = q != ~0ull && sk[lo] != q && !(lane > 0 && prevq == q);
+        const uint64_t km = ballot(keep);
+        wave_sync();
+        sk[lane] = ~0ull;
+        wave_sync();
+        if (keep) sk[mbcnt(km)] = q;
+        wave_sync();
+        q = sk[lane];
+        wave_sync();
+        key = k0;
+        pf = f0;
+        fold_sorted(q, key, pf);
+    }
+    if (lane >= K) {
+        key = ~0ull;
+        pf = 0u;
+    }
+    kth = rl64(key, K - 1);
+}
+
+// Folds proposals src[c0 .. n) (chunks of 64, every `stride` elements) into
+// the list. A proposal is dropped when it is not below the current K-th key
+// or its id is in the snapshot list (snap: ids, lanes < K; compared by id,
+// since the list's keys may come from the initial graph, whose distances are
+// summed in another order than the join's). Survivors of successive chunks
+// are queued in sk (64 slots of this wave) and merged when the next chunk's
+// survivors do not fit and at the end, so a target whose later chunks thin
+// out sorts a few full queues rather than one sparse chunk at a time; a last
+// chunk with nothing queued is merged straight from the registers.
+__device__ __forceinline__ void merge_chunks(const uint64_t* pks, uint32_t c0, uint32_t n, uint32_t stride,
+                             int K, uint32_t snap, uint64_t& key, uint32_t& pf, uint64_t& kth,
+                             uint64_t* sk) {
+    const int lane = lane_id();
+    int np = 0;   // queued proposals in sk[0 .. np)
+    uint64_t nk = ~0ull;
+    if (c0 + (uint32_t)lane < n) nk = pks[c0 + lane];
+    for (;; c0 += stride) {
+        const bool last = c0 >= n;
+        const uint64_t pk = nk;   // NEW entries: the position is found when the id enters the list
+        bool ok = false;
+        uint64_t mask = 0;
+        int cnt = 0;
+        if (!last) {
+            // next chunk in flight while this one is filtered
+            nk = ~0ull;
+            if (c0 + stride + (uint32_t)lane < n) nk = pks[c0 + stride + lane];
+            ok = pk < kth;
+            if (ballot(ok)) {
+                // ids are below 2^31, so (a ^ b) - 1 has bit 31 set exactly when
+                // a == b: lane-local arithmetic, no lane-mask work per entry
+                const uint32_t pid = (uint32_t)pk;
+                uint32_t hit = 0u;
+                int k = 0;
+                for (; k + 4 <= K; k += 4)
+                    hit |= ((rl32(snap, k) ^ pid) - 1u) | ((rl32(snap, k + 1) ^ pid) - 1u) |
+                           ((rl32(snap, k + 2) ^ pid) - 1u) | ((rl32(snap, k + 3) ^ pid) - 1u);
+                for (; k < K; ++k) hit |= (rl32(snap, k) ^ pid) - 1u;
+                ok &= (hit >> 31) == 0u;
+                mask = ballot(ok);
+                cnt = __popcll(mask);
+            }
+        }
+        // one merge site: the last chunk with an empty queue, a queue that
+        // cannot take this chunk, or the end of the input
+        const bool direct = !last && np == 0 && c0 + stride >= n;
+        if (direct || (np && (last || np + cnt > 64))) {
+            uint64_t q = ok ? pk : ~0ull, qm = mask;
+            if (!direct) {
+                wave_sync();
+                q = lane < np ? sk[lane] : ~0ull;
+                qm = np == 64 ? ~0ull : ((1ull << np) - 1);
+                wave_sync();
+            }
+            merge_pending(q, qm, K, key, pf, kth, sk);
+            if (direct) break;
+            np = 0;
+            ok = ok && pk < kth;
+            mask = ballot(ok);
+            cnt = __popcll(mask);
+        }
+        if (last) break;
+        if (ok) sk[np + (int)mbcnt(mask)] = pk;
+        np += cnt;
     }
 }
 
@@ -2310,7 +2350,7 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
 }
 
 // One wave per target; buckets above kHubProposals go to k_merge_hubs.
-__global__ __launch_bounds__(256) void k_merge(Views v) {
+__global__ __launch_bounds__(256, 8) void k_merge(Views v) {
     if (stopped(v)) return;
     __shared__ uint64_t s_k[kMergeWaves][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -2607,20 +2647,26 @@ __global__ void k_perm_init(Views v) {
     if (blockIdx.x == 0 && threadIdx.x < 4) v.flag[threadIdx.x] = 0u;
 }
 
-// flag[0]: clustering finished (a level hooked nothing); flag[1]: a hook happened this level
+// flag[0]: clustering finished (a level hooked nothing); flag[1]: a hook happened this level.
+// Each component takes its cheapest incident edge (either end) among the
+// first kPermEdges list entries of its points; edge key (D, entry index).
+// One thread per point: the point's own component gets the minimum of its
+// edges in one update, the other ends one each.
 __global__ void k_perm_edges(Views v) {
     if (v.flag[0]) return;
     const int E = min(v.K, kPermEdges);
-    const int64_t total = (int64_t)v.N * E;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int u = (int)(i / E), k = (int)(i - (int64_t)u * E);
-        const uint32_t e = (uint32_t)u * (uint32_t)v.K + (uint32_t)k;
-        const int pv = (int)(v.lpos[e] & kPosMask);
-        const int cu = v.comp[u], cv = v.comp[pv];
-        if (cu == cv) continue;
-        const uint64_t key = ((v.lkey[e] >> 32) << 32) | e;
-        if (key < v.best[cu]) atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)key);
-        if (key < v.best[cv]) atomicMin((unsigned long long*)&v.best[cv], (unsigned long long)key);
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < v.N; u += gridDim.x * blockDim.x) {
+        const int cu = v.comp[u];
+        uint64_t mine = ~0ull;
+        for (int k = 0; k < E; ++k) {
+            const uint32_t e = (uint32_t)u * (uint32_t)v.K + (uint32_t)k;
+            const int cv = v.comp[v.lpos[e] & kPosMask];
+            if (cu == cv) continue;
+            const uint64_t key = ((v.lkey[e] >> 32) << 32) | e;
+            mine = key < mine ? key : mine;
+            if (key < v.best[cv]) atomicMin((unsigned long long*)&v.best[cv], (unsigned long long)key);
+        }
+        if (mine < v.best[cu]) atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)mine);
     }
 }
 
@@ -2810,8 +2856,7 @@ void launch_perm_begin(const Views& v, hipStream_t s) {
 
 void launch_perm_level(const Views& v, uint32_t level, hipStream_t s) {
     const int g = grid_for(v.N, 256, 8192);
-    hipLaunchKernelGGL(k_perm_edges, dim3(grid_for((int64_t)v.N * min(v.K, kPermEdges), 256, 16384)), dim3(256), 0,
-                       s, v);
+    hipLaunchKernelGGL(k_perm_edges, dim3(grid_for(v.N, 256, 16384)), dim3(256), 0, s, v);
     hipLaunchKernelGGL(k_perm_hook, dim3(g), dim3(256), 0, s, v, level);
     hipLaunchKernelGGL(k_perm_jump, dim3(g), dim3(256), 0, s, v, level);
     hipLaunchKernelGGL(k_perm_relabel, dim3(g), dim3(256), 0, s, v);

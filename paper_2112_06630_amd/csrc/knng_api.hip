@@ -435,8 +435,9 @@ knng_status enqueue_iteration(knng_ctx* c, int t, double thr) {
     hipStream_t s = c->stream;
     hipEvent_t* E = phase_events(c, t);
     const uint64_t st = stream_state(c->p.seed, 2, (uint64_t)t);
-    launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
-    launch_fill_u64(v.counters, 0ull, kNumCounters, s);
+    // counters and proposal-bucket cursors are cleared by the previous merge
+    // (and at create); the atomic reverse path counts into rdeg and rcur
+    if (!v.rev_S) launch_fill_u32(v.rdeg, 0u, 2 * (int64_t)v.N, s);
     // phase events: start of sampling (E0), start / end of the join (E1,
     // E2), end of the merge (E3), stamped by the dispatches themselves
     if (v.rev_S) {
@@ -596,6 +597,7 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     c->v.stop = c->v.flag + kStopFlag;
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
     launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
+    launch_fill_u32(c->v.pcnt, 0u, N, c->stream);
     launch_fill_u32(c->v.stop, 0u, 1, c->stream);
     if (P.path == KNNG_PATH_VALU) {
         launch_pad_rows(dX, c->v, c->stream);
@@ -978,6 +980,9 @@ void batch_group_setup(const BatchGroup& g, hipStream_t s) {
 
 void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hipStream_t s) {
     const Views& v = g.v;
+    // the hub list is per iteration (its count must not grow past N); the
+    // other counters accumulate over the iterations (errors are read at the end)
+    launch_fill_u64(v.counters + kCntHubs, 0ull, 1, s);
     launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
     launch_fill_u32(v.chg, 0u, (int64_t)v.N, s);
     if (v.rev_S) {

@@ -160,9 +160,10 @@ void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hi
 void launch_make_bf16(const Views& v, hipStream_t s);
 void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_merge(const Views& v, hipStream_t s);
-// Sums the merge's partials into the counters; slot (host-visible, may be
-// null) receives a copy of all counters; thr >= 0 sets *v.stop when
-// changes < thr or a device invariant failed.
+// Sums the merge's partials into the counters (single builds); slot
+// (host-visible, may be null) receives a copy of all counters, which are then
+// cleared for the next iteration; thr >= 0 sets *v.stop when changes < thr or
+// a device invariant failed.
 void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr);
 constexpr int kStopFlag = 12;   // index of the stop word in the device flags
 void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);

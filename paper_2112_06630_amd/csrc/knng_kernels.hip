@@ -2361,13 +2361,14 @@ __global__ __launch_bounds__(256, 8) void k_merge(Views v) {
         const uint32_t base = bucket_lo(v, p);
         const uint32_t n = min(v.pcnt[p], bucket_lo(v, p + 1) - base);
         if (n == 0) continue;
-        if (n > kHubProposals) {
+        if (n > kHubProposals) {   // its bucket cursor is cleared by k_merge_hubs
             if (lane == 0) {
                 const uint32_t slot = (uint32_t)atomicAdd((unsigned long long*)&v.counters[kCntHubs], 1ull);
                 v.hubs[slot] = (uint32_t)p;
             }
             continue;
         }
+        if (lane == 0) v.pcnt[p] = 0u;   // bucket cursors start the next iteration at zero
         const size_t row = (size_t)p * K;
         uint64_t key = lane < K ? v.lkey[row + lane] : ~0ull;
         uint32_t pf = lane < K ? v.lpos[row + lane] : 0u;
@@ -2395,6 +2396,55 @@ __global__ __launch_bounds__(256, 8) void k_merge(Views v) {
         v.partial[3 * blockIdx.x] = a;
         v.partial[3 * blockIdx.x + 1] = b;
         v.partial[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// Counters of an iteration, by one workgroup of 1024 threads after the
+// merge kernels have written their partial sums: c_t, proposals and e_t summed;
+// all counters copied to the host-visible slot (may be null) and cleared for
+// the next iteration; thr >= 0 sets *v.stop when changes < thr or a device
+// invariant failed.
+__device__ void finish_counters_block(const Views& v, uint64_t* slot, double thr) {
+    __shared__ uint64_t s_a[16], s_b[16], s_c[16];
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    const uint64_t* part = v.partial;
+    uint64_t a = 0, b = 0, c = 0;
+    for (int i = t; i < kMergeBlocks + kHubBlocks; i += 1024) {
+        a += part[3 * i];
+        b += part[3 * i + 1];
+        c += part[3 * i + 2];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += shfl_xor64(a, o);
+        b += shfl_xor64(b, o);
+        c += shfl_xor64(c, o);
+    }
+    if (lane == 0) {
+        s_a[w] = a;
+        s_b[w] = b;
+        s_c[w] = c;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint64_t sa = 0, sb = 0, sc = 0;
+        for (int i = 0; i < 16; ++i) {
+            sa += s_a[i];
+            sb += s_b[i];
+            sc += s_c[i];
+        }
+        uint64_t* cnt = v.counters;
+        cnt[kCntChanges] = sa;
+        cnt[kCntProposals] = sb;
+        cnt[kCntPairs2] = 2ull * sc;
+        if (slot) {
+            for (int i = 0; i < kNumCounters; ++i) slot[i] = cnt[i];
+            __threadfence_system();
+        }
+        if (thr >= 0.0 && v.stop) {
+            const bool met = (double)sa < thr || cnt[kCntError] != 0ull;
+            *v.stop = met ? 1u : 0u;
+        }
+        for (int i = 0; i < kNumCounters; ++i) cnt[i] = 0ull;
     }
 }
 
@@ -2430,6 +2480,7 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
             props += n;
         }
         __syncthreads();
+        if (threadIdx.x == 0) v.pcnt[p] = 0u;   // every wave has read it
     }
     if (w == 0 && lane == 0) {
         v.partial[3 * (kMergeBlocks + blockIdx.x)] = changes;
@@ -2443,53 +2494,18 @@ void launch_merge(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_merge_hubs, dim3(kHubBlocks), dim3(1024), 0, s, v);
 }
 
-size_t partial_words() { return 3 * (size_t)(kMergeBlocks + kHubBlocks); }
-
 __global__ __launch_bounds__(1024) void k_finish_counters(Views v, uint64_t* slot, double thr) {
     if (stopped(v)) return;
-    __shared__ uint64_t s_a[16], s_b[16], s_c[16];
-    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
-    uint64_t a = 0, b = 0, c = 0;
-    for (int i = t; i < kMergeBlocks + kHubBlocks; i += 1024) {
-        a += v.partial[3 * i];
-        b += v.partial[3 * i + 1];
-        c += v.partial[3 * i + 2];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += shfl_xor64(a, o);
-        b += shfl_xor64(b, o);
-        c += shfl_xor64(c, o);
-    }
-    if (lane == 0) {
-        s_a[w] = a;
-        s_b[w] = b;
-        s_c[w] = c;
-    }
-    __syncthreads();
-    if (t == 0) {
-        uint64_t sa = 0, sb = 0, sc = 0;
-        for (int i = 0; i < 16; ++i) {
-            sa += s_a[i];
-            sb += s_b[i];
-            sc += s_c[i];
-        }
-        v.counters[kCntChanges] = sa;
-        v.counters[kCntProposals] = sb;
-        v.counters[kCntPairs2] = 2ull * sc;
-        if (slot) {
-            for (int i = 0; i < kNumCounters; ++i) slot[i] = v.counters[i];
-            __threadfence_system();
-        }
-        if (thr >= 0.0 && v.stop) {
-            const bool met = (double)sa < thr || v.counters[kCntError] != 0ull;
-            *v.stop = met ? 1u : 0u;
-        }
-    }
+    finish_counters_block(v, slot, thr);
 }
 
 void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr) {
     launch_timed(k_finish_counters, dim3(1), dim3(1024), 0, s, nullptr, e1, v, slot, thr);
 }
+
+size_t partial_words() { return 3 * (size_t)(kMergeBlocks + kHubBlocks); }
+
+
 
 // ------------------------------------------------------------------ finalize (a8)
 

@@ -1047,19 +1047,61 @@ __device__ __forceinline__ void pool_read(const Views& v, uint64_t st, int u, ui
 
 // One owner whose pool has more than 64 entries (s_key, s_idx: 64 LDS slots
 // of the calling wave).
+// Pool entry i without its weight: member id and position word.
+__device__ __forceinline__ void pool_ids(const Views& v, int u, uint32_t rb, int i, uint32_t& id, uint32_t& pf) {
+    if (i < v.K) {
+        const size_t e = (size_t)u * v.K + i;
+        id = (uint32_t)v.lkey[e];
+        pf = v.lpos[e];
+    } else {
+        const uint4 r = v.rev[rb + (uint32_t)(i - v.K)];
+        id = r.y;
+        pf = r.z;
+    }
+}
+
+constexpr int kThrCache = 512;   // pool entries whose weight and flag a wave keeps in LDS
+
+// Weight and flag (1: OLD) of pool entry i: from the LDS cache when the pool
+// fits it, else read again (the hash recomputed for forward entries).
+__device__ __forceinline__ void pool_wf(const Views& v, uint64_t st, int u, uint32_t ou, uint32_t rb, int i,
+                                        bool cached, const uint32_t* c_wt, const uint8_t* c_old, uint32_t& wt,
+                                        uint32_t& old) {
+    if (cached) {
+        wt = c_wt[i];
+        old = c_old[i];
+    } else {
+        uint32_t id, pf;
+        pool_read(v, st, u, ou, rb, i, wt, id, pf);
+        old = (pf & kNewBit) ? 0u : 1u;
+    }
+}
+
+// One owner whose pool has more than 64 entries (s_key, s_idx: 64 LDS slots
+// of the calling wave; c_wt, c_old: kThrCache-entry cache of the weights and
+// OLD flags). The threshold search and the gathers read the cache; only the
+// survivors' ids are read again.
 __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint32_t rb, int P, uint32_t ou,
-                                       uint64_t* s_key, uint32_t* s_idx) {
+                                       uint64_t* s_key, uint32_t* s_idx, uint32_t* c_wt, uint8_t* c_old) {
     const int lane = lane_id();
     const int K = v.K;
     const uint32_t C = (uint32_t)v.C;
+    const bool cached = P <= kThrCache;
     uint32_t tot[2] = {0u, 0u};
     for (int i0 = 0; i0 < P; i0 += 64) {
         const int i = i0 + lane;
         uint32_t wt = 0, id = 0, pf = 0;
-        if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
+        if (i < P) {
+            pool_read(v, st, u, ou, rb, i, wt, id, pf);
+            if (cached) {
+                c_wt[i] = wt;
+                c_old[i] = (pf & kNewBit) ? 0u : 1u;
+            }
+        }
         tot[0] += __popcll(ballot(i < P && (pf & kNewBit)));
         tot[1] += __popcll(ballot(i < P && !(pf & kNewBit)));
     }
+    wave_sync();
     uint32_t newid = 0xffffffffu;  // lane r < nnew: id of the sampled new member of rank r
     uint32_t nnew = 0, nold = 0;
     uint32_t flip_idx = 0xffffffffu, flip_pos = 0;
@@ -1077,10 +1119,9 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
                 uint32_t cnt = 0;
                 for (int i0 = 0; i0 < P; i0 += 64) {
                     const int i = i0 + lane;
-                    uint32_t wt = 0, id = 0, pf = 0;
-                    if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
-                    const bool isf = ((pf & kNewBit) ? 0 : 1) == f;
-                    cnt += __popcll(ballot(i < P && isf && wt <= (uint32_t)t));
+                    uint32_t wt = 0, old = 2u;
+                    if (i < P) pool_wf(v, st, u, ou, rb, i, cached, c_wt, c_old, wt, old);
+                    cnt += __popcll(ballot(old == (uint32_t)f && wt <= (uint32_t)t));
                 }
                 if (cnt >= need && cnt <= 64) {
                     found = true;
@@ -1102,12 +1143,14 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
         wave_sync();
         for (int i0 = 0; i0 < P; i0 += 64) {
             const int i = i0 + lane;
-            uint32_t wt = 0, id = 0, pf = 0;
-            if (i < P) pool_read(v, st, u, ou, rb, i, wt, id, pf);
-            const bool surv = i < P && (((pf & kNewBit) ? 0 : 1) == f) && wt <= T;
+            uint32_t wt = 0, old = 2u;
+            if (i < P) pool_wf(v, st, u, ou, rb, i, cached, c_wt, c_old, wt, old);
+            const bool surv = old == (uint32_t)f && wt <= T;
             const uint64_t m = ballot(surv);
             const uint32_t slot = n + mbcnt(m);
             if (surv && slot < 64) {
+                uint32_t id, pf;
+                pool_ids(v, u, rb, i, id, pf);
                 s_key[slot] = sel_key(wt, id, pf);
                 s_idx[slot] = (uint32_t)i;
             }
@@ -1196,6 +1239,8 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
     if (stopped(v)) return;
     __shared__ uint64_t s_key[kSelWaves][64];
     __shared__ uint32_t s_idx[kSelWaves][64];
+    __shared__ uint32_t s_cwt[kSelWaves][kThrCache];
+    __shared__ uint8_t s_cold[kSelWaves][kThrCache];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int N = v.N, K = v.K;
     const uint32_t C = (uint32_t)v.C;
@@ -1215,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int
         if (lane == 0) v.big[u] = P > 64 && !thr_inline ? 1u : 0u;
         const uint32_t ou = (uint32_t)v.orig[u];
         if (P > 64) {
-            if (thr_inline) select_large_thr_owner(v, st, u, rb, P, ou, s_key[w], s_idx[w]);
+            if (thr_inline) select_large_thr_owner(v, st, u, rb, P, ou, s_key[w], s_idx[w], s_cwt[w], s_cold[w]);
             continue;
         }
         uint64_t key = ~0ull;

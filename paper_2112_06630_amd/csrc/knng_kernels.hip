@@ -1228,94 +1228,134 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
     wave_sync();
 }
 
-// Pools of at most 64 entries, one per lane, in registers. Select key
-// (w << 32) | (id << 1) | old: sorting it puts the two copies of a member
-// reached by both routes with the same flag next to each other (the second
-// is a duplicate), and a member's NEW entry right before its OLD entry.
-// Ranks per flag are ballot prefix counts over the sorted lanes. Larger pools
-// take the threshold select in the same wave when 2C <= 60 (their latency
-// hides behind the small pools), else k_select_large (big[u] = 1).
-__global__ __launch_bounds__(256) void k_select_small(Views v, uint64_t st0, int t) {
-    if (stopped(v)) return;
-    __shared__ uint64_t s_key[kSelWaves][64];
-    __shared__ uint32_t s_idx[kSelWaves][64];
-    __shared__ uint32_t s_cwt[kSelWaves][kThrCache];
-    __shared__ uint8_t s_cold[kSelWaves][kThrCache];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+// Ascending bitonic sort of (key, value) pairs within segments of W lanes
+// (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
+template <int W>
+__device__ __forceinline__ void seg_sort(uint64_t& k, uint32_t& v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= W; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) cmpx(k, v, j, size == W || (lane & size) == 0);
+    }
+}
+
+// Pool of one owner per W-lane segment (u, P: the segment's owner and pool
+// size, P <= W; u == N: no owner), one entry per lane, in registers. Select
+// key (w << 32) | (id << 1) | old: sorting it puts the two copies of a
+// member reached by both routes with the same flag next to each other (the
+// second is a duplicate), and a member's NEW entry right before its OLD
+// entry. Ranks per flag are ballot prefix counts over the segment's sorted
+// lanes.
+template <int W>
+__device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t, int u, int P) {
+    const int lane = lane_id(), sl = lane & (W - 1);
+    const uint64_t seg = W == 64 ? ~0ull : (lane < 32 ? 0x00000000ffffffffull : 0xffffffff00000000ull);
     const int N = v.N, K = v.K;
     const uint32_t C = (uint32_t)v.C;
-    const bool thr_inline = 2 * v.C <= 60;
-    for (int u = blockIdx.x * kSelWaves + w; u < N; u += gridDim.x * kSelWaves) {
-        if (v.ds && !pos_active(v, u)) {   // finished dataset: nothing sampled, nothing joined
-            if (lane == 0) {
-                v.big[u] = 0u;
-                v.nn[u] = 0u;
-                v.cap[u] = 0u;
-            }
-            continue;
-        }
-        const uint64_t st = sample_state(v, u, st0, t);
+    uint64_t key = ~0ull;
+    uint32_t pos = 0;
+    if (sl < P) {
         const uint32_t rb = v.roff[u];
-        const int P = K + (int)(v.roff[u + 1] - rb);
-        if (lane == 0) v.big[u] = P > 64 && !thr_inline ? 1u : 0u;
-        const uint32_t ou = (uint32_t)v.orig[u];
-        if (P > 64) {
-            if (thr_inline) select_large_thr_owner(v, st, u, rb, P, ou, s_key[w], s_idx[w], s_cwt[w], s_cold[w]);
-            continue;
+        uint32_t id, pf, wt;
+        if (sl < K) {
+            const size_t e = (size_t)u * K + sl;
+            id = (uint32_t)v.lkey[e];
+            pf = v.lpos[e];
+            wt = pair_weight(sample_state(v, u, st0, t), (uint32_t)v.orig[u], id);
+        } else {
+            const uint4 r = v.rev[rb + (uint32_t)(sl - K)];
+            wt = r.x;
+            id = r.y;
+            pf = r.z;
         }
-        uint64_t key = ~0ull;
-        uint32_t pos = 0;
-        if (lane < P) {
-            uint32_t id, pf, wt;
-            if (lane < K) {
-                const size_t e = (size_t)u * K + lane;
-                id = (uint32_t)v.lkey[e];
-                pf = v.lpos[e];
-                wt = pair_weight(st, ou, id);
-            } else {
-                const uint4 r = v.rev[rb + (uint32_t)(lane - K)];
-                wt = r.x;
-                id = r.y;
-                pf = r.z;
-            }
-            key = ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
-            pos = pf & kPosMask;
-        }
-        uint32_t idx = (uint32_t)lane;
-        wave_sort(key, idx);
-        const uint32_t mpos = (uint32_t)__shfl((int)pos, (int)idx);
-        const uint64_t p1 = shfl_up64(key, 1), p2 = shfl_up64(key, 2);
-        const bool real = key != ~0ull;
-        const bool dup = real && lane >= 1 && p1 == key;
-        const bool valid = real && !dup;
-        const bool isnew = (key & 1ull) == 0;
-        const uint64_t mnew = ballot(valid && isnew), mold = ballot(valid && !isnew);
-        const uint32_t rnew = mbcnt(mnew), rold = mbcnt(mold);
-        const bool seln = valid && isnew && rnew < C;
-        const bool s1 = __shfl_up(seln ? 1 : 0, 1) != 0, s2 = __shfl_up(seln ? 1 : 0, 2) != 0;
-        const bool twin = !isnew && ((lane >= 1 && (p1 | 1ull) == key && !(p1 & 1ull) && s1) ||
-                                     (lane >= 2 && (p2 | 1ull) == key && !(p2 & 1ull) && s2));
-        const bool cold = valid && !isnew && rold < C;
-        const bool removed = cold && twin;
-        const uint64_t mrem = ballot(removed);
-        const uint32_t nnew = min(C, (uint32_t)__popcll(mnew));
-        const uint32_t nold = min(C, (uint32_t)__popcll(mold)) - (uint32_t)__popcll(mrem);
+        key = ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
+        pos = pf & kPosMask;
+    }
+    uint32_t idx = (uint32_t)lane;   // the entry's lane; its pool index is idx & (W - 1)
+    seg_sort<W>(key, idx);
+    const uint32_t mpos = (uint32_t)__shfl((int)pos, (int)idx);
+    const uint64_t p1 = shfl_up64(key, 1), p2 = shfl_up64(key, 2);
+    const bool real = key != ~0ull;
+    const bool dup = real && sl >= 1 && p1 == key;
+    const bool valid = real && !dup;
+    const bool isnew = (key & 1ull) == 0;
+    const uint64_t mnew = ballot(valid && isnew) & seg, mold = ballot(valid && !isnew) & seg;
+    const uint32_t rnew = mbcnt(mnew), rold = mbcnt(mold);
+    const bool seln = valid && isnew && rnew < C;
+    const bool s1 = __shfl_up(seln ? 1 : 0, 1) != 0, s2 = __shfl_up(seln ? 1 : 0, 2) != 0;
+    const bool twin = !isnew && ((sl >= 1 && (p1 | 1ull) == key && !(p1 & 1ull) && s1) ||
+                                 (sl >= 2 && (p2 | 1ull) == key && !(p2 & 1ull) && s2));
+    const bool cold = valid && !isnew && rold < C;
+    const bool removed = cold && twin;
+    const uint64_t mrem = ballot(removed) & seg;
+    const uint32_t nnew = min(C, (uint32_t)__popcll(mnew));
+    const uint32_t nold = min(C, (uint32_t)__popcll(mold)) - (uint32_t)__popcll(mrem);
+    const uint32_t ei = idx & (W - 1);
+    if (u < N) {
         uint2* cs = v.cand + (size_t)u * 2 * C;
         const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
         if (seln) cs[rnew] = make_uint2(id, mpos);
         if (cold && !removed) cs[nnew + rold - mbcnt(mrem)] = make_uint2(id, mpos);
         // forward NEW entries whose member was sampled new become OLD
-        if (real && isnew && idx < (uint32_t)K && (seln || (dup && s1)))
-            v.lpos[(size_t)u * K + idx] = mpos;
-        if (lane == 0) {
+        if (real && isnew && ei < (uint32_t)K && (seln || (dup && s1)))
+            v.lpos[(size_t)u * K + ei] = mpos;
+        if (sl == 0) {
             v.nn[u] = nnew | (nold << 16);
             v.cap[u] = owner_pairs(nnew, nold);
         }
     }
 }
 
+// Pool size of owner u (0: past N, or its dataset has finished).
+__device__ __forceinline__ int pool_size(const Views& v, int u) {
+    if (u >= v.N || (v.ds && !pos_active(v, u))) return 0;
+    return v.K + (int)(v.roff[u + 1] - v.roff[u]);
+}
+
+// Owners in pairs: two pools of at most 32 entries share one wave (one
+// 32-lane segment each: a 15-stage sort instead of 21); otherwise each owner
+// takes the wave alone. Pools of more than 64 entries take the threshold
+// select in the same wave when 2C <= 60 (their latency hides behind the
+// small pools), else k_select_large (big[u] = 1).
+__global__ __launch_bounds__(256, 8) void k_select_small(Views v, uint64_t st0, int t) {
+    if (stopped(v)) return;
+    __shared__ uint64_t s_key[kSelWaves][64];
+    __shared__ uint32_t s_idx[kSelWaves][64];
+    __shared__ uint32_t s_cwt[kSelWaves][kThrCache];
+    __shared__ uint8_t s_cold[kSelWaves][kThrCache];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int N = v.N;
+    const bool thr_inline = 2 * v.C <= 60;
+    const int pairs = (N + 1) >> 1;
+    for (int pr = blockIdx.x * kSelWaves + w; pr < pairs; pr += gridDim.x * kSelWaves) {
+        const int u0 = 2 * pr, u1 = u0 + 1;
+        const int P0 = pool_size(v, u0), P1 = pool_size(v, u1);
+        if (lane == 0) {
+            v.big[u0] = P0 > 64 && !thr_inline ? 1u : 0u;
+            if (u1 < N) v.big[u1] = P1 > 64 && !thr_inline ? 1u : 0u;
+        }
+        if (P0 <= 32 && P1 <= 32) {
+            const bool hi = lane >= 32;
+            select_pool<32>(v, st0, t, hi ? u1 : u0, hi ? P1 : P0);
+            continue;
+        }
+        for (int h = 0; h < 2; ++h) {
+            const int u = h ? u1 : u0, P = h ? P1 : P0;
+            if (u >= N) break;
+            if (P > 64) {
+                if (thr_inline)
+                    select_large_thr_owner(v, sample_state(v, u, st0, t), u, v.roff[u], P, (uint32_t)v.orig[u],
+                                           s_key[w], s_idx[w], s_cwt[w], s_cold[w]);
+                continue;
+            }
+            select_pool<64>(v, st0, t, u, P);
+        }
+    }
+}
+
 void launch_select(const Views& v, uint64_t st, int t, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_small, dim3(grid_for(v.N, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
+    hipLaunchKernelGGL(k_select_small, dim3(grid_for((v.N + 1) / 2, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
     // The threshold search (inside k_select_small) needs a count in [2C, 64];
     // a member reached by both routes adds two entries of one weight, so the
     // count can step over a window narrower than 3 (2C = 64 leaves one

@@ -312,10 +312,10 @@ def main():
     # local-join roofline. The join gathers the member rows of every owner
     # with a new member: its algorithmic bytes per launch (no reuse across
     # owners) are sum_u m_u * (row bytes + 20 B of member metadata: sample
-    # entry 8, snapshot K-th key 8, norm 4) + 12 B per emitted proposal (key 8,
-    # source 4). Row bytes: 2 d_pad per BF16 plane read (split form), 4 d_pad
-    # for FP32 rows. m_u per iteration comes from the step API, which replays
-    # the same deterministic trajectory (untimed).
+    # entry 8, snapshot K-th key 8, norm 4) + 8 B per emitted proposal (its
+    # key). Row bytes: 2 d_pad per BF16 plane read (split form), 4 d_pad for
+    # FP32 rows. m_u per iteration comes from the step API, which replays the
+    # same deterministic trajectory (untimed).
     s0 = stats[len(stats) // 2]
     join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
     flops = [e * 2 * w["d"] for e in s0["evals"]]
@@ -325,7 +325,7 @@ def main():
     row_bytes = {"k_join_split": 2 * s0["dpad"] * max(1, s0["planes"]), "k_join_bf16": 2 * s0["dpad"]}.get(
         kernel, 4 * s0["dpad"])
     members, curve_ids = member_counts_and_graphs(X, w, args, s0["iters"], not args.no_recall)
-    jbytes = [m * (row_bytes + 20) + 12 * pr for m, pr in zip(members, s0["proposals"])]
+    jbytes = [m * (row_bytes + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
     achieved_bw = sum(jbytes) / (sum(join_ms) / 1e3) / 1e9
     achieved_fl = sum(flops) / (sum(join_ms) / 1e3) / 1e12
     traffic = traffic_record(kernel)
@@ -357,6 +357,18 @@ def main():
             cum += float(np.median([s["iter_ms"][t] for s in stats]))
             if r >= 0.99 and t99 is None:
                 t99 = cum
+    # context: a plain device-to-device copy of 1 GiB (1 GiB read + 1 GiB written)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
     cpu = None if args.no_cpu else cpu_baseline(Xnp, w)
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
@@ -377,6 +389,10 @@ def main():
         "device_ms_per_build": round(float(np.median([s["total_ms"] for s in stats])), 3),
         "phase_ms": {k: round(float(sum(s0[k])), 3) for k in ("sample_ms", "join_ms", "merge_ms")},
         "roofline": roof, "cpu_baseline": cpu,
+        # context: e*(3d-1) flop/s (the paper's convention: d differences, d
+        # products, d-1 additions per evaluation) and a measured copy bandwidth
+        "paper_gflops": round(evals * (3 * w["d"] - 1) / (ms_per_step / 1e3) / 1e9, 1),
+        "copy_GBps": round(copy_gbs, 1),
     }
     print(json.dumps(out), flush=True)
 

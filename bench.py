@@ -241,6 +241,59 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
     print(json.dumps({k: out[k] for k in out if not k.startswith("_")}, indent=1))
 
 
+def run_sweep(args):
+    """The paper's scaling sweeps (Sec. 4) on its Synthetic Single Gaussian
+    Dataset (covariance 2 I): dimension d = 8, 72, ..., 3144 at n = 16384, or
+    size n = 2^10 .. 2^20 at d = 256; K = 20, rho = 1, delta = 0.001, T = 30.
+    "lowd": d = 8, 16, ..., 96 at n = 16384, where the direct-form (VALU) join
+    still fits its LDS stage, to place the VALU / matrix-core crossover.
+    Every join path the plan accepts at a point is timed (wall clock of whole
+    builds, inputs resident); one JSON line per (point, path)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2112_06630_amd as knng
+
+    dev = torch.device("cuda:0")
+    K, rho, delta, T, seed = 20, 1.0, 0.001, 30, 5
+    if args.sweep == "d":
+        pts = [(16384, d) for d in range(8, 3145, 64)]
+    elif args.sweep == "lowd":
+        pts = [(16384, d) for d in range(8, 97, 8)]
+    else:
+        pts = [(1 << e, 256) for e in range(10, 21)]
+    for N, d in pts:
+        X = torch.from_numpy(synth.single_gaussian(N, d, seed)).to(dev)
+        for path in ("valu", "mfma", "bf16x3"):
+            try:
+                p = knng.make_params(K, rho, delta, T, seed, False, path=path)
+                ws = torch.empty(knng.workspace_bytes(N, d, p), dtype=torch.uint8, device=dev)
+            except Exception:
+                continue   # the path does not take this shape (VALU: rows must fit the LDS stage)
+            if ws.numel() == 0:
+                continue
+            ids = torch.empty((N, K), dtype=torch.int32, device=dev)
+            dists = torch.empty((N, K), dtype=torch.float32, device=dev)
+            run = lambda: knng.build(X, K, rho, delta, T, seed, False, path=path, workspace=ws, out=(ids, dists))
+            for _ in range(max(1, args.warmup)):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = [run()[2] for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            st = sts[-1]
+            ev = sum(st["evals"])
+            join = float(sum(st["join_ms"]))
+            print(json.dumps({"sweep": args.sweep, "N": N, "d": d, "path": path, "ms_per_build": round(ms, 3),
+                              "iters": st["iters"], "evals": ev, "evals_per_s": round(ev / (ms / 1e3), 1),
+                              "paper_gflops": round(ev * (3 * d - 1) / (ms / 1e3) / 1e9, 2),
+                              "alg_tflops": round(ev * 2 * d / (ms / 1e3) / 1e12, 3),
+                              "join_ms": round(join, 3), "planes": st.get("planes")}), flush=True)
+            del ws, ids, dists
+        del X
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +313,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarize two rocprofv3 counter runs into profiles/traffic.json and exit")
     ap.add_argument("--pmc-command", default="", help="the command the counter runs used (recorded)")
+    ap.add_argument("--sweep", choices=["d", "n", "lowd"], default=None,
+                    help="the paper's dimension (n = 16384) or size (d = 256) sweep on a single Gaussian: "
+                         "one JSON line per point and join path, no headline line")
     args = ap.parse_args()
     if args.pmc_summary:
         summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe_mib or 1024, args.pmc_command)
@@ -267,6 +323,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.sweep:
+        run_sweep(args)
+        return
 
     import numpy as np
     import torch

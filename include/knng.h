@@ -55,10 +55,12 @@ typedef enum {
 } knng_precision;
 
 /*
- * Join paths. AUTO takes the VALU direct form when d < 64 or ceil(rho*K) > 32,
- * else (FP32 precision) the split-BF16 Gram form below; on the MFMA side it
- * would take the exact integer form when X qualifies (checked on the device
- * at create).
+ * Join paths. AUTO takes the VALU direct form when d < 48 or ceil(rho*K) > 32,
+ * else (FP32 precision) the split-BF16 Gram form below, except that data
+ * whose values need all three BF16 planes (counted at create) run on FP32
+ * tiles (KNNG_PATH_MFMA) below d = 192, where those are faster; on the MFMA
+ * side it would take the exact integer form when X qualifies (checked on the
+ * device at create).
  *
  * Exact integer form (KNNG_PATH_MFMA_I8). X qualifies when every value is an
  * integer of magnitude <= 2^24 and max(X) - min(X) <= 255 over the whole input

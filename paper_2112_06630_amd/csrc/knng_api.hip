@@ -94,6 +94,13 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
 // KNNG_EINVAL and AUTO never selects it; the kernels stay in the library.
 constexpr bool kInt8FormEnabled = false;
 
+// AUTO's join path, from the single-Gaussian sweeps (n = 16384, K = 20): the
+// direct form on the VALU up to d = 40, the matrix forms from d = 48; among
+// those, data that needs all three BF16 planes runs faster on FP32 tiles
+// below d = 192 (decided after the layout pass has counted the planes).
+constexpr int kAutoMatrixMinD = 48;
+constexpr int kAutoSplit3MinD = 192;
+
 knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool allow_i8 = true) {
     knng_status s = validate(N, d, p);
     if (s != KNNG_OK) return s;
@@ -117,7 +124,8 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
         path = KNNG_PATH_MFMA;
     }
     if (path == KNNG_PATH_AUTO) {
-        path = (d >= 64 && 2 * P.C <= 64) ? (P.bf16 ? KNNG_PATH_MFMA : KNNG_PATH_MFMA_BF16X3) : KNNG_PATH_VALU;
+        path = (d >= kAutoMatrixMinD && 2 * P.C <= 64) ? (P.bf16 ? KNNG_PATH_MFMA : KNNG_PATH_MFMA_BF16X3)
+                                                        : KNNG_PATH_VALU;
         if (path == KNNG_PATH_MFMA_BF16X3 && allow_i8 && d <= kMaxI8Dim) P.want_i8 = 1;
     }
     if ((path == KNNG_PATH_MFMA || path == KNNG_PATH_MFMA_BF16X3) && 2 * P.C > 64)
@@ -618,6 +626,8 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
         c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
         c->stats.planes = c->v.planes;
         if (c->v.planes > 1 || P.want_i8) launch_prep_rest(dX, c->v, c->stream);
+        if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
+            c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)
     }
     if (P.want_i8) {
         knng_status is = select_int8(c);
@@ -881,7 +891,7 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
     for (int i = 0; i < n; ++i) {
         const int d = descs[i].d;
         int path = p->path != KNNG_PATH_AUTO ? p->path : parse_tuned_path(tuning, d);
-        if (!path) path = (d >= 64 && 2 * C <= 64) ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
+        if (!path) path = (d >= kAutoMatrixMinD && 2 * C <= 64) ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
         const int dp = (int)(path != KNNG_PATH_VALU ? round_up(d, 32) : round_up(d, 4));
         BatchGroup* g = nullptr;
         for (auto& x : groups)
@@ -1026,7 +1036,7 @@ knng_status batch_autotune(knng_batch* b, hipStream_t s) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     for (int d : ds_seen) {
-        int best_path = d >= 64 && 2 * C <= 64 ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
+        int best_path = d >= kAutoMatrixMinD && 2 * C <= 64 ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
         if (2 * C <= 64) {
             float best_ms = 1e30f;
             for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA, KNNG_PATH_MFMA_BF16X3}) {

@@ -15,7 +15,8 @@ import math
 import numpy as np
 
 __all__ = ["config", "CONFIGS", "gaussian_mixture", "integer_points", "image_like",
-           "lowd_blobs", "anisotropic_clusters", "batched_datasets", "clustered_labels"]
+           "lowd_blobs", "anisotropic_clusters", "batched_datasets", "clustered_labels",
+           "single_gaussian"]
 
 
 def gaussian_mixture(N: int, d: int, n_centres: int, seed: int, lo: float = -10.0,
@@ -26,6 +27,13 @@ def gaussian_mixture(N: int, d: int, n_centres: int, seed: int, lo: float = -10.
     labels = rng.integers(0, n_centres, N)
     X = (centres[labels] + sigma * rng.standard_normal((N, d))).astype(np.float32)
     return (X, labels) if return_labels else X
+
+
+def single_gaussian(N: int, d: int, seed: int) -> np.ndarray:
+    """The paper's Synthetic Single Gaussian Dataset (Sec. 4): every point from
+    one Gaussian centred at the origin with covariance 2 I_d."""
+    rng = np.random.default_rng(seed)
+    return (math.sqrt(2.0) * rng.standard_normal((N, d), dtype=np.float32)).astype(np.float32)
 
 
 def integer_points(N: int, d: int, hi: int, seed: int) -> np.ndarray:

@@ -145,7 +145,7 @@ def test_split_form_whole_build(knng, gen):
     Gram-form bound, recall as the oracle's (within 0.005)."""
     X, K, rho, seed = _split_case(gen)
     dpad = (X.shape[1] + 31) // 32 * 32
-    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, seed, path="auto")
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, seed, path="bf16x3")
     assert st["path"] == knng.PATH_MFMA_BF16X3
     ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
     D64, bound = fp32_bound(X, ids, dpad, True)
@@ -232,6 +232,21 @@ def test_integer_form_step_parity(knng):
         assert np.array_equal(g.ids.cpu().numpy(), nxt.ids)
         assert np.array_equal(g.dists.cpu().numpy().astype(np.float64), nxt.dists)
         ctx.close()
+
+
+def test_auto_path_choice(knng):
+    """AUTO follows the crossovers of the single-Gaussian sweeps: the direct
+    form below d = 48; from 48 the split form, except that data needing all
+    three BF16 planes run on FP32 tiles below d = 192; integer pixel-like data
+    (one plane) keep the split form."""
+    for d, want in ((40, knng.PATH_VALU), (48, knng.PATH_MFMA), (160, knng.PATH_MFMA),
+                    (224, knng.PATH_MFMA_BF16X3)):
+        X = synth.single_gaussian(600, d, 3)
+        _, _, st = knng.build(dev(X), 10, 1.0, 0.001, 3, 3, path="auto")
+        assert st["path"] == want, (d, st["path"])
+    X = synth.integer_points(600, 96, 200, 3)
+    _, _, st = knng.build(dev(X), 10, 1.0, 0.001, 3, 3, path="auto")
+    assert st["path"] == knng.PATH_MFMA_BF16X3 and st["planes"] == 1
 
 
 @I8_OFF

@@ -59,12 +59,12 @@ def _load():
     lib.orc_dist.argtypes = [P, i64, i64, i64]
     lib.orc_dist.restype = f64
     lib.orc_init.argtypes = [P, i64, i32, i32, u64, P, P, P]
-    lib.orc_sample.argtypes = [P, P, i64, i32, i32, u64, i32, P, P, P, P, P]
+    lib.orc_sample.argtypes = [P, P, i64, i32, i32, u64, i32, P, P, P, P, P, i32]
     lib.orc_join_merge.argtypes = [P, i64, i32, i32, i32, P, P, P, P, P, P, P, P, P]
-    lib.orc_iterate.argtypes = [P, i64, i32, i32, i32, u64, i32, P, P, P, P, P]
+    lib.orc_iterate.argtypes = [P, i64, i32, i32, i32, u64, i32, P, P, P, P, P, i32]
     lib.orc_dist_sum.argtypes = [P, i64, i32]
     lib.orc_dist_sum.restype = f64
-    lib.orc_build.argtypes = [P, i64, i32, i32, f64, f64, i32, u64, P, P, P, P, P, P]
+    lib.orc_build.argtypes = [P, i64, i32, i32, f64, f64, i32, u64, P, P, P, P, P, P, i32]
     lib.orc_bruteforce.argtypes = [P, i64, i32, i32, P, P]
     lib.orc_bruteforce_rows.argtypes = [P, i64, i32, i32, P, i64, P, P]
     lib.orc_list_dists.argtypes = [P, i64, i32, i32, P, P]
@@ -137,7 +137,18 @@ class Sample:
     flags: np.ndarray  # flags after the new->old flip
 
 
-def sample(state: State, K: int, C: int, seed: int, t: int) -> Sample:
+SAMPLING = {"weighted": 0, "turbo": 1}
+
+
+def _mode(sampling: str) -> int:
+    if sampling not in SAMPLING:
+        raise ValueError(f"sampling must be one of {sorted(SAMPLING)}")
+    return SAMPLING[sampling]
+
+
+def sample(state: State, K: int, C: int, seed: int, t: int, sampling: str = "weighted") -> Sample:
+    """Sampling step of iteration t (Sec. 3.1): the heap rule ("weighted") or
+    turbosampling ("turbo")."""
     N = state.ids.shape[0]
     cnew = np.empty((N, C), np.int32)
     cold = np.empty((N, C), np.int32)
@@ -147,12 +158,13 @@ def sample(state: State, K: int, C: int, seed: int, t: int) -> Sample:
     ids = np.ascontiguousarray(state.ids, np.int32)
     fl = np.ascontiguousarray(state.flags, np.uint8)
     _check(_load().orc_sample(_ptr(ids), _ptr(fl), N, K, C, seed, t, _ptr(cnew), _ptr(nnew),
-                              _ptr(cold), _ptr(nold), _ptr(f2)), "sample")
+                              _ptr(cold), _ptr(nold), _ptr(f2), _mode(sampling)), "sample")
     return Sample([cnew[u, :nnew[u]].copy() for u in range(N)],
                   [cold[u, :nold[u]].copy() for u in range(N)], f2)
 
 
-def iterate(X, state: State, K: int, C: int, seed: int) -> tuple[State, int, int]:
+def iterate(X, state: State, K: int, C: int, seed: int,
+            sampling: str = "weighted") -> tuple[State, int, int]:
     """One synchronous iteration t = state.t + 1. Returns (new state, e_t, c_t)."""
     X = _f32(X)
     N, d = X.shape
@@ -160,7 +172,8 @@ def iterate(X, state: State, K: int, C: int, seed: int) -> tuple[State, int, int
     e = ctypes.c_int64(0)
     c = ctypes.c_int64(0)
     _check(_load().orc_iterate(_ptr(X), N, d, K, C, seed, s.t + 1, _ptr(s.ids), _ptr(s.dists),
-                               _ptr(s.flags), ctypes.byref(e), ctypes.byref(c)), "iterate")
+                               _ptr(s.flags), ctypes.byref(e), ctypes.byref(c), _mode(sampling)),
+           "iterate")
     s.t += 1
     return s, int(e.value), int(c.value)
 
@@ -178,7 +191,7 @@ class BuildResult:
 
 
 def build_graph(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
-                keep_states: bool = False) -> BuildResult:
+                keep_states: bool = False, sampling: str = "weighted") -> BuildResult:
     """Whole build. With keep_states, every G_t (t = 0..iters) is kept."""
     X = _f32(X)
     N, d = X.shape
@@ -187,7 +200,7 @@ def build_graph(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
     states = [st.copy()] if keep_states else []
     ev, ch, ds = [], [], []
     for t in range(1, max_iters + 1):
-        st, e, c = iterate(X, st, K, C, seed)
+        st, e, c = iterate(X, st, K, C, seed, sampling)
         ev.append(e)
         ch.append(c)
         ds.append(float(_load().orc_dist_sum(_ptr(st.dists), N, K)))
@@ -199,7 +212,8 @@ def build_graph(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
                        np.array(ch, np.int64), np.array(ds), states)
 
 
-def build_graph_c(X, K: int, rho: float, delta: float, max_iters: int, seed: int) -> BuildResult:
+def build_graph_c(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
+                  sampling: str = "weighted") -> BuildResult:
     """Whole build in one C call (used for timing)."""
     X = _f32(X)
     N, d = X.shape
@@ -211,7 +225,7 @@ def build_graph_c(X, K: int, rho: float, delta: float, max_iters: int, seed: int
     ch = np.zeros(m, np.int64)
     ds = np.zeros(m, np.float64)
     it = _load().orc_build(_ptr(X), N, d, K, rho, delta, max_iters, seed, _ptr(ids), _ptr(dists),
-                           _ptr(flags), _ptr(ev), _ptr(ch), _ptr(ds))
+                           _ptr(flags), _ptr(ev), _ptr(ch), _ptr(ds), _mode(sampling))
     _check(it, "build")
     return BuildResult(ids, dists, flags, it, ev[:it], ch[:it], ds[:it])
 

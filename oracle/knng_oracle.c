@@ -15,8 +15,8 @@
  *
  * The paper defers the new/old bookkeeping and the stop rule to Dong et al.;
  * the readings taken here (synchronous snapshot, new/old flags, per-pair hashed
- * weights, (distance, id) tie-break, c_t < delta*N*K) are listed in the design doc
- * and restated at each step below.
+ * weights, (distance, id) tie-break, c_t < delta*N*K) are stated at each step
+ * below.
  *
  * Everything is plain and sequential per node; OpenMP only splits independent
  * nodes across threads, and every reduction is done in a fixed order, so the
@@ -35,6 +35,8 @@
 
 #define ORC_OLD 0
 #define ORC_NEW 1
+#define ORC_WEIGHTED 0 /* sampling rules (Sec. 3.1): heap (smallest weights) */
+#define ORC_TURBO 1    /* turbosampling (Bernoulli coin) */
 
 /* ---------------------------------------------------------------- hashing
  * Counter-based random numbers. mix64 is the SplitMix64 output function
@@ -157,6 +159,18 @@ int orc_init(const float *X, int64_t N, int32_t d, int32_t K, uint64_t seed,
  * member sampled as new is removed from the old sample. Every forward NEW
  * entry whose target was sampled as new becomes OLD.
  *
+ * Turbosampling (Sec. 3.1, mode ORC_TURBO): the heaps are replaced by a coin
+ * per edge that keeps a member with probability rho*k/|N(u)|, |N(u)| being
+ * the neighbourhood size the paper tracks on every graph update. Readings:
+ * the coin is the same per-pair weight (kept iff w * n_f(u) < C * 2^32, exact
+ * in integers), n_f(u) is the number of pool entries of flag f of u counted
+ * with multiplicity (forward plus reverse, as the tracked size grows by one
+ * per edge), so each flag keeps C members in expectation as the heap rule
+ * does; the fixed neighbourhood bound is C per flag, and when more entries
+ * than that pass, the C of smallest (w, id) stay. Everything else (duplicate
+ * tuples, old members also sampled as new, the flip) is as in the heap rule,
+ * so the turbo sample of each flag is a subset of the heap rule's.
+ *
  * Outputs: cnew[u*C .. +nnew[u]) and cold[u*C .. +nold[u]) hold the sampled
  * member ids sorted by (w, id); flags_out holds the flags after the flip.
  */
@@ -174,10 +188,10 @@ static int cmp_cand(const void *x, const void *y)
 int orc_sample(const int32_t *ids, const uint8_t *flags_in, int64_t N, int32_t K,
                int32_t C, uint64_t seed, int32_t t,
                int32_t *cnew, int32_t *nnew, int32_t *cold, int32_t *nold,
-               uint8_t *flags_out)
+               uint8_t *flags_out, int32_t mode)
 {
     if (!ids || !flags_in || !cnew || !nnew || !cold || !nold || !flags_out ||
-        N < 2 || K < 1 || C < 1 || C > K)
+        N < 2 || K < 1 || C < 1 || C > K || (mode != ORC_WEIGHTED && mode != ORC_TURBO))
         return -1;
     /* reverse lists: rev(v) = {(u, flag of u->v)}, filled in ascending u */
     int64_t *roff = (int64_t *)calloc((size_t)N + 1, sizeof(int64_t));
@@ -223,10 +237,15 @@ int orc_sample(const int32_t *ids, const uint8_t *flags_in, int64_t N, int32_t K
             ++n;
         }
         qsort(pool, (size_t)n, sizeof(orc_cand), cmp_cand);
+        uint64_t nf[2] = {0, 0}; /* pool entries per flag, with multiplicity */
+        for (int64_t i = 0; i < n; ++i) nf[pool[i].flag == ORC_NEW ? 0 : 1] += 1;
         int32_t cn = 0, co_raw = 0;
         int32_t *old_raw = cold + u * C; /* first take the C smallest old, then drop members also in new */
         for (int64_t i = 0; i < n; ++i) {
             if (i > 0 && cmp_cand(&pool[i - 1], &pool[i]) == 0) continue; /* identical tuple */
+            if (mode == ORC_TURBO &&
+                (uint64_t)pool[i].w * nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)C << 32))
+                continue; /* the coin dropped this edge */
             if (pool[i].flag == ORC_NEW) {
                 if (cn < C) cnew[u * C + cn++] = pool[i].id;
             } else {
@@ -369,7 +388,7 @@ int orc_join_merge(const float *X, int64_t N, int32_t d, int32_t K, int32_t C,
  * (ids, dists, flags), updated in place. */
 int orc_iterate(const float *X, int64_t N, int32_t d, int32_t K, int32_t C,
                 uint64_t seed, int32_t t, int32_t *ids, double *dists, uint8_t *flags,
-                int64_t *evals_out, int64_t *changes_out)
+                int64_t *evals_out, int64_t *changes_out, int32_t mode)
 {
     int32_t *cnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N * C));
     int32_t *cold = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N * C));
@@ -378,7 +397,7 @@ int orc_iterate(const float *X, int64_t N, int32_t d, int32_t K, int32_t C,
     uint8_t *f2 = (uint8_t *)malloc((size_t)(N * K));
     int rc = -2;
     if (cnew && cold && nnew && nold && f2) {
-        rc = orc_sample(ids, flags, N, K, C, seed, t, cnew, nnew, cold, nold, f2);
+        rc = orc_sample(ids, flags, N, K, C, seed, t, cnew, nnew, cold, nold, f2, mode);
         if (rc == 0) {
             memcpy(flags, f2, (size_t)(N * K));
             rc = orc_join_merge(X, N, d, K, C, cnew, nnew, cold, nold, ids, dists, flags,
@@ -403,7 +422,7 @@ double orc_dist_sum(const double *dists, int64_t N, int32_t K)
  * are given (capacity max_iters). Returns the number of iterations run. */
 int orc_build(const float *X, int64_t N, int32_t d, int32_t K, double rho, double delta,
               int32_t max_iters, uint64_t seed, int32_t *ids, double *dists, uint8_t *flags,
-              int64_t *evals, int64_t *changes, double *dsum)
+              int64_t *evals, int64_t *changes, double *dsum, int32_t mode)
 {
     if (rho <= 0.0 || rho > 1.0 || delta < 0.0 || max_iters < 0) return -1;
     int rc = orc_init(X, N, d, K, seed, ids, dists, flags);
@@ -412,7 +431,7 @@ int orc_build(const float *X, int64_t N, int32_t d, int32_t K, double rho, doubl
     int32_t iters = 0;
     for (int32_t t = 1; t <= max_iters; ++t) {
         int64_t e = 0, c = 0;
-        rc = orc_iterate(X, N, d, K, C, seed, t, ids, dists, flags, &e, &c);
+        rc = orc_iterate(X, N, d, K, C, seed, t, ids, dists, flags, &e, &c, mode);
         if (rc) return rc;
         if (evals) evals[t - 1] = e;
         if (changes) changes[t - 1] = c;

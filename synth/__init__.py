@@ -36,6 +36,18 @@ def single_gaussian(N: int, d: int, seed: int) -> np.ndarray:
     return (math.sqrt(2.0) * rng.standard_normal((N, d), dtype=np.float32)).astype(np.float32)
 
 
+def synthetic_gaussian(N: int, d: int, seed: int) -> np.ndarray:
+    """The paper's Synthetic Gaussian Dataset (Sec. 4), non-single variant: one
+    Gaussian per dimension i, centred at the canonical basis vector e_i, with
+    covariance 2 I_d; each point picks its Gaussian uniformly at random (the
+    paper does not give the mixing weights)."""
+    rng = np.random.default_rng(seed)
+    labels = rng.integers(0, d, N)
+    X = math.sqrt(2.0) * rng.standard_normal((N, d))
+    X[np.arange(N), labels] += 1.0
+    return X.astype(np.float32)
+
+
 def integer_points(N: int, d: int, hi: int, seed: int) -> np.ndarray:
     """Small non-negative integer coordinates in [0, hi]: every FP32 sum below 2^24
     is exact, so FP32 and FP64 distances agree bit for bit."""

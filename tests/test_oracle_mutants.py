@@ -29,6 +29,10 @@ MUTANTS = {
     "merge_readds_listed_ids": ("if (!in_list) all[n++] = cand[i];", "all[n++] = cand[i];"),
     "weight_not_symmetric": ("uint32_t a = (uint32_t)(u < x ? u : x), b = (uint32_t)(u < x ? x : u);",
                              "uint32_t a = (uint32_t)x, b = (uint32_t)u;"),
+    "turbo_counts_whole_pool": ("nf[pool[i].flag == ORC_NEW ? 0 : 1] += 1;", "{ nf[0] += 1; nf[1] += 1; }"),
+    "turbo_coin_skipped": ("if (mode == ORC_TURBO &&", "if (0 &&"),
+    "turbo_coin_uses_k": ("* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)C << 32))",
+                          "* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)K << 32))"),
 }
 
 

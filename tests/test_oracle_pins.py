@@ -200,6 +200,140 @@ def test_evals_count_closed_form(oracle_lib):
     assert e == exp
 
 
+# --------------------------------------------------------------------------- turbosampling
+
+def _random_state(N, K, seed, p_new=0.5):
+    """A random graph (distinct non-self members per row) with random flags."""
+    rng = np.random.default_rng(seed)
+    ids = np.empty((N, K), np.int32)
+    for u in range(N):
+        c = rng.choice(N - 1, K, replace=False)
+        ids[u] = np.where(c >= u, c + 1, c)
+    flags = np.where(rng.random((N, K)) < p_new, oracle.NEW, oracle.OLD).astype(np.uint8)
+    return oracle.State(ids, np.zeros((N, K)), flags, 0)
+
+
+def _turbo_by_definition(st, C, seed, t):
+    """Sec. 3.1 turbosampling spelled out on one owner at a time: every edge
+    (forward and reverse) is a pool entry with the pair's weight; entry of flag
+    f survives when w * n_f < C * 2^32 (n_f: entries of flag f); identical
+    (w, id, flag) entries count once; the C smallest (w, id) survivors per flag
+    are kept; old members also kept as new are dropped."""
+    N, K = st.ids.shape
+    pools = [[] for _ in range(N)]
+    for u in range(N):
+        for k in range(K):
+            v = int(st.ids[u, k])
+            f = int(st.flags[u, k])
+            w = oracle.hash64(seed, 2, t, min(u, v), max(u, v)) >> 32
+            pools[u].append((w, v, f))
+            pools[v].append((w, u, f))
+    out = []
+    for u in range(N):
+        n = {f: sum(1 for e in pools[u] if e[2] == f) for f in (oracle.NEW, oracle.OLD)}
+        keep = sorted({e for e in pools[u] if e[0] * n[e[2]] < (C << 32)})
+        nw = [e[1] for e in keep if e[2] == oracle.NEW][:C]
+        od = [e[1] for e in keep if e[2] == oracle.OLD][:C]
+        out.append((nw, [x for x in od if x not in nw]))
+    return out
+
+
+@pytest.mark.parametrize("N,K,rho,seed,t", [(30, 5, 1.0, 1, 1), (40, 6, 0.5, 2, 3), (25, 8, 0.25, 3, 7)])
+def test_turbo_matches_definition_by_brute_force(oracle_lib, N, K, rho, seed, t):
+    """Brute force on tiny random states (mixed flags, mutual pairs present)."""
+    st = _random_state(N, K, seed)
+    C = oracle.cap(K, rho)
+    sm = oracle.sample(st, K, C, seed, t, sampling="turbo")
+    exp = _turbo_by_definition(st, C, seed, t)
+    for u in range(N):
+        assert sm.cnew[u].tolist() == exp[u][0]
+        assert sm.cold[u].tolist() == exp[u][1]
+        for k in range(K):
+            f = st.flags[u, k]
+            if f == oracle.NEW and int(st.ids[u, k]) in exp[u][0]:
+                f = oracle.OLD
+            assert sm.flags[u, k] == f
+
+
+def test_turbo_equals_heap_rule_when_pools_are_small(oracle_lib):
+    """With n_f <= C the coin keeps every entry (probability 1), so owners
+    whose pools of both flags are that small sample exactly as the heap rule."""
+    N, K, C = 400, 6, 6
+    st = _random_state(N, K, 11, p_new=0.5)
+    rev = [[0, 0] for _ in range(N)]
+    for u in range(N):
+        for k in range(K):
+            rev[u][int(st.flags[u, k] == oracle.NEW)] += 1
+            rev[int(st.ids[u, k])][int(st.flags[u, k] == oracle.NEW)] += 1
+    small = [u for u in range(N) if max(rev[u]) <= C]
+    assert len(small) > 20
+    a = oracle.sample(st, K, C, 11, 2, sampling="turbo")
+    b = oracle.sample(st, K, C, 11, 2, sampling="weighted")
+    for u in small:
+        assert a.cnew[u].tolist() == b.cnew[u].tolist()
+        assert a.cold[u].tolist() == b.cold[u].tolist()
+        assert np.array_equal(a.flags[u], b.flags[u])
+
+
+def test_turbo_kept_counts_follow_the_coin(oracle_lib):
+    """Each entry of flag f passes with probability C/n_f (Sec. 3.1), so on a
+    random graph (mutual pairs rare) the kept count of flag f is
+    min(C, Binomial(n_f, C/n_f)). The total over owners must match the sum of
+    those expectations within 6 standard deviations; counting the whole pool
+    instead of the flag's entries, or skipping the coin, moves it far out."""
+    from scipy.stats import binom
+    N, K, rho = 6000, 10, 0.5
+    C = oracle.cap(K, rho)
+    st = _random_state(N, K, 5, p_new=0.7)
+    n = np.zeros((N, 2), np.int64)
+    for u in range(N):
+        for k in range(K):
+            j = 1 if st.flags[u, k] == oracle.NEW else 0
+            n[u, j] += 1
+            n[int(st.ids[u, k]), j] += 1
+    sm = oracle.sample(st, K, C, 5, 4, sampling="turbo")
+    for j, got in ((1, sum(len(a) for a in sm.cnew)), (0, sum(len(a) for a in sm.cold))):
+        mean = var = 0.0
+        for m in n[:, j]:
+            if m == 0:
+                continue
+            p = min(1.0, C / m)
+            x = np.arange(0, m + 1)
+            pm = binom.pmf(x, m, p)
+            y = np.minimum(x, C)
+            mu = float((pm * y).sum())
+            mean += mu
+            var += float((pm * (y - mu) ** 2).sum())
+        assert abs(got - mean) < 6 * math.sqrt(var) + 0.002 * mean, (got, mean, math.sqrt(var))
+    assert sum(len(a) for a in sm.cnew) < sum(min(C, m) for m in n[:, 1])
+
+
+def test_turbo_new_sample_is_within_heap_sample(oracle_lib):
+    """The coin only removes entries from the heap rule's ordering, so per owner
+    the turbo new sample is a prefix of the heap rule's new sample, and at t = 1
+    (every flag NEW) e_1 cannot exceed the heap rule's."""
+    X, _ = synth.config(1, N=800)
+    K, C = 10, oracle.cap(10, 1.0)
+    st = oracle.init(X, K, 9)
+    a = oracle.sample(st, K, C, 9, 1, sampling="turbo")
+    b = oracle.sample(st, K, C, 9, 1, sampling="weighted")
+    for u in range(800):
+        assert b.cnew[u].tolist()[:len(a.cnew[u])] == a.cnew[u].tolist()
+    _, ea, _ = oracle.iterate(X, st, K, C, 9, "turbo")
+    _, eb, _ = oracle.iterate(X, st, K, C, 9, "weighted")
+    assert ea < eb
+
+
+def test_turbo_build_converges(oracle_lib):
+    """A turbosampled build still finds most exact neighbours (recall vs brute force)."""
+    X, _ = synth.config(1, N=1500)
+    K = 10
+    r = oracle.build_graph_c(X, K, 1.0, 0.001, 30, 4, sampling="turbo")
+    ids, _ = oracle.bruteforce(X, K)
+    rec = np.mean([len(set(r.ids[u]) & set(ids[u])) / K for u in range(1500)])
+    assert r.iters < 30 and rec > 0.9
+
+
 # --------------------------------------------------------------------------- join + merge
 
 def test_exact_knn_is_a_fixed_point(oracle_lib):

@@ -38,3 +38,17 @@ def test_batched_sizes():
     Ns = [x.shape[0] for x, _ in b]
     ds = {x.shape[1] for x, _ in b}
     assert min(Ns) >= 500 and max(Ns) <= 20000 and ds <= {16, 64, 128}
+
+
+def test_paper_gaussian_datasets():
+    """Sec. 4: single variant ~ N(0, 2I); non-single variant: mean e_i/d per
+    coordinate (uniform over the d basis centres), covariance 2I + the
+    spread of the centres."""
+    X = synth.single_gaussian(200000, 4, 1).astype(np.float64)
+    assert np.allclose(X.mean(0), 0.0, atol=0.02)
+    assert np.allclose(np.cov(X.T), 2.0 * np.eye(4), atol=0.03)
+    d = 8
+    Y = synth.synthetic_gaussian(400000, d, 2).astype(np.float64)
+    assert np.allclose(Y.mean(0), 1.0 / d, atol=0.02)
+    centre_cov = np.eye(d) / d - np.full((d, d), 1.0 / d**2)
+    assert np.allclose(np.cov(Y.T), 2.0 * np.eye(d) + centre_cov, atol=0.03)

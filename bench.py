@@ -35,6 +35,12 @@ WORKLOADS = {
                        gen=lambda: __import__("synth").lowd_blobs(4_000_000, 2)),
     "batch512": dict(workload="batch512", N=None, d=None, K=15, rho=1.0, delta=0.001, max_iters=30, seed=4,
                      gen=lambda: __import__("synth").batched_datasets(512, 4)),
+    # the paper's selection-step workload (Sec. 4: Synthetic Gaussian Dataset, n = 16384, d = 8)
+    "gauss16k_d8": dict(workload="gauss16k_d8", N=16384, d=8, K=20, rho=1.0, delta=0.001, max_iters=30, seed=6,
+                        gen=lambda: __import__("synth").synthetic_gaussian(16384, 8, 6)),
+    # audio-shaped stand-in (Sec. 4: Audio dataset, 54387 x 192)
+    "audio54k_d192": dict(workload="audio54k_d192", N=54387, d=192, K=20, rho=1.0, delta=0.001, max_iters=30,
+                          seed=7, gen=lambda: __import__("synth").audio_like(54387, 192, 7)),
     "aniso200k_d960": dict(workload="aniso200k_d960", N=200_000, d=960, K=20, rho=0.5, delta=0.001, max_iters=30,
                            seed=3, gen=lambda: __import__("synth").anisotropic_clusters(200_000, 960, 3)),
 }
@@ -77,9 +83,10 @@ def recall_of(X, ids, tau, rows, rel=1e-5):
     return good / (len(rows) * ids.shape[1])
 
 
-def cpu_baseline(Xnp, w, budget_s=20.0):
+def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted"):
     """FP64 oracle on the host: init + iterations 1, 2, ... of the same workload
-    until ~budget_s of CPU work; evals/s over the iterations run."""
+    (same sampling rule) until ~budget_s of CPU work; evals/s over the
+    iterations run."""
     import oracle
     oracle.build(force=False)
     C = oracle.cap(w["K"], w["rho"])
@@ -88,7 +95,7 @@ def cpu_baseline(Xnp, w, budget_s=20.0):
     ev = 0
     iters = 0
     while time.perf_counter() - t0 < budget_s and iters < w["max_iters"]:
-        st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"])
+        st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"], sampling)
         ev += e
         iters += 1
     dt = time.perf_counter() - t0
@@ -116,7 +123,7 @@ def member_counts_and_graphs(X, w, args, iters, keep_graphs):
     asked, the graph G_t."""
     import paper_2112_06630_amd as knng
     ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                       path=args.path, precision=args.precision)
+                       path=args.path, precision=args.precision, sampling=args.sampling)
     ctx.init()
     members, graphs = [], []
     for _ in range(iters):
@@ -242,9 +249,10 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
 
 
 def run_sweep(args):
-    """The paper's scaling sweeps (Sec. 4) on its Synthetic Single Gaussian
-    Dataset (covariance 2 I): dimension d = 8, 72, ..., 3144 at n = 16384, or
-    size n = 2^10 .. 2^20 at d = 256; K = 20, rho = 1, delta = 0.001, T = 30.
+    """The paper's scaling sweeps (Sec. 4): dimension d = 8, 72, ..., 3144 at
+    n = 16384 on its Synthetic Single Gaussian Dataset, or size n = 2^10 ..
+    2^20 at d = 256 on its Synthetic Gaussian Dataset (one Gaussian per basis
+    vector); covariance 2 I; K = 20, rho = 1, delta = 0.001, T = 30.
     "lowd": d = 8, 16, ..., 96 at n = 16384, where the direct-form (VALU) join
     still fits its LDS stage, to place the VALU / matrix-core crossover.
     Every join path the plan accepts at a point is timed (wall clock of whole
@@ -263,10 +271,11 @@ def run_sweep(args):
     else:
         pts = [(1 << e, 256) for e in range(10, 21)]
     for N, d in pts:
-        X = torch.from_numpy(synth.single_gaussian(N, d, seed)).to(dev)
+        gen = synth.synthetic_gaussian if args.sweep == "n" else synth.single_gaussian
+        X = torch.from_numpy(gen(N, d, seed)).to(dev)
         for path in ("valu", "mfma", "bf16x3"):
             try:
-                p = knng.make_params(K, rho, delta, T, seed, False, path=path)
+                p = knng.make_params(K, rho, delta, T, seed, False, path=path, sampling=args.sampling)
                 ws = torch.empty(knng.workspace_bytes(N, d, p), dtype=torch.uint8, device=dev)
             except Exception:
                 continue   # the path does not take this shape (VALU: rows must fit the LDS stage)
@@ -274,7 +283,8 @@ def run_sweep(args):
                 continue
             ids = torch.empty((N, K), dtype=torch.int32, device=dev)
             dists = torch.empty((N, K), dtype=torch.float32, device=dev)
-            run = lambda: knng.build(X, K, rho, delta, T, seed, False, path=path, workspace=ws, out=(ids, dists))
+            run = lambda: knng.build(X, K, rho, delta, T, seed, False, path=path, workspace=ws, out=(ids, dists),
+                                     sampling=args.sampling)
             for _ in range(max(1, args.warmup)):
                 run()
             torch.cuda.synchronize()
@@ -285,7 +295,8 @@ def run_sweep(args):
             st = sts[-1]
             ev = sum(st["evals"])
             join = float(sum(st["join_ms"]))
-            print(json.dumps({"sweep": args.sweep, "N": N, "d": d, "path": path, "ms_per_build": round(ms, 3),
+            print(json.dumps({"sweep": args.sweep, "N": N, "d": d, "path": path, "sampling": args.sampling,
+                              "ms_per_build": round(ms, 3),
                               "iters": st["iters"], "evals": ev, "evals_per_s": round(ev / (ms / 1e3), 1),
                               "paper_gflops": round(ev * (3 * d - 1) / (ms / 1e3) / 1e9, 2),
                               "alg_tflops": round(ev * 2 * d / (ms / 1e3) / 1e12, 3),
@@ -303,6 +314,9 @@ def main():
     ap.add_argument("--workload", default="image60k_d784", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "bf16x3"])
+    ap.add_argument("--delta", type=float, default=None, help="override the workload's stop threshold")
+    ap.add_argument("--sampling", default="weighted", choices=["weighted", "turbo"],
+                    help="selection-step rule (Sec. 3.1): bounded heaps or turbosampling")
     ap.add_argument("--recall-rows", type=int, default=100000,
                     help="query rows for recall (all rows when N is smaller; a seeded sample otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -332,7 +346,9 @@ def main():
     import synth
     import paper_2112_06630_amd as knng
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    if args.delta is not None:
+        w["delta"] = args.delta
     if args.workload == "batch512":
         bench_batch(args, w)
         return
@@ -340,12 +356,13 @@ def main():
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
     p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                         path=args.path, precision=args.precision)
+                         path=args.path, precision=args.precision, sampling=args.sampling)
     ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
     ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
     dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
     run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
-                             path=args.path, workspace=ws, out=(ids, dists), precision=args.precision)
+                             path=args.path, workspace=ws, out=(ids, dists), precision=args.precision,
+                             sampling=args.sampling)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -401,6 +418,7 @@ def main():
     # time to recall 0.99: per-iteration graphs from the same step-API replay
     rec = None
     t99 = None
+    rcurve = None
     if not args.no_recall:
         N = w["N"]
         if N <= args.recall_rows:
@@ -412,8 +430,10 @@ def main():
         curve = [recall_of(X, ids_t, tau, rows) for ids_t in curve_ids]
         rec = curve[-1]
         cum = s0["init_ms"] + s0["reorder_ms"]
+        rcurve = []
         for t, r in enumerate(curve):
             cum += float(np.median([s["iter_ms"][t] for s in stats]))
+            rcurve.append([round(cum, 4), round(r, 6)])
             if r >= 0.99 and t99 is None:
                 t99 = cum
     # context: a plain device-to-device copy of 1 GiB (1 GiB read + 1 GiB written)
@@ -428,7 +448,7 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) / 1e3) / 1e9
     del src, dst
-    cpu = None if args.no_cpu else cpu_baseline(Xnp, w)
+    cpu = None if args.no_cpu else cpu_baseline(Xnp, w, sampling=args.sampling)
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
 
@@ -440,9 +460,11 @@ def main():
         "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
                    "reorder": bool(args.reorder), "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
-                   "precision": args.precision},
+                   "precision": args.precision, "sampling": args.sampling},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
         "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
+        "recall_curve": rcurve,   # [device ms since the build began, recall of G_t] per iteration
+        "evals_per_iter": [int(e) for e in s0["evals"]],
         "rescored_per_build": int(sum(s0.get("rescored", []))),
         "reorder_ms": round(float(s0["reorder_ms"]), 3), "init_ms": round(float(s0["init_ms"]), 3),
         "device_ms_per_build": round(float(np.median([s["total_ms"] for s in stats])), 3),

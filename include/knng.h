@@ -101,6 +101,29 @@ typedef enum {
     KNNG_PATH_MFMA_BF16X3 = 4   /* split-BF16 Gram form on BF16 MFMA tiles, FP32 accumulation */
 } knng_path;
 
+/*
+ * Sampling rules of the selection step (Sec. 3.1). Both sample new and old
+ * members separately, at most C = ceil(rho*K) of each, from the pool of u:
+ * its forward entries and the reverse entries (w, u) of every w listing u,
+ * each carrying the weight w = H(seed, t, min, max) >> 32 of its pair.
+ *
+ * KNNG_SAMPLING_WEIGHTED: the C entries of smallest (w, id) per flag (the
+ *   bounded-heap rule: a uniform subset of min(C, n) distinct members).
+ * KNNG_SAMPLING_TURBO: turbosampling. Each entry of flag f passes a coin of
+ *   probability C / n_f(u), n_f(u) being the number of pool entries of flag f
+ *   (forward plus reverse, with multiplicity: the neighbourhood size the paper
+ *   keeps per node); the coin is the same weight, passing iff
+ *   w * n_f(u) < C * 2^32. At most C survivors per flag are kept (those of
+ *   smallest (w, id)), so each flag keeps about C members in expectation and
+ *   never more than C. Needs ceil(rho*K) <= 30.
+ * In both, an old member also sampled as new is dropped from the old sample,
+ * and forward NEW entries of sampled new members become OLD.
+ */
+typedef enum {
+    KNNG_SAMPLING_WEIGHTED = 0,
+    KNNG_SAMPLING_TURBO = 1
+} knng_sampling;
+
 typedef struct {
     int32_t K;          /* list length, 1 <= K <= 64 and K <= N-1 (Sec. 2: k) */
     double rho;         /* sample rate, 0 < rho <= 1 (Sec. 3.1: rho*k per neighbourhood) */
@@ -110,6 +133,7 @@ typedef struct {
     int32_t precision;  /* knng_precision */
     int32_t reorder;    /* 1: graph-ordered point permutation after iteration 1 (Sec. 3.2) */
     int32_t path;       /* knng_path */
+    int32_t sampling;   /* knng_sampling (Sec. 3.1) */
 } knng_params;
 
 #define KNNG_MAX_ITERS 64

@@ -19,7 +19,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["build", "Context", "Params", "workspace_bytes", "sample_cap", "KnngError", "LIB_PATH",
-           "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "PATH_MFMA_I8", "PATH_MFMA_BF16X3", "MAX_ITERS", "lib"]
+           "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "PATH_MFMA_I8", "PATH_MFMA_BF16X3", "MAX_ITERS", "lib",
+           "SAMPLING_WEIGHTED", "SAMPLING_TURBO"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libknng.so")
@@ -27,6 +28,8 @@ LIB_PATH = os.path.join(_HERE, "libknng.so")
 PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_I8, PATH_MFMA_BF16X3 = 0, 1, 2, 3, 4
 _PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_i8": PATH_MFMA_I8,
           "bf16x3": PATH_MFMA_BF16X3}
+SAMPLING_WEIGHTED, SAMPLING_TURBO = 0, 1
+_SAMPLING = {"weighted": SAMPLING_WEIGHTED, "turbo": SAMPLING_TURBO}
 MAX_ITERS = 64
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV = 0, 1, 2, 3, 4
@@ -41,7 +44,7 @@ class KnngError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("rho", ctypes.c_double), ("delta", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("path", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("path", ctypes.c_int32), ("sampling", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -102,11 +105,13 @@ _PRECISIONS = {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16_SCREEN}
 
 
 def make_params(K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
-                reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32") -> Params:
+                reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32",
+                sampling: str | int = "weighted") -> Params:
     pth = _PATHS[path] if isinstance(path, str) else int(path)
     prc = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    smp = _SAMPLING[sampling] if isinstance(sampling, str) else int(sampling)
     return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, prc,
-                  1 if reorder else 0, pth)
+                  1 if reorder else 0, pth, smp)
 
 
 def sample_cap(K: int, rho: float) -> int:
@@ -144,7 +149,7 @@ def _stats_dict(s: _Stats) -> dict:
 
 def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
           reorder: bool = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
-          out: tuple | None = None, precision: str | int = "fp32"):
+          out: tuple | None = None, precision: str | int = "fp32", sampling: str | int = "weighted"):
     """K-NN graph of the rows of X (device float32 [N, d]).
 
     Returns (ids int32 [N, K], dists float32 [N, K] squared l2, stats dict);
@@ -153,7 +158,7 @@ def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_i
     """
     _check_x(X)
     N, d = X.shape
-    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision)
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
     ws = workspace_bytes(N, d, p)
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(ws, dtype=torch.uint8, device=X.device)
@@ -180,12 +185,13 @@ class Context:
     """Step API: one build whose state lives in a caller-held workspace."""
 
     def __init__(self, X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
-                 seed: int = 0, reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32"):
+                 seed: int = 0, reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32",
+                 sampling: str | int = "weighted"):
         _check_x(X)
         self.X = X
         self.N, self.d = X.shape
         self.K = K
-        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path, precision)
+        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
         self.C = sample_cap(K, rho)
         self.ws_bytes = workspace_bytes(self.N, self.d, self.params)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=X.device)
@@ -291,7 +297,8 @@ class Batch:
     """
 
     def __init__(self, Xs, seeds, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
-                 path: str | int = "auto", tuning: str | None = None, stream=None):
+                 path: str | int = "auto", tuning: str | None = None, stream=None,
+                 sampling: str | int = "weighted"):
         if len(Xs) != len(seeds) or not Xs:
             raise ValueError("one seed per dataset")
         for X in Xs:
@@ -308,7 +315,7 @@ class Batch:
         for i, (X, s) in enumerate(zip(Xs, seeds)):
             self._descs[i] = _Dataset(X.data_ptr(), X.shape[0], X.shape[1], 0, int(s) & 0xFFFFFFFFFFFFFFFF,
                                       self.ids[i].data_ptr(), self.dists[i].data_ptr())
-        self.params = make_params(K, rho, delta, max_iters, 0, False, path)
+        self.params = make_params(K, rho, delta, max_iters, 0, False, path, sampling=sampling)
         nb = int(lib.knng_batch_workspace_bytes(self._descs, n, ctypes.byref(self.params)))
         if nb == 0:
             raise KnngError(EINVAL, _err())

@@ -63,6 +63,7 @@ struct Plan {
     int dp;
     int dpi;         // int8 row length of the exact integer form
     int split;       // split-BF16 copies of the rows
+    int turbo;       // turbosampling coin (knng_sampling)
     int rev_shift, rev_S, rev_B, rev_E;   // counting-sort reverse bucketing (rev_S = 0: atomics)
     int C;
     int64_t pmax;    // proposal slots
@@ -85,6 +86,10 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
         return fail(KNNG_EINVAL, "max_iters must be in [0, 64]");
     if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_BF16X3) return fail(KNNG_EINVAL, "unknown path");
+    if (p->sampling != KNNG_SAMPLING_WEIGHTED && p->sampling != KNNG_SAMPLING_TURBO)
+        return fail(KNNG_EINVAL, "unknown sampling rule");
+    if (p->sampling == KNNG_SAMPLING_TURBO && 2 * sample_cap(p->K, p->rho) > 60)
+        return fail(KNNG_EINVAL, "turbosampling needs ceil(rho*K) <= 30");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
     return KNNG_OK;
 }
@@ -106,6 +111,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     if (s != KNNG_OK) return s;
     const int K = p->K;
     P.C = sample_cap(K, p->rho);
+    P.turbo = p->sampling == KNNG_SAMPLING_TURBO ? 1 : 0;
     int path = p->path;
     P.bf16 = p->precision == KNNG_BF16_SCREEN ? 1 : 0;
     P.want_i8 = 0;
@@ -238,6 +244,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.dp = P.dp;
     v.K = K;
     v.C = P.C;
+    v.turbo = P.turbo;
     v.Xp = reinterpret_cast<float*>(b + P.o_Xp);
     v.nrm = reinterpret_cast<float*>(b + P.o_nrm);
     v.orig = reinterpret_cast<int32_t*>(b + P.o_orig);

@@ -39,6 +39,7 @@ constexpr int kMaxI8Dim = 32768;   // d * 255^2 and the int32 Gram terms stay be
 // Views of the caller's workspace, carved by the host.
 struct Views {
     int N, d, dp, K, C;
+    int turbo;          // 1: turbosampling coin in the sampling step (Sec. 3.1)
     float* Xp;          // [N, dp] rows in position order, zero padded
     float* nrm;         // [N] squared norms (Gram path)
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null

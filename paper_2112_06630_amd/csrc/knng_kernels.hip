@@ -1026,6 +1026,12 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
 // each and sorted like a small pool. Each search step is one ballot-count
 // pass over the pool. OLD entries whose member was sampled NEW are removed
 // by comparing with the (at most C) sampled new ids.
+// Turbosampling coin (Sec. 3.1): an entry of weight wt among n entries of its
+// flag passes with probability C/n, i.e. iff wt * n < C * 2^32 (exact).
+__device__ __forceinline__ bool turbo_coin(uint32_t wt, uint32_t n, uint32_t C) {
+    return (uint64_t)wt * n < ((uint64_t)C << 32);
+}
+
 __device__ __forceinline__ uint64_t sel_key(uint32_t wt, uint32_t id, uint32_t pf) {
     return ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
 }
@@ -1172,16 +1178,17 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
         const uint64_t mv = ballot(valid);
         const uint32_t r = mbcnt(mv);
         const uint32_t id = (uint32_t)(key >> 1) & 0x7fffffffu;
+        const bool coin = !v.turbo || turbo_coin((uint32_t)(key >> 32), tot[f], C);
         uint32_t pos = 0;
-        if (valid && r < C) {
+        if (valid && r < C && coin) {
             uint32_t wt2, id2, pf2;
             pool_read(v, st, u, ou, rb, (int)idx, wt2, id2, pf2);
             pos = pf2 & kPosMask;
         }
         if (f == 0) {
-            const bool sel = valid && r < C;
+            const bool sel = valid && r < C && coin;
             const int s1 = __shfl_up(sel ? 1 : 0, 1);
-            nnew = min(C, (uint32_t)__popcll(mv));
+            nnew = (uint32_t)__popcll(ballot(sel));
             if (sel) cs[r] = make_uint2(id, pos);
             // forward NEW entries of sampled members flip to OLD once the OLD
             // pass (which reads the flags as sampled) is done; the forward copy
@@ -1205,10 +1212,10 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
                 const uint32_t nk = rl32(newid, (int)k);
                 innew |= nk == id;
             }
-            const bool cand_old = valid && r < C;
+            const bool cand_old = valid && r < C && coin;
             const bool removed = cand_old && innew;
             const uint64_t mrem = ballot(removed);
-            nold = min(C, (uint32_t)__popcll(mv)) - (uint32_t)__popcll(mrem);
+            nold = (uint32_t)__popcll(ballot(cand_old)) - (uint32_t)__popcll(mrem);
             if (cand_old && !removed) cs[nnew + r - mbcnt(mrem)] = make_uint2(id, pos);
         }
     }
@@ -1282,15 +1289,23 @@ __device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t,
     const bool isnew = (key & 1ull) == 0;
     const uint64_t mnew = ballot(valid && isnew) & seg, mold = ballot(valid && !isnew) & seg;
     const uint32_t rnew = mbcnt(mnew), rold = mbcnt(mold);
-    const bool seln = valid && isnew && rnew < C;
+    // turbosampling: the entry's coin against its flag's pool count (with
+    // multiplicity); survivors are a prefix of the flag's ranks
+    bool coin = true;
+    if (v.turbo) {
+        const uint32_t nf = (uint32_t)__popcll(ballot(real && isnew) & seg);
+        const uint32_t no = (uint32_t)__popcll(ballot(real && !isnew) & seg);
+        coin = turbo_coin((uint32_t)(key >> 32), isnew ? nf : no, C);
+    }
+    const bool seln = valid && isnew && rnew < C && coin;
     const bool s1 = __shfl_up(seln ? 1 : 0, 1) != 0, s2 = __shfl_up(seln ? 1 : 0, 2) != 0;
     const bool twin = !isnew && ((sl >= 1 && (p1 | 1ull) == key && !(p1 & 1ull) && s1) ||
                                  (sl >= 2 && (p2 | 1ull) == key && !(p2 & 1ull) && s2));
-    const bool cold = valid && !isnew && rold < C;
+    const bool cold = valid && !isnew && rold < C && coin;
     const bool removed = cold && twin;
     const uint64_t mrem = ballot(removed) & seg;
-    const uint32_t nnew = min(C, (uint32_t)__popcll(mnew));
-    const uint32_t nold = min(C, (uint32_t)__popcll(mold)) - (uint32_t)__popcll(mrem);
+    const uint32_t nnew = (uint32_t)__popcll(ballot(seln) & seg);
+    const uint32_t nold = (uint32_t)__popcll(ballot(cold) & seg) - (uint32_t)__popcll(mrem);
     const uint32_t ei = idx & (W - 1);
     if (u < N) {
         uint2* cs = v.cand + (size_t)u * 2 * C;

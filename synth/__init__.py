@@ -145,6 +145,36 @@ def anisotropic_clusters(N: int = 200_000, d: int = 960, seed: int = 3, n_cluste
     return X
 
 
+def audio_like(N: int = 54387, d: int = 192, seed: int = 7, n_speakers: int = 30, rank: int = 16,
+               ar: float = 0.9):
+    """Stand-in for the shape of the Audio dataset of Sec. 4 (54387 frames of
+    192 features from spoken English sentences; the real set is not used).
+
+    Frames come in sentences (lengths 20 + Geometric(1/60)) of one speaker
+    each; a speaker has a mean m_s ~ N(0, I) and a rank-16 mixing A_s; within
+    a sentence a latent z_t follows an AR(1) walk (coefficient 0.9, unit
+    stationary variance) and the frame is (m_s + A_s z_t / 4 + 0.1 N(0, I))
+    times per-feature scales 1 / sqrt(1 + j / 24), j = 0..d-1 (feature
+    variance falling along the vector, as in spectral features)."""
+    from scipy.signal import lfilter
+    rng = np.random.default_rng(seed)
+    scale = (1.0 / np.sqrt(1.0 + np.arange(d) / 24.0)).astype(np.float64)
+    means = rng.standard_normal((n_speakers, d))
+    mix = rng.standard_normal((n_speakers, d, rank)) / math.sqrt(rank)
+    X = np.empty((N, d), np.float32)
+    s = 0
+    while s < N:
+        L = min(N - s, 20 + int(rng.geometric(1.0 / 60.0)))
+        spk = int(rng.integers(0, n_speakers))
+        eps = rng.standard_normal((L, rank))
+        z = lfilter([math.sqrt(1.0 - ar * ar)], [1.0, -ar], eps, axis=0)
+        z[0] = eps[0]
+        fr = means[spk] + 0.25 * z @ mix[spk].T + 0.1 * rng.standard_normal((L, d))
+        X[s:s + L] = (fr * scale).astype(np.float32)
+        s += L
+    return X
+
+
 def batched_datasets(count: int = 512, seed: int = 4, n_lo: int = 500, n_hi: int = 20000,
                      dims=(16, 64, 128)):
     """Independent Gaussian-mixture datasets of uneven N and d.

@@ -5,6 +5,11 @@ exact integer below 2^24 in FP32 and in the split-BF16 form, so the whole
 GPU graph, e_t and c_t must equal the FP64 oracle's full build bit for bit (about 15 s of oracle on 8
 host threads).
 
+audio54k_d192 (an audio-shaped stand-in, 54387 x 192 continuous features,
+K=20, rho=1): one iteration from the oracle's G_0 against its G_1 within the
+FP32 Gram-form bound, and the whole build checked on sampled rows against
+brute force and against the oracle's own build.
+
 blobs4m_d3 and aniso200k_d960 are too large for a full oracle build in a test;
 their sampled rows are checked one by one against brute force from the
 oracle: stored distances within the FP32 bound, rows sorted, distinct, no
@@ -16,6 +21,7 @@ import torch
 
 import oracle
 import synth
+from parity import check_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -97,3 +103,27 @@ def test_aniso200k_sampled_rows(knng):
     assert st["path"] == knng.PATH_MFMA_BF16X3
     rows = np.random.default_rng(1).choice(X.shape[0], 128, replace=False)
     _check_sampled(X, ids.cpu().numpy(), dists.cpu().numpy(), rows, p["K"], 960, True, 0.5)
+
+
+def test_audio54k_step_and_build(knng):
+    X = synth.audio_like(54387, 192, 7)
+    K, rho, delta, T, seed = 20, 1.0, 0.001, 30, 7
+    C = oracle.cap(K, rho)
+    s0 = oracle.init(X, K, seed)
+    s1, e1, _ = oracle.iterate(X, s0, K, C, seed)
+    ctx = knng.Context(_dev(X), K, rho, delta, T, seed)
+    ctx.load(torch.from_numpy(s0.ids), torch.from_numpy(s0.flags), 0)
+    eg, _ = ctx.iterate()
+    assert eg == e1
+    g = ctx.export()
+    res = check_rows(X, g.ids.cpu().numpy(), g.dists.cpu().numpy(), s1.ids, s1.dists, dpad=192, gram=True)
+    assert res["exact_rows"] >= X.shape[0] - 60, res
+    ctx.close()
+    ids, dists, st = knng.build(_dev(X), K, rho, delta, T, seed)
+    assert st["path"] == knng.PATH_MFMA_BF16X3 and st["converged"]
+    rows = np.random.default_rng(2).choice(X.shape[0], 400, replace=False)
+    rec = _check_sampled(X, ids.cpu().numpy(), dists.cpu().numpy(), rows, K, 192, True, 0.9)
+    ref = oracle.build_graph(X, K, rho, delta, T, seed)
+    _, ed = oracle.bruteforce_rows(X, K, rows)
+    ref_rec = float(np.mean(ref.dists[rows] <= ed[:, -1:] * (1 + 1e-5)))
+    assert rec >= ref_rec - 0.01, (rec, ref_rec)

@@ -52,3 +52,16 @@ def test_paper_gaussian_datasets():
     assert np.allclose(Y.mean(0), 1.0 / d, atol=0.02)
     centre_cov = np.eye(d) / d - np.full((d, d), 1.0 / d**2)
     assert np.allclose(np.cov(Y.T), 2.0 * np.eye(d) + centre_cov, atol=0.03)
+
+
+def test_audio_like_shape():
+    """Audio-shaped stand-in: 54387 x 192 FP32, seeded, per-feature spread
+    falling along the vector, consecutive frames of a sentence close."""
+    X = synth.audio_like(54387, 192, 7)
+    assert X.shape == (54387, 192) and X.dtype == np.float32
+    assert np.array_equal(X[:100], synth.audio_like(54387, 192, 7)[:100])
+    sd = X.std(0)
+    assert sd[:16].mean() > 2 * sd[-16:].mean()
+    step = np.linalg.norm(X[1:2000] - X[:1999], axis=1)
+    rand = np.linalg.norm(X[1:2000] - X[np.random.default_rng(0).permutation(1999)], axis=1)
+    assert np.median(step) < 0.6 * np.median(rand)

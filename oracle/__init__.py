@@ -68,9 +68,10 @@ def _load():
     lib.orc_bruteforce.argtypes = [P, i64, i32, i32, P, P]
     lib.orc_bruteforce_rows.argtypes = [P, i64, i32, i32, P, i64, P, P]
     lib.orc_list_dists.argtypes = [P, i64, i32, i32, P, P]
+    lib.orc_greedy_order.argtypes = [P, i64, i32, P, P]
     lib.orc_num_threads.restype = ctypes.c_int
     for name in ("orc_init", "orc_sample", "orc_join_merge", "orc_iterate", "orc_build",
-                 "orc_bruteforce", "orc_bruteforce_rows", "orc_list_dists"):
+                 "orc_bruteforce", "orc_bruteforce_rows", "orc_list_dists", "orc_greedy_order"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -249,6 +250,17 @@ def bruteforce_rows(X, K: int, rows) -> tuple[np.ndarray, np.ndarray]:
     _check(_load().orc_bruteforce_rows(_ptr(X), N, d, K, _ptr(rows), len(rows), _ptr(ids),
                                        _ptr(dists)), "bruteforce_rows")
     return ids, dists
+
+
+def greedy_order(ids) -> tuple[np.ndarray, np.ndarray]:
+    """Sec. 3.2 greedy clustering heuristic on a list graph whose rows are
+    sorted nearest first: returns (sigma, sigma_inv), sigma[node] = spot."""
+    ids = np.ascontiguousarray(ids, np.int32)
+    N, K = ids.shape
+    sigma = np.empty(N, np.int32)
+    inv = np.empty(N, np.int32)
+    _check(_load().orc_greedy_order(_ptr(ids), N, K, _ptr(sigma), _ptr(inv)), "greedy_order")
+    return sigma, inv
 
 
 def list_dists(X, ids) -> np.ndarray:

@@ -442,6 +442,42 @@ int orc_build(const float *X, int64_t N, int32_t d, int32_t K, double rho, doubl
     return iters;
 }
 
+/* ---------------------------------------------------------------- greedy reordering
+ * Sec. 3.2 (Algorithm 1, greedy clustering heuristic): one pass over the list
+ * graph builds a permutation sigma (node -> memory spot) and its inverse, so
+ * that the node put at spot i+1 is the nearest listed neighbour of the node
+ * at spot i not already placed at a spot up to i. A host reference for the
+ * device permutation's locality; it does not change any list (the method's
+ * result keeps original ids).
+ * Readings: at step i the list scanned is that of the node occupying spot i
+ * (the chain the text describes), nearest first (rows are sorted by (D, id));
+ * the two swaps use the values from before the step (the node a moves to
+ * spot i+1 and the node there takes a's old spot); steps run for i = 0..n-2.
+ */
+int orc_greedy_order(const int32_t *ids, int64_t N, int32_t K, int32_t *sigma, int32_t *sigma_inv)
+{
+    if (!ids || !sigma || !sigma_inv || N < 1 || K < 1) return -1;
+    for (int64_t v = 0; v < N; ++v) {
+        sigma[v] = (int32_t)v;
+        sigma_inv[v] = (int32_t)v;
+    }
+    for (int64_t i = 0; i + 1 < N; ++i) {
+        const int32_t *a = ids + (int64_t)sigma_inv[i] * K;
+        for (int32_t j = 0; j < K; ++j) {
+            const int64_t s = sigma[a[j]];
+            if (s <= i) continue;      /* placed before: it sits near its own neighbours */
+            if (s == i + 1) break;     /* already next to the node at spot i */
+            const int32_t b = sigma_inv[i + 1];
+            sigma[a[j]] = (int32_t)(i + 1);
+            sigma[b] = (int32_t)s;
+            sigma_inv[i + 1] = a[j];
+            sigma_inv[s] = b;
+            break;
+        }
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- exact K-NN
  * Sec. 2: the trivial K-NNG evaluates all n(n-1)/2 distances and keeps the k
  * best. Used for recall. Ties broken by id, like the lists above. */

@@ -29,6 +29,9 @@ MUTANTS = {
     "merge_readds_listed_ids": ("if (!in_list) all[n++] = cand[i];", "all[n++] = cand[i];"),
     "weight_not_symmetric": ("uint32_t a = (uint32_t)(u < x ? u : x), b = (uint32_t)(u < x ? x : u);",
                              "uint32_t a = (uint32_t)x, b = (uint32_t)u;"),
+    "greedy_scans_list_of_node_i": ("const int32_t *a = ids + (int64_t)sigma_inv[i] * K;",
+                                    "const int32_t *a = ids + i * K;"),
+    "greedy_inverse_not_updated": ("sigma_inv[i + 1] = a[j];", ";"),
     "turbo_counts_whole_pool": ("nf[pool[i].flag == ORC_NEW ? 0 : 1] += 1;", "{ nf[0] += 1; nf[1] += 1; }"),
     "turbo_coin_skipped": ("if (mode == ORC_TURBO &&", "if (0 &&"),
     "turbo_coin_uses_k": ("* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)C << 32))",

@@ -334,6 +334,55 @@ def test_turbo_build_converges(oracle_lib):
     assert r.iters < 30 and rec > 0.9
 
 
+# --------------------------------------------------------------------------- greedy reordering (Alg. 1)
+
+def _window_purity(labels, w, stride):
+    n_lab = int(labels.max()) + 1
+    return np.array([np.bincount(labels[s:s + w], minlength=n_lab).max() / w
+                     for s in range(0, len(labels) - w + 1, stride)])
+
+
+def test_greedy_order_is_a_permutation_with_its_inverse(oracle_lib):
+    X, _ = synth.config(1, N=1500)
+    r = oracle.build_graph(X, 10, 1.0, 0.0, 1, 2)
+    sig, inv = oracle.greedy_order(r.ids)
+    assert sorted(sig.tolist()) == list(range(1500))
+    assert np.array_equal(inv[sig], np.arange(1500))
+    assert np.array_equal(sig[inv], np.arange(1500))
+
+
+def test_greedy_order_places_the_nearest_unplaced_neighbour_next(oracle_lib):
+    """Sec. 3.2: spots up to i never change after step i - 1, so in the final
+    order the node at spot i + 1 is the first entry of the (nearest-first) list
+    of the node at spot i that does not sit at a spot <= i, whenever there is
+    one; otherwise the step leaves spot i + 1 alone."""
+    X, _ = synth.config(1, N=1200)
+    r = oracle.build_graph(X, 8, 1.0, 0.0, 2, 4)
+    sig, inv = oracle.greedy_order(r.ids)
+    constrained = 0
+    for i in range(1199):
+        cand = [int(a) for a in r.ids[inv[i]] if sig[a] > i]
+        if cand:
+            assert inv[i + 1] == cand[0], i
+            constrained += 1
+    assert constrained > 600
+
+
+def test_greedy_order_recovers_clusters_first(oracle_lib):
+    """Sec. 4 (Fig. 4): on clustered data (n = 16384, d = 8, 8 clusters) the
+    order built from G_1 keeps long single-cluster runs at the start, where
+    many nodes are unplaced, and mixes towards 1/8 at the end."""
+    X, lab = synth.gaussian_mixture(16384, 8, 8, 3, return_labels=True)
+    st = oracle.init(X, 20, 3)
+    s1, _, _ = oracle.iterate(X, st, 20, 20, 3)
+    sig, inv = oracle.greedy_order(s1.ids)
+    pur = _window_purity(lab[inv], 2000, 1024)
+    base = _window_purity(lab, 2000, 1024).mean()
+    assert base < 0.2
+    assert pur[:8].mean() > 3 * base
+    assert pur[-2:].mean() < 0.25
+
+
 # --------------------------------------------------------------------------- join + merge
 
 def test_exact_knn_is_a_fixed_point(oracle_lib):

@@ -38,6 +38,9 @@ WORKLOADS = {
     # the paper's selection-step workload (Sec. 4: Synthetic Gaussian Dataset, n = 16384, d = 8)
     "gauss16k_d8": dict(workload="gauss16k_d8", N=16384, d=8, K=20, rho=1.0, delta=0.001, max_iters=30, seed=6,
                         gen=lambda: __import__("synth").synthetic_gaussian(16384, 8, 6)),
+    # the paper's reordering workload (Sec. 4, Fig. 5: Synthetic Clustered Dataset, 16384 points, 16 clusters, d = 8)
+    "clustered16k_d8": dict(workload="clustered16k_d8", N=16384, d=8, K=20, rho=1.0, delta=0.001, max_iters=30,
+                            seed=4, gen=lambda: __import__("synth").clustered_labels(16384, 8, 16, 4)[0]),
     # audio-shaped stand-in (Sec. 4: Audio dataset, 54387 x 192)
     "audio54k_d192": dict(workload="audio54k_d192", N=54387, d=192, K=20, rho=1.0, delta=0.001, max_iters=30,
                           seed=7, gen=lambda: __import__("synth").audio_like(54387, 192, 7)),
@@ -465,6 +468,7 @@ def main():
         "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
         "recall_curve": rcurve,   # [device ms since the build began, recall of G_t] per iteration
         "evals_per_iter": [int(e) for e in s0["evals"]],
+        "iter_ms": [round(float(np.median([s["iter_ms"][t] for s in stats])), 4) for t in range(s0["iters"])],
         "rescored_per_build": int(sum(s0.get("rescored", []))),
         "reorder_ms": round(float(s0["reorder_ms"]), 3), "init_ms": round(float(s0["init_ms"]), 3),
         "device_ms_per_build": round(float(np.median([s["total_ms"] for s in stats])), 3),

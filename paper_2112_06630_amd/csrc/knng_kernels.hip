@@ -113,11 +113,13 @@ __device__ __forceinline__ void cmpx(uint64_t& k, uint32_t& v, int j, bool asc) 
     const uint64_t ok = shfl_xor64(k, j);
     const uint32_t ov = xor_lanes(v, j);
     const bool low = (lane & j) == 0;
-    const bool sw = (asc == low) ? (ok < k) : (ok > k);
-    if (sw) {
-        k = ok;
-        v = ov;
-    }
+    // lane masks and selects, no branch: a conditional choice between the two
+    // comparisons compiles to divergent control flow per stage
+    const bool keep_min = asc == low;
+    const bool lt = ok < k, gt = k < ok;
+    const bool sw = (keep_min & lt) | (!keep_min & gt);
+    k = sw ? ok : k;
+    v = sw ? ov : v;
 }
 
 // Ascending bitonic sort of 64 (key, value) pairs, one per lane.
@@ -1235,6 +1237,46 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
     wave_sync();
 }
 
+// Ascending bitonic sort of distinct 32-bit keys within segments of W lanes
+// (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
+template <int W>
+__device__ __forceinline__ void seg_sort32(uint32_t& k) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= W; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint32_t o = xor_lanes(k, j);
+            const bool keep_min = (size == W || (lane & size) == 0) == ((lane & j) == 0);
+            k = keep_min ? min(k, o) : max(k, o);
+        }
+    }
+}
+
+// Odd-even transposition passes within W-lane segments on (key, value)
+// pairs until a pass swaps nothing (the wave leaves together): finishes the
+// order of a sequence that is already sorted up to short runs.
+template <int W>
+__device__ __forceinline__ void seg_fixup(uint64_t& key, uint32_t& val) {
+    const int lane = lane_id(), sl = lane & (W - 1);
+    for (int pass = 0; pass < W; ++pass) {
+        bool any = false;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            const bool lower = (sl & 1) == ph;    // phase 0: pairs (2i, 2i+1); phase 1: (2i+1, 2i+2)
+            const bool has = lower ? sl + 1 < W : sl >= 1;
+            const int partner = has ? (lower ? lane + 1 : lane - 1) : lane;
+            const uint64_t ok = shfl64(key, partner);
+            const uint32_t ov = (uint32_t)__shfl((int)val, partner);
+            const bool sw = has && (lower ? ok < key : key < ok);
+            key = sw ? ok : key;
+            val = sw ? ov : val;
+            any |= sw;
+        }
+        if (ballot(any) == 0ull) break;
+    }
+}
+
 // Ascending bitonic sort of (key, value) pairs within segments of W lanes
 // (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
 template <int W>
@@ -1253,15 +1295,14 @@ __device__ __forceinline__ void seg_sort(uint64_t& k, uint32_t& v) {
 // member reached by both routes with the same flag next to each other (the
 // second is a duplicate), and a member's NEW entry right before its OLD
 // entry. Ranks per flag are ballot prefix counts over the segment's sorted
-// lanes.
+// lanes. pool_load reads the entries (pos: the entry's position word).
 template <int W>
-__device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t, int u, int P) {
-    const int lane = lane_id(), sl = lane & (W - 1);
-    const uint64_t seg = W == 64 ? ~0ull : (lane < 32 ? 0x00000000ffffffffull : 0xffffffff00000000ull);
-    const int N = v.N, K = v.K;
-    const uint32_t C = (uint32_t)v.C;
-    uint64_t key = ~0ull;
-    uint32_t pos = 0;
+__device__ __forceinline__ void pool_load(const Views& v, uint64_t st0, int t, int u, int P, uint64_t& key,
+                                          uint32_t& pos) {
+    const int sl = lane_id() & (W - 1);
+    const int K = v.K;
+    key = ~0ull;
+    pos = 0;
     if (sl < P) {
         const uint32_t rb = v.roff[u];
         uint32_t id, pf, wt;
@@ -1279,8 +1320,39 @@ __device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t,
         key = ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
         pos = pf & kPosMask;
     }
-    uint32_t idx = (uint32_t)lane;   // the entry's lane; its pool index is idx & (W - 1)
-    seg_sort<W>(key, idx);
+}
+
+// Sort key of the proxy order: top 25 weight bits, the OLD bit, the entry's
+// lane in the segment (distinct, and in the select key's order wherever the
+// top weight bits differ). Padding lanes take the largest value; a real
+// proxy can equal it only in a full segment, so after the sort the first P
+// lanes hold the entries.
+template <int W>
+__device__ __forceinline__ uint32_t pool_proxy(uint64_t key, int P) {
+    const int sl = lane_id() & (W - 1);
+    return sl < P ? (((uint32_t)(key >> 32) & ~127u) | ((uint32_t)(key & 1ull) << 6) | (uint32_t)sl) : 0xffffffffu;
+}
+
+// After the proxy sort: fetch the full keys, then finish the order of the
+// rare runs of equal proxy weights on the full key. idx: source lane.
+template <int W>
+__device__ __forceinline__ void pool_unproxy(uint32_t k32, int P, uint64_t& key, uint32_t& idx) {
+    const int lane = lane_id(), sl = lane & (W - 1);
+    idx = (uint32_t)(lane & ~(W - 1)) | (k32 & (uint32_t)(W - 1));
+    const uint64_t fk = shfl64(key, (int)idx);   // every lane takes part in the exchange
+    key = sl < P ? fk : ~0ull;
+    seg_fixup<W>(key, idx);
+}
+
+// Ranks, the new/old samples and the flips of one owner per segment, from
+// its pool sorted by select key (key, source lane idx, positions pos by
+// source lane).
+template <int W>
+__device__ __forceinline__ void pool_finish(const Views& v, int u, uint64_t key, uint32_t idx, uint32_t pos) {
+    const int lane = lane_id(), sl = lane & (W - 1);
+    const uint64_t seg = W == 64 ? ~0ull : (lane < 32 ? 0x00000000ffffffffull : 0xffffffff00000000ull);
+    const int N = v.N, K = v.K;
+    const uint32_t C = (uint32_t)v.C;
     const uint32_t mpos = (uint32_t)__shfl((int)pos, (int)idx);
     const uint64_t p1 = shfl_up64(key, 1), p2 = shfl_up64(key, 2);
     const bool real = key != ~0ull;
@@ -1322,6 +1394,43 @@ __device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t,
     }
 }
 
+template <int W>
+__device__ __forceinline__ void select_pool(const Views& v, uint64_t st0, int t, int u, int P) {
+    uint64_t key;
+    uint32_t pos, idx;
+    pool_load<W>(v, st0, t, u, P, key, pos);
+    uint32_t k32 = pool_proxy<W>(key, P);
+    seg_sort32<W>(k32);
+    pool_unproxy<W>(k32, P, key, idx);
+    pool_finish<W>(v, u, key, idx, pos);
+}
+
+// Two owners of pools of at most 64 entries in one wave, one after the other
+// in registers: their loads are issued together and their sorts interleaved
+// stage by stage, so the two dependency chains overlap.
+__device__ __forceinline__ void select_pool_x2(const Views& v, uint64_t st0, int t, int ua, int Pa, int ub, int Pb) {
+    uint64_t ka, kb;
+    uint32_t pa, pb, ia, ib;
+    pool_load<64>(v, st0, t, ua, Pa, ka, pa);
+    pool_load<64>(v, st0, t, ub, Pb, kb, pb);
+    uint32_t xa = pool_proxy<64>(ka, Pa), xb = pool_proxy<64>(kb, Pb);
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint32_t oa = xor_lanes(xa, j), ob = xor_lanes(xb, j);
+            const bool keep_min = (size == 64 || (lane & size) == 0) == ((lane & j) == 0);
+            xa = keep_min ? min(xa, oa) : max(xa, oa);
+            xb = keep_min ? min(xb, ob) : max(xb, ob);
+        }
+    }
+    pool_unproxy<64>(xa, Pa, ka, ia);
+    pool_unproxy<64>(xb, Pb, kb, ib);
+    pool_finish<64>(v, ua, ka, ia, pa);
+    pool_finish<64>(v, ub, kb, ib, pb);
+}
+
 // Pool size of owner u (0: past N, or its dataset has finished).
 __device__ __forceinline__ int pool_size(const Views& v, int u) {
     if (u >= v.N || (v.ds && !pos_active(v, u))) return 0;
@@ -1329,7 +1438,8 @@ __device__ __forceinline__ int pool_size(const Views& v, int u) {
 }
 
 // Owners in pairs: two pools of at most 32 entries share one wave (one
-// 32-lane segment each: a 15-stage sort instead of 21); otherwise each owner
+// 32-lane segment each: a 15-stage sort instead of 21); two pools of at most
+// 64 are sorted side by side in the wave's registers; otherwise each owner
 // takes the wave alone. Pools of more than 64 entries take the threshold
 // select in the same wave when 2C <= 60 (their latency hides behind the
 // small pools), else k_select_large (big[u] = 1).
@@ -1353,6 +1463,10 @@ __global__ __launch_bounds__(256, 8) void k_select_small(Views v, uint64_t st0, 
         if (P0 <= 32 && P1 <= 32) {
             const bool hi = lane >= 32;
             select_pool<32>(v, st0, t, hi ? u1 : u0, hi ? P1 : P0);
+            continue;
+        }
+        if (P0 <= 64 && P1 <= 64) {
+            select_pool_x2(v, st0, t, u0, P0, u1 < N ? u1 : N, P1);
             continue;
         }
         for (int h = 0; h < 2; ++h) {

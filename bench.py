@@ -41,6 +41,11 @@ WORKLOADS = {
     # the paper's reordering workload (Sec. 4, Fig. 5: Synthetic Clustered Dataset, 16384 points, 16 clusters, d = 8)
     "clustered16k_d8": dict(workload="clustered16k_d8", N=16384, d=8, K=20, rho=1.0, delta=0.001, max_iters=30,
                             seed=4, gen=lambda: __import__("synth").clustered_labels(16384, 8, 16, 4)[0]),
+    # the paper's roofline workloads (Sec. 4, Fig. 3: Synthetic Gaussian Dataset, n = 131072, d = 8 and 256)
+    "gauss131k_d8": dict(workload="gauss131k_d8", N=131072, d=8, K=20, rho=1.0, delta=0.001, max_iters=30, seed=8,
+                         gen=lambda: __import__("synth").synthetic_gaussian(131072, 8, 8)),
+    "gauss131k_d256": dict(workload="gauss131k_d256", N=131072, d=256, K=20, rho=1.0, delta=0.001, max_iters=30,
+                           seed=8, gen=lambda: __import__("synth").synthetic_gaussian(131072, 256, 8)),
     # audio-shaped stand-in (Sec. 4: Audio dataset, 54387 x 192)
     "audio54k_d192": dict(workload="audio54k_d192", N=54387, d=192, K=20, rho=1.0, delta=0.001, max_iters=30,
                           seed=7, gen=lambda: __import__("synth").audio_like(54387, 192, 7)),
@@ -71,6 +76,22 @@ def exact_kth(X, K, rows):
         D[torch.arange(len(r), device=X.device), r] = float("inf")
         out[s:s + step] = torch.topk(D, K, dim=1, largest=False).values[:, -1]
     return out
+
+
+def dist_error(X, ids, dists, rows):
+    """Stored FP32 distances of the query rows against an FP64 recomputation
+    (torch on the GPU; evaluation only): max absolute error and max error
+    relative to the distance."""
+    Xd = X.double()
+    abs_max, rel_max = 0.0, 0.0
+    for s in range(0, len(rows), 2048):
+        r = rows[s:s + 2048]
+        diff = Xd[ids[r].long()] - Xd[r, None, :]
+        D = (diff * diff).sum(-1)
+        e = (dists[r].double() - D).abs()
+        abs_max = max(abs_max, float(e.max()))
+        rel_max = max(rel_max, float((e / D.clamp_min(1e-30)).max()))
+    return abs_max, rel_max
 
 
 def recall_of(X, ids, tau, rows, rel=1e-5):
@@ -422,6 +443,7 @@ def main():
     rec = None
     t99 = None
     rcurve = None
+    derr = None
     if not args.no_recall:
         N = w["N"]
         if N <= args.recall_rows:
@@ -432,6 +454,7 @@ def main():
         tau = exact_kth(X, w["K"], rows)
         curve = [recall_of(X, ids_t, tau, rows) for ids_t in curve_ids]
         rec = curve[-1]
+        derr = dist_error(X, ids, dists, rows)
         cum = s0["init_ms"] + s0["reorder_ms"]
         rcurve = []
         for t, r in enumerate(curve):
@@ -467,6 +490,8 @@ def main():
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
         "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
         "recall_curve": rcurve,   # [device ms since the build began, recall of G_t] per iteration
+        # stored FP32 distances of the recall rows vs FP64: max absolute and max relative error
+        "dist_err_vs_fp64": None if derr is None else {"abs": derr[0], "rel": derr[1]},
         "evals_per_iter": [int(e) for e in s0["evals"]],
         "iter_ms": [round(float(np.median([s["iter_ms"][t] for s in stats])), 4) for t in range(s0["iters"])],
         "rescored_per_build": int(sum(s0.get("rescored", []))),

@@ -178,10 +178,10 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     P.o_partial = take(partial_words() * 8);
     if (P.bf16) {
         P.o_Xb = take((size_t)N * P.dp * 2);
-        P.o_nb = take((size_t)N * 4);
+        P.o_nb = take((size_t)N * 8);
         if (p->reorder) {
             P.o_Xb2 = take((size_t)N * P.dp * 2);
-            P.o_nb2 = take((size_t)N * 4);
+            P.o_nb2 = take((size_t)N * 8);
         }
     }
     if (P.split) {
@@ -269,10 +269,10 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.partial = reinterpret_cast<uint64_t*>(b + P.o_partial);
     if (P.bf16) {
         v.Xb = reinterpret_cast<uint16_t*>(b + P.o_Xb);
-        v.nb = reinterpret_cast<float*>(b + P.o_nb);
+        v.nb = reinterpret_cast<float2*>(b + P.o_nb);
         if (P.reorder) {
             v.Xb2 = reinterpret_cast<uint16_t*>(b + P.o_Xb2);
-            v.nb2 = reinterpret_cast<float*>(b + P.o_nb2);
+            v.nb2 = reinterpret_cast<float2*>(b + P.o_nb2);
         }
     }
     if (P.reorder) {

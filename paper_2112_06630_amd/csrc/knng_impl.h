@@ -43,7 +43,7 @@ struct Views {
     float* Xp;          // [N, dp] rows in position order, zero padded
     float* nrm;         // [N] squared norms (Gram path)
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
-    float* nb;          // [N] squared norms of the BF16 rows
+    float2* nb;         // [N] BF16 rows: {squared norm, norm of the rounding error bf16(x) - x}
     uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
     int planes;         // split form: leading planes the join reads (1..3; the rest are all zero)
     int dpi;            // int8 row length (multiple of 64), exact integer form
@@ -107,7 +107,7 @@ struct Views {
     float* Xp2;         // [N, dp]
     float* nrm2;        // [N]
     uint16_t* Xb2;      // [N, dp]
-    float* nb2;         // [N]
+    float2* nb2;        // [N]
     int8_t* Xi2;        // [N, dpi]
     uint16_t* Xs2;      // [3, N, dp]
     int32_t* ni2;       // [N]

@@ -1860,13 +1860,17 @@ void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
 // snapshot filter is rescored in FP32 from the original rows, and only the
 // rescored distances are proposed, filtered exactly and stored.
 //
-// Screen bound. With x~ = bf16(x) rounded to nearest, |x~_j - x_j| <= u_b |x_j|,
-// u_b = 2^-8, so | ||x~-y~|| - ||x-y|| | <= eps = u_b (||x|| + ||y||) and
-// |D~e - D| <= 2 eps sqrt(D) + eps^2 for D~e the exact distance of the BF16 rows.
-// The tile computes D~ = n~x + n~y - 2 x~.y~ in FP32 (BF16 products are exact in
-// FP32) with |D~ - D~e| <= (d+3) 2^-24 (||x~|| + ||y~||)^2. A pair with D <= T
-// therefore has D~ <= T + 2 eps sqrt(T) + eps^2 + (d+3) 2^-24 (||x~|| + ||y~||)^2,
-// the test applied (in FP64, with the bound enlarged by 2^-20 relative).
+// Screen bound. With x~ = bf16(x) and e_x = ||x~ - x|| (the row's rounding
+// error, computed exactly when the copies are made: x~_j - x_j is exact in
+// FP32, its squares and sum are taken in FP64; e_x = 0 for rows exact in
+// BF16, such as 8-bit pixels, and e_x <= 2^-8 ||x|| always),
+// | ||x~-y~|| - ||x-y|| | <= ||(x~-x) - (y~-y)|| <= eps = e_x + e_y, so
+// |D~e - D| <= 2 eps sqrt(D) + eps^2 for D~e the exact distance of the BF16
+// rows. The tile computes D~ = n~x + n~y - 2 x~.y~ in FP32 (BF16 products are
+// exact in FP32) with |D~ - D~e| <= (d+3) 2^-24 (||x~|| + ||y~||)^2. A pair with
+// D <= T therefore has D~ <= T + 2 eps sqrt(T) + eps^2 + (d+3) 2^-24
+// (||x~|| + ||y~||)^2, the test applied (in FP64, with the bound enlarged by
+// 2^-20 relative).
 //
 // Rescore. One wave per pair: lane l sums (x_j - y_j)^2 over j = l, l+64, ...
 // in order, lane partials are added by a fixed tree and lane 0's value is
@@ -1885,6 +1889,7 @@ __global__ void k_make_bf16(Views v) {
         const float* x = v.Xp + (size_t)p * v.dp;
         uint16_t* y = v.Xb + (size_t)p * v.dp;
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        double r = 0.0;   // sum of squared rounding errors (each exact in FP32, squares exact in FP64)
         for (int j = 0; j < v.dp; j += 4) {
             const float4 a = *reinterpret_cast<const float4*>(x + j);
             const uint16_t b0 = bf16_rne(a.x), b1 = bf16_rne(a.y), b2 = bf16_rne(a.z), b3 = bf16_rne(a.w);
@@ -1897,8 +1902,13 @@ __global__ void k_make_bf16(Views v) {
             s1 = fmaf(f1, f1, s1);
             s2 = fmaf(f2, f2, s2);
             s3 = fmaf(f3, f3, s3);
+            const double e0 = (double)(f0 - a.x), e1 = (double)(f1 - a.y), e2 = (double)(f2 - a.z),
+                         e3 = (double)(f3 - a.w);
+            r += (e0 * e0 + e1 * e1) + (e2 * e2 + e3 * e3);
         }
-        v.nb[p] = (s0 + s1) + (s2 + s3);
+        // the FP64 sum's relative error (below d 2^-53) and the FP32 rounding of
+        // the norm (2^-24) are covered by the 2^-20 enlargement of the bound
+        v.nb[p] = make_float2((s0 + s1) + (s2 + s3), (float)(sqrt(r) * (1.0 + 1.0 / 1073741824.0)));
     }
 }
 
@@ -1928,8 +1938,10 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
-    __shared__ float s_nrm[kJoinWaves][64];
     __shared__ float s_nb[kJoinWaves][64];
+    __shared__ float s_eb[kJoinWaves][64];   // rounding-error norm of the member's BF16 row
+    __shared__ double s_sn[kJoinWaves][64];  // sqrt of the BF16 squared norm
+    __shared__ double s_st[kJoinWaves][64];  // sqrt of the snapshot threshold distance
     __shared__ uint32_t s_emit[kJoinWaves][3][64];
     __shared__ uint32_t s_surv[kJoinWaves][kBfMaxSurv];   // survivors: i | j << 8 | directions << 16
     __shared__ float s_sd[kJoinWaves][kBfMaxSurv];        // their rescored FP32 distances
@@ -1939,7 +1951,6 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
     emit_clear(el, 64);
     uint64_t rescored = 0;
-    const double ub = 1.0 / 256.0;
     const double cfp = (double)(dp + 3) * (1.0 / 16777216.0);
     const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
     for (int u = xr.next; u < xr.end; u += xr.step) {
@@ -1955,9 +1966,13 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
             const uint2 c = cs[lane];
             s_oid[w][lane] = c.x;
             s_pos[w][lane] = c.y;
-            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
-            s_nrm[w][lane] = v.nrm[c.y];
-            s_nb[w][lane] = v.nb[c.y];
+            const uint64_t thr = v.lkey[(size_t)c.y * K + K - 1];
+            const float2 nb = v.nb[c.y];
+            s_thr[w][lane] = thr;
+            s_nb[w][lane] = nb.x;
+            s_eb[w][lane] = nb.y;
+            s_sn[w][lane] = sqrt((double)nb.x);
+            s_st[w][lane] = sqrt((double)__uint_as_float((uint32_t)(thr >> 32)));
         }
         wave_sync();
         const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
@@ -2001,13 +2016,13 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
                         bool si = false, sj = false;
                         if (j < m && i < nnew && !(j < nnew && j <= i)) {
                             const double Dt = (double)((s_nb[w][i] + s_nb[w][j]) - 2.0f * acc[t][r]);
-                            const double eps = ub * (sqrt((double)s_nrm[w][i]) + sqrt((double)s_nrm[w][j]));
-                            const double nbs = sqrt((double)s_nb[w][i]) + sqrt((double)s_nb[w][j]);
+                            const double eps = (double)s_eb[w][i] + (double)s_eb[w][j];
+                            const double nbs = s_sn[w][i] + s_sn[w][j];
                             const double fp = cfp * nbs * nbs;
                             const double Ti = (double)__uint_as_float((uint32_t)(s_thr[w][i] >> 32));
                             const double Tj = (double)__uint_as_float((uint32_t)(s_thr[w][j] >> 32));
-                            const double mi = (2.0 * eps * sqrt(Ti) + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
-                            const double mj = (2.0 * eps * sqrt(Tj) + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
+                            const double mi = (2.0 * eps * s_st[w][i] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
+                            const double mj = (2.0 * eps * s_st[w][j] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
                             si = Dt - mi <= Ti;
                             sj = Dt - mj <= Tj;
                         }

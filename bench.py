@@ -128,10 +128,17 @@ def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted"):
                       f"({ev} evals in {dt:.1f} s)"}
 
 
-def traffic_record(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+def traffic_path(workload: str) -> str:
+    """Counter summary of a workload: profiles/traffic.json for the headline
+    workload, profiles/traffic_<workload>.json for the others."""
+    name = "traffic.json" if workload == WORKLOAD["workload"] else f"traffic_{workload}.json"
+    return os.path.join(ROOT, "profiles", name)
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs of the
+    workload, if they were taken on the current kernel source; else None."""
+    p = traffic_path(workload)
     if not os.path.exists(p):
         return None
     rec = json.load(open(p)).get(kernel)
@@ -223,8 +230,8 @@ def bench_batch(args, w):
     print(json.dumps(out), flush=True)
 
 
-def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
-    """Writes profiles/traffic.json: HBM bytes per launch of each knng kernel
+def summarize_pmc(fetch_csv, write_csv, copy_mib, command, workload):
+    """Writes the workload's counter summary (traffic_path): HBM bytes per launch of each knng kernel
     from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch), each scaled by what the counter reads for the plain copy of
     copy_mib MiB that bench.py --copy-probe-mib issues in the same run.
@@ -267,7 +274,7 @@ def summarize_pmc(fetch_csv, write_csv, copy_mib, command):
         out[k] = {"source_hash": kernel_source_hash(), "bytes_per_launch": int(fb + wb),
                   "fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
                   "launches": len(keep_f), "early_exits": len(fl) - len(keep_f)}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = traffic_path(workload)
     json.dump(out, open(path, "w"), indent=1, sort_keys=True)
     print(json.dumps({k: out[k] for k in out if not k.startswith("_")}, indent=1))
 
@@ -349,14 +356,16 @@ def main():
                     help="after the builds, copy this many MiB once (device to device) so that "
                          "HBM counters can be scaled by a kernel of known traffic")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarize two rocprofv3 counter runs into profiles/traffic.json and exit")
+                    help="summarize two rocprofv3 counter runs of --workload into its profiles/traffic*.json "
+                         "and exit")
     ap.add_argument("--pmc-command", default="", help="the command the counter runs used (recorded)")
     ap.add_argument("--sweep", choices=["d", "n", "lowd"], default=None,
                     help="the paper's dimension (n = 16384) or size (d = 256) sweep on a single Gaussian: "
                          "one JSON line per point and join path, no headline line")
     args = ap.parse_args()
     if args.pmc_summary:
-        summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe_mib or 1024, args.pmc_command)
+        summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.copy_probe_mib or 1024, args.pmc_command,
+                      args.workload)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
@@ -428,7 +437,7 @@ def main():
     jbytes = [m * (row_bytes + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
     achieved_bw = sum(jbytes) / (sum(join_ms) / 1e3) / 1e9
     achieved_fl = sum(flops) / (sum(join_ms) / 1e3) / 1e12
-    traffic = traffic_record(kernel)
+    traffic = traffic_record(kernel, w["workload"])
     # the contraction itself, priced at the peak of the instructions it runs on (context)
     peak_fl = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
     roof = {"bound": "hbm", "achieved": round(achieved_bw, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

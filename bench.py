@@ -30,7 +30,7 @@ WORKLOADS = {
     "image60k_d784": dict(workload="image60k_d784", N=60000, d=784, K=20, rho=1.0, delta=0.001, max_iters=30,
                           seed=1, gen=lambda: __import__("synth").image_like(60000, 1)),
     "gauss2k_d8": dict(workload="gauss2k_d8", N=2000, d=8, K=10, rho=1.0, delta=0.001, max_iters=20, seed=0,
-                       gen=lambda: __import__("synth").config(1)[0]),
+                       gen=lambda: __import__("synth").workload("gauss2k_d8")[0]),
     "blobs4m_d3": dict(workload="blobs4m_d3", N=4_000_000, d=3, K=15, rho=0.5, delta=0.001, max_iters=30, seed=2,
                        gen=lambda: __import__("synth").lowd_blobs(4_000_000, 2)),
     "batch512": dict(workload="batch512", N=None, d=None, K=15, rho=1.0, delta=0.001, max_iters=30, seed=4,
@@ -368,7 +368,7 @@ def main():
                       args.workload)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.sweep:
         run_sweep(args)

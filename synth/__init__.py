@@ -14,9 +14,9 @@ import math
 
 import numpy as np
 
-__all__ = ["config", "CONFIGS", "gaussian_mixture", "integer_points", "image_like",
+__all__ = ["workload", "WORKLOADS", "gaussian_mixture", "integer_points", "image_like",
            "lowd_blobs", "anisotropic_clusters", "batched_datasets", "clustered_labels",
-           "single_gaussian"]
+           "single_gaussian", "synthetic_gaussian", "audio_like"]
 
 
 def gaussian_mixture(N: int, d: int, n_centres: int, seed: int, lo: float = -10.0,
@@ -194,27 +194,28 @@ def batched_datasets(count: int = 512, seed: int = 4, n_lo: int = 500, n_hi: int
 
 
 # Method parameters per workload. max_iters for the large cases and the seeds
-# of configs 3 and 4 are readings (the workload text leaves them open).
-CONFIGS = {
-    1: dict(name="gauss2k_d8", K=10, rho=1.0, delta=0.001, max_iters=20, seed=0),
-    2: dict(name="image60k_d784", K=20, rho=1.0, delta=0.001, max_iters=30, seed=1),
-    3: dict(name="blobs4m_d3", K=15, rho=0.5, delta=0.001, max_iters=30, seed=2),
-    4: dict(name="aniso200k_d960", K=20, rho=0.5, delta=0.001, max_iters=30, seed=3),
-    5: dict(name="batch512", K=15, rho=1.0, delta=0.001, max_iters=30, seed=4),
+# of blobs4m_d3 and aniso200k_d960 are readings (the workload text leaves
+# them open).
+WORKLOADS = {
+    "gauss2k_d8": dict(name="gauss2k_d8", K=10, rho=1.0, delta=0.001, max_iters=20, seed=0),
+    "image60k_d784": dict(name="image60k_d784", K=20, rho=1.0, delta=0.001, max_iters=30, seed=1),
+    "blobs4m_d3": dict(name="blobs4m_d3", K=15, rho=0.5, delta=0.001, max_iters=30, seed=2),
+    "aniso200k_d960": dict(name="aniso200k_d960", K=20, rho=0.5, delta=0.001, max_iters=30, seed=3),
+    "batch512": dict(name="batch512", K=15, rho=1.0, delta=0.001, max_iters=30, seed=4),
 }
 
 
-def config(i: int, N: int | None = None):
-    """(X, params) for workload i (1..4). ``N`` shrinks the point count (tests)."""
-    p = dict(CONFIGS[i])
-    if i == 1:
+def workload(name: str, N: int | None = None):
+    """(X, params) of a named workload. ``N`` shrinks the point count (tests)."""
+    p = dict(WORKLOADS[name])
+    if name == "gauss2k_d8":
         X = gaussian_mixture(N or 2000, 8, 10, 0)
-    elif i == 2:
+    elif name == "image60k_d784":
         X = image_like(N or 60000, 1)
-    elif i == 3:
+    elif name == "blobs4m_d3":
         X = lowd_blobs(N or 4_000_000, 2)
-    elif i == 4:
+    elif name == "aniso200k_d960":
         X = anisotropic_clusters(N or 200_000, 960, 3)
     else:
-        raise ValueError("config 5 is a batch: use batched_datasets()")
+        raise ValueError(f"{name}: a batch of datasets, see batched_datasets()")
     return X, p

@@ -35,7 +35,7 @@ def knng():
 
 @pytest.fixture(scope="module")
 def image60k():
-    X, p = synth.config(2)
+    X, p = synth.workload("image60k_d784")
     ref = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     return X, p, ref
 
@@ -90,7 +90,7 @@ def _check_sampled(X, ids, dists, rows, K, dpad, gram, min_recall):
 
 
 def test_blobs4m_sampled_rows(knng):
-    X, p = synth.config(3)
+    X, p = synth.workload("blobs4m_d3")
     ids, dists, st = knng.build(_dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     assert st["path"] == 1 and st["converged"]
     rows = np.random.default_rng(0).choice(X.shape[0], 256, replace=False)
@@ -98,7 +98,7 @@ def test_blobs4m_sampled_rows(knng):
 
 
 def test_aniso200k_sampled_rows(knng):
-    X, p = synth.config(4)
+    X, p = synth.workload("aniso200k_d960")
     ids, dists, st = knng.build(_dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     assert st["path"] == knng.PATH_MFMA_BF16X3
     rows = np.random.default_rng(1).choice(X.shape[0], 128, replace=False)

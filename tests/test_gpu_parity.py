@@ -274,7 +274,7 @@ def test_integer_form_selection(knng):
 
 
 def test_init_matches_oracle(knng):
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     ctx = knng.Context(dev(X), 10, seed=0)
     ctx.init()
     g = ctx.export()
@@ -287,7 +287,7 @@ def test_init_matches_oracle(knng):
 @pytest.mark.parametrize("rho", [1.0, 0.5, 0.25])
 def test_sample_sets_match_oracle(knng, rho):
     """Sampled new/old sets are integer-exact, for every t of an oracle trajectory."""
-    X, p = synth.config(1, N=1500)
+    X, p = synth.workload("gauss2k_d8", N=1500)
     K = 10
     C = oracle.cap(K, rho)
     r = oracle.build_graph(X, K, rho, 0.0, 5, 7, keep_states=True)
@@ -306,7 +306,7 @@ def test_sample_sets_match_oracle(knng, rho):
 
 def test_step_parity_cfg1(knng):
     """Load the oracle's G_t, run one GPU iteration, compare with the oracle's G_{t+1}."""
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     K = p["K"]
     r = oracle.build_graph(X, K, p["rho"], p["delta"], p["max_iters"], p["seed"], keep_states=True)
     for s, nxt, e, c in zip(r.states[:-1], r.states[1:], r.evals, r.changes):
@@ -320,7 +320,7 @@ def test_step_parity_cfg1(knng):
 
 
 def test_build_cfg1_parity_and_recall(knng):
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     ref = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     ids, dists, st = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     ids = ids.cpu().numpy()
@@ -382,7 +382,7 @@ def test_iteration_cap(knng, T, path):
 
 
 def test_zero_iterations_returns_init(knng):
-    X, _ = synth.config(1, N=500)
+    X, _ = synth.workload("gauss2k_d8", N=500)
     ids, dists, st = knng.build(dev(X), 10, 1.0, 0.001, 0, 4)
     ref = oracle.init(X, 10, 4)
     assert st["iters"] == 0
@@ -421,7 +421,7 @@ def test_load_rejects_bad_rows(knng):
 
 
 def test_deterministic_repeat(knng):
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     a = knng.build(dev(X), 10, 1.0, 0.001, 20, 0)
     b = knng.build(dev(X), 10, 1.0, 0.001, 20, 0)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
@@ -445,7 +445,7 @@ def test_permutation_is_result_invisible_integer(knng, path):
 
 
 def test_permutation_is_result_invisible_cfg1(knng):
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     a = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=False)
     b = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=True)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])

@@ -31,7 +31,7 @@ def dev(X):
 @pytest.mark.parametrize("rho", [1.0, 0.5, 0.25])
 def test_turbo_sample_sets_match_oracle(knng, rho):
     """Sampled new/old sets are integer-exact for every t of an oracle trajectory."""
-    X, _ = synth.config(1, N=1500)
+    X, _ = synth.workload("gauss2k_d8", N=1500)
     K = 10
     C = oracle.cap(K, rho)
     r = oracle.build_graph(X, K, rho, 0.0, 5, 7, keep_states=True, sampling="turbo")
@@ -147,7 +147,7 @@ def test_turbo_rejects_large_cap(knng):
 def test_image60k_turbo_bitwise(knng):
     """The benchmark workload (60000 x 784 pixel integers, K = 20, rho = 1)
     with turbosampling: the whole graph, e_t and c_t equal the oracle's."""
-    X, p = synth.config(2)
+    X, p = synth.workload("image60k_d784")
     ref = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], sampling="turbo")
     ids, dists, st = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"],
                                 sampling="turbo")

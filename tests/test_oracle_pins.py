@@ -129,7 +129,7 @@ def _rev(st):
 
 def test_sample_bounds_and_membership(oracle_lib):
     """Sec. 3.1: N(u) draws from forward and reverse neighbours, bounded by rho*k per flag."""
-    X, p = synth.config(1, N=600)
+    X, p = synth.workload("gauss2k_d8", N=600)
     K, C = 10, oracle.cap(10, 0.5)
     r = oracle.build_graph(X, K, 0.5, 0.0, 2, 3)
     st = oracle.State(r.ids, r.dists, r.flags, 2)
@@ -191,7 +191,7 @@ def test_sample_selection_is_uniform(oracle_lib):
 
 def test_evals_count_closed_form(oracle_lib):
     """e_t = sum_u [n_new(n_new-1)/2 + n_new*n_old] (new x new and new x old pairs)."""
-    X, _ = synth.config(1, N=500)
+    X, _ = synth.workload("gauss2k_d8", N=500)
     K, C = 10, 7
     st = oracle.init(X, K, 8)
     sm = oracle.sample(st, K, C, 8, 1)
@@ -312,7 +312,7 @@ def test_turbo_new_sample_is_within_heap_sample(oracle_lib):
     """The coin only removes entries from the heap rule's ordering, so per owner
     the turbo new sample is a prefix of the heap rule's new sample, and at t = 1
     (every flag NEW) e_1 cannot exceed the heap rule's."""
-    X, _ = synth.config(1, N=800)
+    X, _ = synth.workload("gauss2k_d8", N=800)
     K, C = 10, oracle.cap(10, 1.0)
     st = oracle.init(X, K, 9)
     a = oracle.sample(st, K, C, 9, 1, sampling="turbo")
@@ -326,7 +326,7 @@ def test_turbo_new_sample_is_within_heap_sample(oracle_lib):
 
 def test_turbo_build_converges(oracle_lib):
     """A turbosampled build still finds most exact neighbours (recall vs brute force)."""
-    X, _ = synth.config(1, N=1500)
+    X, _ = synth.workload("gauss2k_d8", N=1500)
     K = 10
     r = oracle.build_graph_c(X, K, 1.0, 0.001, 30, 4, sampling="turbo")
     ids, _ = oracle.bruteforce(X, K)
@@ -343,7 +343,7 @@ def _window_purity(labels, w, stride):
 
 
 def test_greedy_order_is_a_permutation_with_its_inverse(oracle_lib):
-    X, _ = synth.config(1, N=1500)
+    X, _ = synth.workload("gauss2k_d8", N=1500)
     r = oracle.build_graph(X, 10, 1.0, 0.0, 1, 2)
     sig, inv = oracle.greedy_order(r.ids)
     assert sorted(sig.tolist()) == list(range(1500))
@@ -356,7 +356,7 @@ def test_greedy_order_places_the_nearest_unplaced_neighbour_next(oracle_lib):
     order the node at spot i + 1 is the first entry of the (nearest-first) list
     of the node at spot i that does not sit at a spot <= i, whenever there is
     one; otherwise the step leaves spot i + 1 alone."""
-    X, _ = synth.config(1, N=1200)
+    X, _ = synth.workload("gauss2k_d8", N=1200)
     r = oracle.build_graph(X, 8, 1.0, 0.0, 2, 4)
     sig, inv = oracle.greedy_order(r.ids)
     constrained = 0
@@ -387,7 +387,7 @@ def test_greedy_order_recovers_clusters_first(oracle_lib):
 
 def test_exact_knn_is_a_fixed_point(oracle_lib):
     """Feeding the exact K-NNG (all NEW) changes nothing: no proposal can beat it."""
-    X, _ = synth.config(1, N=400)
+    X, _ = synth.workload("gauss2k_d8", N=400)
     K = 10
     ids, dists = oracle.bruteforce(X, K)
     st = oracle.State(ids, dists, np.ones_like(ids, dtype=np.uint8), 0)
@@ -399,7 +399,7 @@ def test_exact_knn_is_a_fixed_point(oracle_lib):
 def test_iteration_invariants_and_monotone_keys(oracle_lib):
     """Rows: K distinct non-self ids sorted by (dist, id), stored D = recomputed D;
     the i-th key of every row never increases, so sum of list distances never increases."""
-    X, p = synth.config(1, N=800)
+    X, p = synth.workload("gauss2k_d8", N=800)
     K, C = 10, 10
     st = oracle.init(X, K, 2)
     prev_sum = st.dists.sum()
@@ -422,7 +422,7 @@ def test_iteration_invariants_and_monotone_keys(oracle_lib):
 def test_build_reaches_exact_knn_on_small_inputs(oracle_lib):
     """Sec. 2: NN-Descent approximates the exact K-NNG; the paper reports recall
     above 99% (Sec. 2). On small clustered inputs the oracle must get there."""
-    X, p = synth.config(1)
+    X, p = synth.workload("gauss2k_d8")
     r = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     ei, ed = oracle.bruteforce(X, p["K"])
     assert oracle.recall(X, r.ids, ed) >= 0.99
@@ -444,7 +444,7 @@ def test_identical_points_pure_id_tiebreak(oracle_lib):
 
 def test_stop_rule(oracle_lib):
     """Sec. 2: iterate until the number of changes falls below the threshold."""
-    X, p = synth.config(1, N=1000)
+    X, p = synth.workload("gauss2k_d8", N=1000)
     r = oracle.build_graph(X, 10, 1.0, 0.01, 50, 0)
     thr = 0.01 * 1000 * 10
     assert r.changes[-1] < thr and (r.changes[:-1] >= thr).all()
@@ -453,7 +453,7 @@ def test_stop_rule(oracle_lib):
 
 
 def test_c_build_equals_stepwise_build(oracle_lib):
-    X, p = synth.config(1, N=700)
+    X, p = synth.workload("gauss2k_d8", N=700)
     a = oracle.build_graph(X, 10, 0.7, 0.001, 12, 9)
     b = oracle.build_graph_c(X, 10, 0.7, 0.001, 12, 9)
     assert a.iters == b.iters
@@ -464,7 +464,7 @@ def test_c_build_equals_stepwise_build(oracle_lib):
 def test_thread_count_independence(oracle_lib):
     """Results must not depend on the OpenMP thread count."""
     code = ("import numpy as np, oracle, synth, sys\n"
-            "X,p=synth.config(1, N=900)\n"
+            "X,p=synth.workload('gauss2k_d8', N=900)\n"
             "r=oracle.build_graph_c(X,10,0.8,0.001,10,4)\n"
             "sys.stdout.write(str(hash(r.ids.tobytes()+r.dists.tobytes()+r.evals.tobytes())))\n")
     outs = []

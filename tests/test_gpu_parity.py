@@ -304,7 +304,7 @@ def test_sample_sets_match_oracle(knng, rho):
         ctx.close()
 
 
-def test_step_parity_cfg1(knng):
+def test_step_parity_gauss2k(knng):
     """Load the oracle's G_t, run one GPU iteration, compare with the oracle's G_{t+1}."""
     X, p = synth.workload("gauss2k_d8")
     K = p["K"]
@@ -319,7 +319,7 @@ def test_step_parity_cfg1(knng):
         ctx.close()
 
 
-def test_build_cfg1_parity_and_recall(knng):
+def test_build_gauss2k_parity_and_recall(knng):
     X, p = synth.workload("gauss2k_d8")
     ref = oracle.build_graph(X, p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
     ids, dists, st = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"])
@@ -444,7 +444,7 @@ def test_permutation_is_result_invisible_integer(knng, path):
     assert st["iters"] == a[2]["iters"]
 
 
-def test_permutation_is_result_invisible_cfg1(knng):
+def test_permutation_is_result_invisible_gauss2k(knng):
     X, p = synth.workload("gauss2k_d8")
     a = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=False)
     b = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], reorder=True)

@@ -63,19 +63,32 @@ def kernel_source_hash() -> str:
 
 
 def exact_kth(X, K, rows):
-    """Exact K-th neighbour distance (FP64, self excluded) of the query rows,
-    on the GPU with torch (evaluation only, not the method's path)."""
+    """Exact K-th neighbour distance (FP64, self excluded) and the exact
+    neighbour ids of the query rows, on the GPU with torch (evaluation only,
+    not the method's path)."""
     import torch
     Xd = X.double()
     n = (Xd * Xd).sum(1)
     out = torch.empty(len(rows), dtype=torch.float64, device=X.device)
+    ids = torch.empty((len(rows), K), dtype=torch.int64, device=X.device)
     step = max(1, min(4096, (1 << 28) // X.shape[0]))
     for s in range(0, len(rows), step):
         r = rows[s:s + step]
         D = n[r, None] + n[None, :] - 2.0 * (Xd[r] @ Xd.T)
         D[torch.arange(len(r), device=X.device), r] = float("inf")
-        out[s:s + step] = torch.topk(D, K, dim=1, largest=False).values[:, -1]
-    return out
+        tk = torch.topk(D, K, dim=1, largest=False)
+        out[s:s + step] = tk.values[:, -1]
+        ids[s:s + step] = tk.indices
+    return out, ids
+
+
+def plain_recall(ids, exact_ids, rows):
+    """Plain intersection recall |found ∩ exact| / K over the query rows (ties
+    at the K-th distance count against it)."""
+    import torch
+    found = ids[rows].long()
+    hit = (found[:, :, None] == exact_ids[:, None, :]).any(-1)
+    return float(hit.float().mean())
 
 
 def dist_error(X, ids, dists, rows):
@@ -107,12 +120,14 @@ def recall_of(X, ids, tau, rows, rel=1e-5):
     return good / (len(rows) * ids.shape[1])
 
 
-def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted"):
+def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted", threads=0):
     """FP64 oracle on the host: init + iterations 1, 2, ... of the same workload
     (same sampling rule) until ~budget_s of CPU work; evals/s over the
     iterations run."""
     import oracle
     oracle.build(force=False)
+    if threads:
+        oracle.set_num_threads(threads)
     C = oracle.cap(w["K"], w["rho"])
     t0 = time.perf_counter()
     st = oracle.init(Xnp, w["K"], w["seed"])
@@ -210,7 +225,7 @@ def bench_batch(args, w):
         tot, good = 0, 0.0
         for X, ids in zip(Xs, b.ids):
             rows = torch.arange(X.shape[0], device=dev)
-            tau = exact_kth(X, w["K"], rows)
+            tau, _ = exact_kth(X, w["K"], rows)
             good += recall_of(X, ids, tau, rows) * X.shape[0]
             tot += X.shape[0]
         rec = good / tot
@@ -351,6 +366,8 @@ def main():
     ap.add_argument("--recall-rows", type=int, default=100000,
                     help="query rows for recall (all rows when N is smaller; a seeded sample otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU oracle baseline (0: all host cores)")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the builds, copy this many MiB once (device to device) so that "
@@ -453,6 +470,7 @@ def main():
     t99 = None
     rcurve = None
     derr = None
+    rec_plain = None
     if not args.no_recall:
         N = w["N"]
         if N <= args.recall_rows:
@@ -460,8 +478,9 @@ def main():
         else:
             rows = torch.from_numpy(np.sort(np.random.default_rng(12345).choice(N, args.recall_rows,
                                                                                 replace=False))).to(dev)
-        tau = exact_kth(X, w["K"], rows)
+        tau, exact_ids = exact_kth(X, w["K"], rows)
         curve = [recall_of(X, ids_t, tau, rows) for ids_t in curve_ids]
+        rec_plain = plain_recall(ids, exact_ids, rows)
         rec = curve[-1]
         derr = dist_error(X, ids, dists, rows)
         cum = s0["init_ms"] + s0["reorder_ms"]
@@ -483,7 +502,7 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) / 1e3) / 1e9
     del src, dst
-    cpu = None if args.no_cpu else cpu_baseline(Xnp, w, sampling=args.sampling)
+    cpu = None if args.no_cpu else cpu_baseline(Xnp, w, sampling=args.sampling, threads=args.cpu_threads)
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
 
@@ -496,7 +515,8 @@ def main():
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
                    "reorder": bool(args.reorder), "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
                    "precision": args.precision, "sampling": args.sampling},
-        "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "ms_to_recall_0.99": t99,
+        "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "recall_plain": rec_plain,
+        "ms_to_recall_0.99": t99,
         "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
         "recall_curve": rcurve,   # [device ms since the build began, recall of G_t] per iteration
         # stored FP32 distances of the recall rows vs FP64: max absolute and max relative error

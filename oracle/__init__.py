@@ -70,6 +70,8 @@ def _load():
     lib.orc_list_dists.argtypes = [P, i64, i32, i32, P, P]
     lib.orc_greedy_order.argtypes = [P, i64, i32, P, P]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
     for name in ("orc_init", "orc_sample", "orc_join_merge", "orc_iterate", "orc_build",
                  "orc_bruteforce", "orc_bruteforce_rows", "orc_list_dists", "orc_greedy_order"):
         getattr(lib, name).restype = ctypes.c_int
@@ -107,6 +109,11 @@ def cap(K: int, rho: float) -> int:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (the results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 @dataclass

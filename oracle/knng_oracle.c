@@ -561,3 +561,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of later calls (results do not depend on it; timing only). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -122,13 +122,43 @@ __device__ __forceinline__ void cmpx(uint64_t& k, uint32_t& v, int j, bool asc) 
     v = sw ? ov : v;
 }
 
-// Ascending bitonic sort of 64 (key, value) pairs, one per lane.
-__device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& v) {
+// Ascending bitonic sort of distinct 32-bit keys within segments of W lanes
+// (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
+template <int W>
+__device__ __forceinline__ void seg_sort32(uint32_t& k) {
     const int lane = lane_id();
 #pragma unroll
-    for (int size = 2; size <= 64; size <<= 1) {
+    for (int size = 2; size <= W; size <<= 1) {
 #pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) cmpx(k, v, j, (lane & size) == 0);
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint32_t o = xor_lanes(k, j);
+            const bool keep_min = (size == W || (lane & size) == 0) == ((lane & j) == 0);
+            k = keep_min ? min(k, o) : max(k, o);
+        }
+    }
+}
+
+// Odd-even transposition passes within W-lane segments on (key, value)
+// pairs until a pass swaps nothing (the wave leaves together): finishes the
+// order of a sequence that is already sorted up to short runs.
+template <int W>
+__device__ __forceinline__ void seg_fixup(uint64_t& key, uint32_t& val) {
+    const int lane = lane_id(), sl = lane & (W - 1);
+    for (int pass = 0; pass < W; ++pass) {
+        bool any = false;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            const bool lower = (sl & 1) == ph;    // phase 0: pairs (2i, 2i+1); phase 1: (2i+1, 2i+2)
+            const bool has = lower ? sl + 1 < W : sl >= 1;
+            const int partner = has ? (lower ? lane + 1 : lane - 1) : lane;
+            const uint64_t ok = shfl64(key, partner);
+            const uint32_t ov = (uint32_t)__shfl((int)val, partner);
+            const bool sw = has && (lower ? ok < key : key < ok);
+            key = sw ? ok : key;
+            val = sw ? ov : val;
+            any |= sw;
+        }
+        if (ballot(any) == 0ull) break;
     }
 }
 
@@ -1172,7 +1202,18 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
         uint64_t key = s_key[lane];
         uint32_t idx = (uint32_t)lane < n ? s_idx[lane] : 0xffffffffu;
         wave_sync();
-        wave_sort(key, idx);
+        {   // sort a distinct 32-bit proxy, fetch the full keys, finish equal-weight runs
+            uint32_t x = (uint32_t)lane < n ? (((uint32_t)(key >> 32) & ~127u) | ((uint32_t)(key & 1ull) << 6) |
+                                                (uint32_t)lane)
+                                             : 0xffffffffu;
+            seg_sort32<64>(x);
+            const int src = (int)(x & 63u);
+            const uint64_t fk = shfl64(key, src);
+            const uint32_t fi = (uint32_t)__shfl((int)idx, src);
+            key = (uint32_t)lane < n ? fk : ~0ull;
+            idx = (uint32_t)lane < n ? fi : 0xffffffffu;
+            seg_fixup<64>(key, idx);
+        }
         const uint64_t p1 = shfl_up64(key, 1);
         const bool real = key != ~0ull;
         const bool dup = real && lane >= 1 && p1 == key;
@@ -1235,58 +1276,6 @@ __device__ void select_large_thr_owner(const Views& v, uint64_t st, int u, uint3
         v.cap[u] = owner_pairs(nnew, nold);
     }
     wave_sync();
-}
-
-// Ascending bitonic sort of distinct 32-bit keys within segments of W lanes
-// (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
-template <int W>
-__device__ __forceinline__ void seg_sort32(uint32_t& k) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int size = 2; size <= W; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            const uint32_t o = xor_lanes(k, j);
-            const bool keep_min = (size == W || (lane & size) == 0) == ((lane & j) == 0);
-            k = keep_min ? min(k, o) : max(k, o);
-        }
-    }
-}
-
-// Odd-even transposition passes within W-lane segments on (key, value)
-// pairs until a pass swaps nothing (the wave leaves together): finishes the
-// order of a sequence that is already sorted up to short runs.
-template <int W>
-__device__ __forceinline__ void seg_fixup(uint64_t& key, uint32_t& val) {
-    const int lane = lane_id(), sl = lane & (W - 1);
-    for (int pass = 0; pass < W; ++pass) {
-        bool any = false;
-#pragma unroll
-        for (int ph = 0; ph < 2; ++ph) {
-            const bool lower = (sl & 1) == ph;    // phase 0: pairs (2i, 2i+1); phase 1: (2i+1, 2i+2)
-            const bool has = lower ? sl + 1 < W : sl >= 1;
-            const int partner = has ? (lower ? lane + 1 : lane - 1) : lane;
-            const uint64_t ok = shfl64(key, partner);
-            const uint32_t ov = (uint32_t)__shfl((int)val, partner);
-            const bool sw = has && (lower ? ok < key : key < ok);
-            key = sw ? ok : key;
-            val = sw ? ov : val;
-            any |= sw;
-        }
-        if (ballot(any) == 0ull) break;
-    }
-}
-
-// Ascending bitonic sort of (key, value) pairs within segments of W lanes
-// (W = 64: the whole wave; W = 32: lanes 0-31 and 32-63 separately).
-template <int W>
-__device__ __forceinline__ void seg_sort(uint64_t& k, uint32_t& v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int size = 2; size <= W; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) cmpx(k, v, j, size == W || (lane & size) == 0);
-    }
 }
 
 // Pool of one owner per W-lane segment (u, P: the segment's owner and pool
@@ -2380,17 +2369,25 @@ constexpr int kHubBlocks = 512;
 // Ascending bitonic sort of 64 keys, one per lane.
 __device__ __forceinline__ void wave_sort_keys(uint64_t& k) {
     const int lane = lane_id();
+    // a distinct 32-bit proxy: the top 26 bits of the distance (non-negative
+    // FP32 bits order as the values) above the lane; sorted, the full keys
+    // are fetched back and runs of equal proxy distances finished on the
+    // full key
+    uint32_t x = (((uint32_t)(k >> 32) >> 5) << 6) | (uint32_t)lane;
+    seg_sort32<64>(x);
+    k = shfl64(k, (int)(x & 63u));
+    for (int pass = 0; pass < 64; ++pass) {
+        bool any = false;
 #pragma unroll
-    for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-        for (int j = size >> 1; j > 0; j >>= 1) {
-            // selects, not branches: the smaller key to the lower lane of an
-            // ascending block, the larger to its upper lane
-            const uint64_t o = shfl_xor64(k, j);
-            const bool lt = o < k;
-            const uint64_t mn = lt ? o : k, mx = lt ? k : o;
-            k = (((lane & j) == 0) == ((lane & size) == 0)) ? mn : mx;
+        for (int ph = 0; ph < 2; ++ph) {
+            const bool lower = (lane & 1) == ph;   // phase 0: pairs (2i, 2i+1); phase 1: (2i+1, 2i+2)
+            const bool has = lower ? lane < 63 : lane >= 1;
+            const uint64_t o = shfl64(k, has ? (lower ? lane + 1 : lane - 1) : lane);
+            const bool sw = has && (lower ? o < k : k < o);
+            k = sw ? o : k;
+            any |= sw;
         }
+        if (ballot(any) == 0ull) break;
     }
 }
 

@@ -115,7 +115,7 @@ typedef enum {
  *   keeps per node); the coin is the same weight, passing iff
  *   w * n_f(u) < C * 2^32. At most C survivors per flag are kept (those of
  *   smallest (w, id)), so each flag keeps about C members in expectation and
- *   never more than C. Needs ceil(rho*K) <= 30.
+ *   never more than C.
  * In both, an old member also sampled as new is dropped from the old sample,
  * and forward NEW entries of sampled new members become OLD.
  */

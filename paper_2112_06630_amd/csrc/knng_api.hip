@@ -88,8 +88,6 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_BF16X3) return fail(KNNG_EINVAL, "unknown path");
     if (p->sampling != KNNG_SAMPLING_WEIGHTED && p->sampling != KNNG_SAMPLING_TURBO)
         return fail(KNNG_EINVAL, "unknown sampling rule");
-    if (p->sampling == KNNG_SAMPLING_TURBO && 2 * sample_cap(p->K, p->rho) > 60)
-        return fail(KNNG_EINVAL, "turbosampling needs ceil(rho*K) <= 30");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
     return KNNG_OK;
 }

@@ -38,6 +38,12 @@ __device__ __forceinline__ uint32_t pair_weight(uint64_t st, uint32_t a, uint32_
     return (uint32_t)(mix64(st ^ (((uint64_t)lo << 32) | hi)) >> 32);
 }
 
+// Turbosampling coin (Sec. 3.1): an entry of weight wt among n entries of its
+// flag passes with probability C/n, i.e. iff wt * n < C * 2^32 (exact).
+__device__ __forceinline__ bool turbo_coin(uint32_t wt, uint32_t n, uint32_t C) {
+    return (uint64_t)wt * n < ((uint64_t)C << 32);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
@@ -979,14 +985,32 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
             L.dup[w][i] = dup ? 1 : 0;
         }
         wave_sync();
+        // ---- turbosampling: pool entries per flag, with multiplicity ----
+        uint32_t tot[2] = {0u, 0u};
+        if (v.turbo) {
+            for (int i0 = 0; i0 < P; i0 += 64) {
+                const int i = i0 + lane;
+                uint32_t pf = 0;
+                if (i < P) pf = i < K ? v.lpos[(size_t)u * K + i] : v.rev[rb + (uint32_t)(i - K)].z;
+                tot[0] += (uint32_t)__popcll(ballot(i < P && (pf & kNewBit)));
+                tot[1] += (uint32_t)__popcll(ballot(i < P && !(pf & kNewBit)));
+            }
+        }
+        // an entry's coin (staged key: old << 63 | w << 31 | id); the entries
+        // that pass are a prefix of their flag's ranks
+        auto coin = [&](uint64_t k) {
+            return !v.turbo || turbo_coin((uint32_t)(k >> 31), tot[k >> 63], (uint32_t)C);
+        };
         // ---- ranks among distinct keys; twin = NEW entry of the same member ----
-        uint32_t nvnew = 0, nvold = 0;
+        uint32_t nvnew = 0, ncnew = 0, ncold = 0;
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
             const bool valid = i < n && !L.dup[w][i];
             const uint64_t ki = i < n ? skey[i] : ~0ull;
+            const bool c = valid && coin(ki);
             nvnew += __popcll(ballot(valid && !(ki >> 63)));
-            nvold += __popcll(ballot(valid && (ki >> 63)));
+            ncnew += __popcll(ballot(c && !(ki >> 63)));
+            ncold += __popcll(ballot(c && (ki >> 63)));
         }
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
@@ -1009,19 +1033,19 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
         }
         if (lane == 0) L.oldmask[w] = 0ull;
         wave_sync();
-        const uint32_t nnew = min((uint32_t)C, nvnew);
+        const uint32_t nnew = min((uint32_t)C, ncnew);
         // ---- old entries whose member is sampled as new are removed ----
         for (int i = lane; i < n; i += 64) {
             if (L.dup[w][i] || !(skey[i] >> 63)) continue;
             const uint32_t ro = L.rank[w][i] - nvnew;
-            if (ro >= (uint32_t)C) continue;
+            if (ro >= (uint32_t)C || !coin(skey[i])) continue;
             const int tw = L.twin[w][i];
-            if (tw >= 0 && L.rank[w][tw] < (uint32_t)C)
+            if (tw >= 0 && L.rank[w][tw] < (uint32_t)C && coin(skey[tw]))
                 atomicOr((unsigned long long*)&L.oldmask[w], 1ull << ro);
         }
         wave_sync();
         const uint64_t omask = L.oldmask[w];
-        const uint32_t nold = min((uint32_t)C, nvold) - (uint32_t)__popcll(omask);
+        const uint32_t nold = min((uint32_t)C, ncold) - (uint32_t)__popcll(omask);
         // ---- outputs: sampled sets, flips, per-target proposal capacities ----
         uint2* cs = v.cand + (size_t)u * 2 * C;
         for (int i = lane; i < n; i += 64) {
@@ -1032,13 +1056,13 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
             const uint32_t id = (uint32_t)(ki & 0x7fffffffu);
             const uint32_t rank = L.rank[w][i];
             if (!(ki >> 63)) {
-                if (rank < (uint32_t)C) {
+                if (rank < (uint32_t)C && coin(ki)) {
                     cs[rank] = make_uint2(id, pos);
                     if (i < nf) v.lpos[(size_t)u * K + L.src[w][i]] = pos;  // flip NEW -> OLD
                 }
             } else {
                 const uint32_t ro = rank - nvnew;
-                if (ro < (uint32_t)C && !((omask >> ro) & 1ull)) {
+                if (ro < (uint32_t)C && coin(ki) && !((omask >> ro) & 1ull)) {
                     const uint32_t slot = nnew + ro - (uint32_t)__popcll(omask & ((1ull << ro) - 1ull));
                     cs[slot] = make_uint2(id, pos);
                 }
@@ -1058,12 +1082,6 @@ __global__ __launch_bounds__(256) void k_select_large(Views v, uint64_t st0, int
 // each and sorted like a small pool. Each search step is one ballot-count
 // pass over the pool. OLD entries whose member was sampled NEW are removed
 // by comparing with the (at most C) sampled new ids.
-// Turbosampling coin (Sec. 3.1): an entry of weight wt among n entries of its
-// flag passes with probability C/n, i.e. iff wt * n < C * 2^32 (exact).
-__device__ __forceinline__ bool turbo_coin(uint32_t wt, uint32_t n, uint32_t C) {
-    return (uint64_t)wt * n < ((uint64_t)C << 32);
-}
-
 __device__ __forceinline__ uint64_t sel_key(uint32_t wt, uint32_t id, uint32_t pf) {
     return ((uint64_t)wt << 32) | ((uint64_t)id << 1) | ((pf & kNewBit) ? 0u : 1u);
 }

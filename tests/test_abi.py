@@ -63,8 +63,6 @@ def _params(**kw):
     (100, 784, dict(K=64, rho=1.0, path="bf16x3"), "MFMA"),
     (100, 784, dict(path="mfma_i8"), "disabled"),
     (100, 8, dict(sampling=2), "unknown sampling"),
-    (100, 8, dict(K=40, rho=1.0, path="valu", sampling="turbo"), "turbosampling"),
-    (100, 8, dict(K=64, rho=0.5, path="valu", sampling="turbo"), "turbosampling"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
     import paper_2112_06630_amd as knng

@@ -75,7 +75,9 @@ def hub_state(X, K, seed, hubs, t):
 HUBS = [(0, 0.75), (1, 0.3), (2, 0.04)]
 
 
-@pytest.mark.parametrize("K,rho", [(10, 1.0), (16, 1.0), (20, 0.5), (30, 1.0)])
+# C <= 30: the threshold select for pools beyond 64 entries; C > 30 (K = 40,
+# and K = 64 at rho = 0.5): the rank-based select of k_select_large
+@pytest.mark.parametrize("K,rho", [(10, 1.0), (16, 1.0), (20, 0.5), (30, 1.0), (40, 1.0), (64, 0.5)])
 @pytest.mark.parametrize("sampling", ["weighted", "turbo"])
 def test_hub_pools_one_iteration(knng, K, rho, sampling):
     N = 900
@@ -138,10 +140,17 @@ def test_turbo_batch_equals_single_builds(knng):
         assert torch.equal(b.dists[i], dists), i
 
 
-def test_turbo_rejects_large_cap(knng):
-    X = dev(synth.integer_points(200, 8, 9, 1))
-    with pytest.raises(knng.KnngError, match="turbosampling"):
-        knng.build(X, 40, 1.0, 0.001, 5, 1, path="valu", sampling="turbo")
+@pytest.mark.parametrize("K,rho,path", [(40, 1.0, "valu"), (64, 0.5, "mfma"), (48, 1.0, "valu")])
+def test_turbo_large_caps_bitwise(knng, K, rho, path):
+    """Caps above 30 (the rank-based large-pool select) on integer data."""
+    X = synth.integer_points(1200, 16 if path == "valu" else 64, 9, 6)
+    ref = oracle.build_graph(X, K, rho, 0.001, 12, 6, sampling="turbo")
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 12, 6, path=path, sampling="turbo")
+    assert st["iters"] == ref.iters
+    assert st["evals"] == ref.evals.tolist()
+    assert st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)
 
 
 def test_image60k_turbo_bitwise(knng):

@@ -1879,9 +1879,10 @@ void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
 // (||x~|| + ||y~||)^2, the test applied (in FP64, with the bound enlarged by
 // 2^-20 relative).
 //
-// Rescore. One wave per pair: lane l sums (x_j - y_j)^2 over j = l, l+64, ...
-// in order, lane partials are added by a fixed tree and lane 0's value is
-// broadcast: one deterministic FP32 formula, symmetric in (x, y).
+// Rescore. One lane per surviving pair: four partial sums of (x_j - y_j)^2
+// over the 16-byte groups of the rows, added as (s0 + s1) + (s2 + s3) (the
+// direct form's FP32 formula and error bound): deterministic and symmetric in
+// (x, y).
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -1925,17 +1926,23 @@ void launch_make_bf16(const Views& v, hipStream_t s) {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// FP32 squared distance of two rows, one wave: strided lane partial sums,
-// fixed reduction tree, lane 0's value broadcast.
-__device__ __forceinline__ float dist_wave(const float* __restrict__ a, const float* __restrict__ b, int dp) {
-    const int lane = lane_id();
-    float s = 0.f;
-    for (int j = lane; j < dp; j += 64) {
-        const float t = a[j] - b[j];
-        s = fmaf(t, t, s);
+// FP32 squared distance of two rows by one lane: four partial sums over the
+// components of 16-byte groups (j = 4c + r goes to sum r), added as
+// (s0 + s1) + (s2 + s3). Symmetric in (a, b); dp % 4 == 0, rows 16-byte aligned.
+__device__ __forceinline__ float dist_lane(const float* __restrict__ a, const float* __restrict__ b, int dp) {
+    const float4* pa = reinterpret_cast<const float4*>(a);
+    const float4* pb = reinterpret_cast<const float4*>(b);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll 4
+    for (int c = 0; c < (dp >> 2); ++c) {
+        const float4 x = pa[c], y = pb[c];
+        const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
+        s0 = fmaf(t0, t0, s0);
+        s1 = fmaf(t1, t1, s1);
+        s2 = fmaf(t2, t2, s2);
+        s3 = fmaf(t3, t3, s3);
     }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
-    return __uint_as_float(rl32(__float_as_uint(s), 0));
+    return (s0 + s1) + (s2 + s3);
 }
 
 constexpr int kBfMaxSurv = 3 * 32 * 32 / 2;   // survivor pairs per owner <= e(u) <= C(C-1)/2 + C^2 < 1.5 C^2, C <= 32
@@ -2048,12 +2055,15 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
             nsv = kBfMaxSurv;
         }
         wave_sync();
-        // rescore in FP32 from the original rows
-        for (uint32_t q = 0; q < nsv; ++q) {
-            const uint32_t e = s_surv[w][q];
-            const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
-            const float D = dist_wave(v.Xp + (size_t)s_pos[w][a] * dp, v.Xp + (size_t)s_pos[w][b] * dp, dp);
-            if (lane == 0) s_sd[w][q] = D;
+        // rescore in FP32 from the original rows, one survivor per lane (the
+        // owner's member rows are re-read from the caches by its lanes)
+        for (uint32_t q0 = 0; q0 < nsv; q0 += 64) {
+            const uint32_t q = q0 + (uint32_t)lane;
+            if (q < nsv) {
+                const uint32_t e = s_surv[w][q];
+                const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
+                s_sd[w][q] = dist_lane(v.Xp + (size_t)s_pos[w][a] * dp, v.Xp + (size_t)s_pos[w][b] * dp, dp);
+            }
         }
         rescored += nsv;
         wave_sync();

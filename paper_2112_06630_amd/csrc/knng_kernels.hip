@@ -1879,10 +1879,10 @@ void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
 // (||x~|| + ||y~||)^2, the test applied (in FP64, with the bound enlarged by
 // 2^-20 relative).
 //
-// Rescore. One lane per surviving pair: four partial sums of (x_j - y_j)^2
-// over the 16-byte groups of the rows, added as (s0 + s1) + (s2 + s3) (the
-// direct form's FP32 formula and error bound): deterministic and symmetric in
-// (x, y).
+// Rescore. Sixteen lanes per surviving pair, each with four partial sums of
+// (x_j - y_j)^2 over its 16-byte groups, added by a fixed tree: an FP32
+// direct-form evaluation (64 partial sums of d/64 terms each, within the
+// direct form's error bound), deterministic and symmetric in (x, y).
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -1926,23 +1926,34 @@ void launch_make_bf16(const Views& v, hipStream_t s) {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// FP32 squared distance of two rows by one lane: four partial sums over the
-// components of 16-byte groups (j = 4c + r goes to sum r), added as
-// (s0 + s1) + (s2 + s3). Symmetric in (a, b); dp % 4 == 0, rows 16-byte aligned.
-__device__ __forceinline__ float dist_lane(const float* __restrict__ a, const float* __restrict__ b, int dp) {
+// FP32 squared distance of two rows by a group of 16 lanes (lanes 16g..16g+15):
+// lane k of the group sums the components of the 16-byte groups c = k, k+16,
+// ... into four partial sums (one per component), adds them as
+// (s0 + s1) + (s2 + s3), and the 16 lane values are added by a fixed
+// butterfly (distances 1, 2, 4, 8). Deterministic and symmetric in (a, b);
+// dp % 4 == 0, rows 16-byte aligned. Every lane of the wave takes part in the
+// butterfly; a group with act == false sums nothing.
+__device__ __forceinline__ float dist_group16(const float* __restrict__ a, const float* __restrict__ b, int dp,
+                                              bool act) {
+    const int k = lane_id() & 15;
     const float4* pa = reinterpret_cast<const float4*>(a);
     const float4* pb = reinterpret_cast<const float4*>(b);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-#pragma unroll 4
-    for (int c = 0; c < (dp >> 2); ++c) {
-        const float4 x = pa[c], y = pb[c];
-        const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
-        s0 = fmaf(t0, t0, s0);
-        s1 = fmaf(t1, t1, s1);
-        s2 = fmaf(t2, t2, s2);
-        s3 = fmaf(t3, t3, s3);
+    if (act) {
+#pragma unroll 2
+        for (int c = k; c < (dp >> 2); c += 16) {
+            const float4 x = pa[c], y = pb[c];
+            const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
+            s0 = fmaf(t0, t0, s0);
+            s1 = fmaf(t1, t1, s1);
+            s2 = fmaf(t2, t2, s2);
+            s3 = fmaf(t3, t3, s3);
+        }
     }
-    return (s0 + s1) + (s2 + s3);
+    float sum = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) sum += __uint_as_float(xor_lanes(__float_as_uint(sum), m));
+    return sum;
 }
 
 constexpr int kBfMaxSurv = 3 * 32 * 32 / 2;   // survivor pairs per owner <= e(u) <= C(C-1)/2 + C^2 < 1.5 C^2, C <= 32
@@ -2055,15 +2066,21 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
             nsv = kBfMaxSurv;
         }
         wave_sync();
-        // rescore in FP32 from the original rows, one survivor per lane (the
-        // owner's member rows are re-read from the caches by its lanes)
-        for (uint32_t q0 = 0; q0 < nsv; q0 += 64) {
-            const uint32_t q = q0 + (uint32_t)lane;
+        // rescore in FP32 from the original rows, 16 lanes per surviving pair
+        // (four pairs per pass; each load instruction covers 256 contiguous
+        // bytes of four rows)
+        for (uint32_t q0 = 0; q0 < nsv; q0 += 4) {
+            const uint32_t q = q0 + (uint32_t)(lane >> 4);
+            float D = 0.f;
+            const float* ra = v.Xp;
+            const float* rb = v.Xp;
             if (q < nsv) {
                 const uint32_t e = s_surv[w][q];
-                const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
-                s_sd[w][q] = dist_lane(v.Xp + (size_t)s_pos[w][a] * dp, v.Xp + (size_t)s_pos[w][b] * dp, dp);
+                ra = v.Xp + (size_t)s_pos[w][e & 255u] * dp;
+                rb = v.Xp + (size_t)s_pos[w][(e >> 8) & 255u] * dp;
             }
+            D = dist_group16(ra, rb, dp, q < nsv);
+            if (q < nsv && (lane & 15) == 0) s_sd[w][q] = D;
         }
         rescored += nsv;
         wave_sync();

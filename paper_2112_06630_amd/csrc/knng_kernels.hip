@@ -1449,8 +1449,9 @@ __device__ __forceinline__ int pool_size(const Views& v, int u) {
 // 64 are sorted side by side in the wave's registers; otherwise each owner
 // takes the wave alone. Pools of more than 64 entries take the threshold
 // select in the same wave when 2C <= 60 (their latency hides behind the
-// small pools), else k_select_large (big[u] = 1).
-__global__ __launch_bounds__(256, 8) void k_select_small(Views v, uint64_t st0, int t) {
+// small pools), else k_select_large (big[u] = 1). Six waves per SIMD: at
+// eight (64 VGPRs) the two interleaved pools spill to scratch.
+__global__ __launch_bounds__(256, 6) void k_select_small(Views v, uint64_t st0, int t) {
     if (stopped(v)) return;
     __shared__ uint64_t s_key[kSelWaves][64];
     __shared__ uint32_t s_idx[kSelWaves][64];

@@ -211,13 +211,18 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
         P.o_orig2 = take((size_t)N * 4);
     }
     // counting-sort reverse bucketing: super-buckets of 2^shift positions, at
-    // most kRevMaxS of them, blocks of E entries (at most 1024 blocks)
+    // most kRevMaxS of them, blocks of E entries (at most 1024 blocks). The
+    // shift grows while a block's run into one super-bucket averages under 32
+    // entries (512 B: shorter runs are written as partial lines) and at
+    // least 256 super-buckets remain (one workgroup each in k_rev_bucket).
     P.rev_S = 0;
+    int64_t E = 4096;
+    while ((int64_t)(NK + E - 1) / E > 1024) E *= 2;
     for (int sh = 8; sh <= kRevMaxShift; ++sh) {
         const int64_t S = (N + (1LL << sh) - 1) >> sh;
+        const int64_t S2 = (N + (2LL << sh) - 1) >> (sh + 1);
+        if (sh < kRevMaxShift && E < 32 * S && S2 >= 256) continue;
         if (S <= kRevMaxS) {
-            int64_t E = 4096;
-            while ((NK + E - 1) / E > 1024) E *= 2;
             P.rev_shift = sh;
             P.rev_S = (int)S;
             P.rev_E = (int)E;

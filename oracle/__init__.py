@@ -171,6 +171,32 @@ def sample(state: State, K: int, C: int, seed: int, t: int, sampling: str = "wei
                   [cold[u, :nold[u]].copy() for u in range(N)], f2)
 
 
+def join_merge(X, state: State, smp: Sample, K: int, C: int) -> tuple[State, int, int]:
+    """Join and merge (Sec. 2 calculation step) of one iteration on the sampled
+    sets ``smp`` of ``state`` (its flags replaced by ``smp.flags``, the flags
+    after sampling). Returns (new state, e_t, c_t)."""
+    X = _f32(X)
+    N, d = X.shape
+    s = state.copy()
+    s.flags = np.ascontiguousarray(smp.flags, np.uint8).copy()
+    s.ids = np.ascontiguousarray(s.ids, np.int32)
+    s.dists = np.ascontiguousarray(s.dists, np.float64)
+    cnew = np.zeros((N, C), np.int32)
+    cold = np.zeros((N, C), np.int32)
+    nnew = np.array([len(a) for a in smp.cnew], np.int32)
+    nold = np.array([len(a) for a in smp.cold], np.int32)
+    for u in range(N):
+        cnew[u, :nnew[u]] = smp.cnew[u]
+        cold[u, :nold[u]] = smp.cold[u]
+    e = ctypes.c_int64(0)
+    c = ctypes.c_int64(0)
+    _check(_load().orc_join_merge(_ptr(X), N, d, K, C, _ptr(cnew), _ptr(nnew), _ptr(cold), _ptr(nold),
+                                  _ptr(s.ids), _ptr(s.dists), _ptr(s.flags), ctypes.byref(e), ctypes.byref(c)),
+           "join_merge")
+    s.t += 1
+    return s, int(e.value), int(c.value)
+
+
 def iterate(X, state: State, K: int, C: int, seed: int,
             sampling: str = "weighted") -> tuple[State, int, int]:
     """One synchronous iteration t = state.t + 1. Returns (new state, e_t, c_t)."""

@@ -443,38 +443,41 @@ int orc_build(const float *X, int64_t N, int32_t d, int32_t K, double rho, doubl
 }
 
 /* ---------------------------------------------------------------- greedy reordering
- * Sec. 3.2 (Algorithm 1, greedy clustering heuristic): one pass over the list
- * graph builds a permutation sigma (node -> memory spot) and its inverse, so
- * that the node put at spot i+1 is the nearest listed neighbour of the node
- * at spot i not already placed at a spot up to i. A host reference for the
- * device permutation's locality; it does not change any list (the method's
- * result keeps original ids).
- * Readings: at step i the list scanned is that of the node occupying spot i
- * (the chain the text describes), nearest first (rows are sorted by (D, id));
- * the two swaps use the values from before the step (the node a moves to
- * spot i+1 and the node there takes a's old spot); steps run for i = 0..n-2.
+ * Sec. 3.2 (greedy clustering heuristic): the memory order is grown one spot
+ * at a time so that the node placed at spot i+1 is the nearest listed
+ * neighbour of the node at spot i that has no spot yet. A host reference for
+ * the device permutation's locality; it changes no list (the method's result
+ * keeps original ids).
+ * Readings: spot 0 holds node 0; a list is scanned nearest first (rows are
+ * sorted by (D, id)); when every neighbour of the node at spot i is already
+ * placed, spot i+1 takes the unplaced node of smallest id (the paper leaves
+ * that spot to whatever its in-place exchanges put there).
+ * Outputs: sigma[node] = spot and sigma_inv[spot] = node.
  */
 int orc_greedy_order(const int32_t *ids, int64_t N, int32_t K, int32_t *sigma, int32_t *sigma_inv)
 {
     if (!ids || !sigma || !sigma_inv || N < 1 || K < 1) return -1;
-    for (int64_t v = 0; v < N; ++v) {
-        sigma[v] = (int32_t)v;
-        sigma_inv[v] = (int32_t)v;
-    }
-    for (int64_t i = 0; i + 1 < N; ++i) {
-        const int32_t *a = ids + (int64_t)sigma_inv[i] * K;
-        for (int32_t j = 0; j < K; ++j) {
-            const int64_t s = sigma[a[j]];
-            if (s <= i) continue;      /* placed before: it sits near its own neighbours */
-            if (s == i + 1) break;     /* already next to the node at spot i */
-            const int32_t b = sigma_inv[i + 1];
-            sigma[a[j]] = (int32_t)(i + 1);
-            sigma[b] = (int32_t)s;
-            sigma_inv[i + 1] = a[j];
-            sigma_inv[s] = b;
-            break;
+    uint8_t *placed = (uint8_t *)calloc((size_t)N, 1);
+    if (!placed) return -2;
+    int64_t lowest = 0;   /* every node below it has a spot */
+    int32_t prev = 0;
+    for (int64_t spot = 0; spot < N; ++spot) {
+        int32_t node = -1;
+        if (spot > 0) {
+            const int32_t *nb = ids + (int64_t)prev * K;
+            for (int32_t k = 0; k < K && node < 0; ++k)
+                if (!placed[nb[k]]) node = nb[k];
         }
+        if (node < 0) {
+            while (placed[lowest]) ++lowest;
+            node = (int32_t)lowest;
+        }
+        placed[node] = 1;
+        sigma[node] = (int32_t)spot;
+        sigma_inv[spot] = node;
+        prev = node;
     }
+    free(placed);
     return 0;
 }
 

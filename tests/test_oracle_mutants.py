@@ -29,9 +29,20 @@ MUTANTS = {
     "merge_readds_listed_ids": ("if (!in_list) all[n++] = cand[i];", "all[n++] = cand[i];"),
     "weight_not_symmetric": ("uint32_t a = (uint32_t)(u < x ? u : x), b = (uint32_t)(u < x ? x : u);",
                              "uint32_t a = (uint32_t)x, b = (uint32_t)u;"),
-    "greedy_scans_list_of_node_i": ("const int32_t *a = ids + (int64_t)sigma_inv[i] * K;",
-                                    "const int32_t *a = ids + i * K;"),
-    "greedy_inverse_not_updated": ("sigma_inv[i + 1] = a[j];", ";"),
+    "greedy_scans_list_of_spot_index": ("const int32_t *nb = ids + (int64_t)prev * K;",
+                                        "const int32_t *nb = ids + (spot - 1) * K;"),
+    "greedy_inverse_not_written": ("sigma_inv[spot] = node;", ";"),
+    "greedy_takes_placed_nodes": ("if (!placed[nb[k]]) node = nb[k];", "node = nb[k];"),
+    "new_new_proposes_one_way": ("prop[o++] = (orc_prop){nw[j], nw[i], D};",
+                                 "prop[o++] = (orc_prop){nw[i], nw[j], D};"),
+    "new_old_proposes_one_way": ("prop[o++] = (orc_prop){od[j], nw[i], D};",
+                                 "prop[o++] = (orc_prop){nw[i], od[j], D};"),
+    "cap_floor": ("double r = ceil(rho * (double)K);", "double r = floor(rho * (double)K);"),
+    "hash_ab_swapped": ("return orc_mix64(st ^ (((uint64_t)a << 32) | (uint64_t)b));",
+                        "return orc_mix64(st ^ (((uint64_t)b << 32) | (uint64_t)a));"),
+    "hash_t_dropped": ("uint64_t st = orc_mix64(s ^ t);", "uint64_t st = orc_mix64(s);"),
+    "merge_keeps_repeated_candidates": ("if (i > 0 && cand[i].id == cand[i - 1].id) continue;", ";"),
+    "entered_ids_flagged_old": ("if (f == 2) { f = ORC_NEW; ++c; }", "if (f == 2) { f = ORC_OLD; ++c; }"),
     "turbo_counts_whole_pool": ("nf[pool[i].flag == ORC_NEW ? 0 : 1] += 1;", "{ nf[0] += 1; nf[1] += 1; }"),
     "turbo_coin_skipped": ("if (mode == ORC_TURBO &&", "if (0 &&"),
     "turbo_coin_uses_k": ("* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)C << 32))",

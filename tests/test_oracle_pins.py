@@ -43,6 +43,61 @@ def test_hash_weights_are_uniform(oracle_lib):
     assert len(np.unique(w)) == len(w)
 
 
+def _unmix64(z):
+    """Inverse of the SplitMix64 output function (pinned above): undo the
+    xor-shifts and multiply by the inverses of the two odd constants mod 2^64."""
+    M = 0xFFFFFFFFFFFFFFFF
+
+    def unxorshift(y, s):
+        x = y
+        for _ in range(64 // s + 1):
+            x = y ^ (x >> s)
+        return x & M
+
+    z = unxorshift(z, 31)
+    z = (z * pow(0x94D049BB133111EB, -1, 1 << 64)) & M
+    z = unxorshift(z, 27)
+    z = (z * pow(0xBF58476D1CE4E5B9, -1, 1 << 64)) & M
+    return unxorshift(z, 30)
+
+
+def test_hash_composition_by_inverting_mix64(oracle_lib):
+    """H(seed, tag, t, a, b) = mix64(mix64(mix64(seed + phi*(tag+1)) ^ t) ^ (a << 32 | b))
+    (the counter-hash reading of Sec. 3.1's uniform weights and Sec. 2's random
+    initial graph). mix64 is a bijection, so peeling one layer off with its
+    inverse must expose (a << 32 | b) against H(., 0, 0), then t, then
+    seed + phi*(tag+1); with seed 0 the innermost layer is the (tag+1)-th
+    SplitMix64 output (the reference values)."""
+    M = 0xFFFFFFFFFFFFFFFF
+    PHI = 0x9E3779B97F4A7C15
+    rng = np.random.default_rng(5)
+    for z in rng.integers(0, 2**63, 20, dtype=np.int64).tolist():
+        assert _unmix64(oracle.mix64(z)) == z
+        assert _unmix64(oracle.mix64(z | (1 << 63))) == z | (1 << 63)
+    for _ in range(40):
+        seed = int(rng.integers(0, 2**63)) | (int(rng.integers(0, 2)) << 63)
+        tag = int(rng.integers(1, 3))
+        t = int(rng.integers(0, 1000))
+        a, b = (int(x) for x in rng.integers(0, 2**31, 2))
+        h = oracle.hash64(seed, tag, t, a, b)
+        inner = _unmix64(oracle.hash64(seed, tag, t, 0, 0))
+        assert _unmix64(h) ^ inner == (a << 32) | b
+        assert _unmix64(inner) ^ _unmix64(_unmix64(oracle.hash64(seed, tag, 0, 0, 0))) == t
+        assert _unmix64(_unmix64(_unmix64(oracle.hash64(seed, tag, 0, 0, 0)))) == (seed + PHI * (tag + 1)) & M
+    vals = [int(l, 16) for l in open(os.path.join(HERE, "golden", "splitmix64_seed0.txt")) if l.startswith("0x")]
+    for tag in (0, 1):
+        assert _unmix64(_unmix64(oracle.hash64(0, tag, 0, 0, 0))) == vals[tag]
+
+
+@pytest.mark.parametrize("K,rho,C", [(15, 0.5, 8), (20, 0.5, 10), (20, 1.0, 20), (9, 0.3, 3), (10, 0.25, 3),
+                                     (10, 0.01, 1), (1, 1.0, 1), (64, 1.0, 64), (7, 0.9, 7)])
+def test_cap_closed_forms(oracle_lib, K, rho, C):
+    """C = min(K, max(1, ceil(rho*K))): Sec. 3.1 samples rho*k per neighbourhood;
+    a non-integer rho*k is rounded up (15 * 0.5 = 7.5 -> 8, 9 * 0.3 = 2.7 -> 3),
+    and at least one member is sampled (10 * 0.01 -> 1)."""
+    assert oracle.cap(K, rho) == C
+
+
 # --------------------------------------------------------------------------- distances / brute force
 
 def test_dist_matches_numpy_on_integer_points(oracle_lib):
@@ -384,6 +439,73 @@ def test_greedy_order_recovers_clusters_first(oracle_lib):
 
 
 # --------------------------------------------------------------------------- join + merge
+
+def _sorted_random_state(X, K, seed, p_new=0.6):
+    """A random graph with the true distances (integer data: exact), rows sorted
+    by (D, id), random NEW/OLD flags."""
+    N = X.shape[0]
+    st = _random_state(N, K, seed, p_new)
+    Xi = X.astype(np.int64)
+    for u in range(N):
+        dd = ((Xi[st.ids[u]] - Xi[u]) ** 2).sum(1)
+        order = np.lexsort((st.ids[u], dd))
+        st.ids[u] = st.ids[u][order]
+        st.flags[u] = st.flags[u][order]
+        st.dists[u] = dd[order].astype(np.float64)
+    return st
+
+
+def _join_merge_by_definition(X, st, smp, K):
+    """Sec. 2's calculation step written out per pair: in each owner's sample,
+    every new x new pair (p != q, unordered) and every new x old pair is
+    evaluated once and proposes each of its two points to the other; the new
+    list of p is the K smallest (D, id) of its list and of the proposed ids not
+    already in it (each such id once); ids that enter are NEW, kept entries keep
+    the flag they have after sampling; c_t counts the ids that entered."""
+    N = X.shape[0]
+    Xi = X.astype(np.int64)
+    props = [dict() for _ in range(N)]
+    e = 0
+    for u in range(N):
+        nw = [int(x) for x in smp.cnew[u]]
+        od = [int(x) for x in smp.cold[u]]
+        pairs = [(nw[i], nw[j]) for i in range(len(nw)) for j in range(i + 1, len(nw))]
+        pairs += [(a, b) for a in nw for b in od]
+        e += len(pairs)
+        for a, b in pairs:
+            dd = float(((Xi[a] - Xi[b]) ** 2).sum())
+            props[a][b] = dd
+            props[b][a] = dd
+    ids, dists, flags = st.ids.copy(), st.dists.copy(), smp.flags.copy()
+    c = 0
+    for p in range(N):
+        listed = set(st.ids[p].tolist())
+        ent = [(float(st.dists[p, k]), int(st.ids[p, k]), int(smp.flags[p, k]), 0) for k in range(K)]
+        ent += [(dd, q, oracle.NEW, 1) for q, dd in props[p].items() if q not in listed]
+        ent.sort(key=lambda x: (x[0], x[1]))
+        for k, (dd, q, f, fresh) in enumerate(ent[:K]):
+            ids[p, k], dists[p, k], flags[p, k] = q, dd, f
+            c += fresh
+    return ids, dists, flags, e, c
+
+
+@pytest.mark.parametrize("N,K,rho,seed,t", [(40, 5, 1.0, 1, 1), (60, 6, 0.5, 2, 2), (50, 8, 0.75, 3, 4),
+                                             (30, 4, 0.25, 4, 1)])
+def test_join_merge_matches_definition_by_brute_force(oracle_lib, N, K, rho, seed, t):
+    """One join + merge of the oracle equals the step written out pair by pair,
+    on random states with mixed flags and small integer coordinates (exact
+    distances, frequent ties: the (D, id) order decides)."""
+    X = synth.integer_points(N, 3, 4, seed)
+    st = _sorted_random_state(X, K, seed)
+    C = oracle.cap(K, rho)
+    smp = oracle.sample(st, K, C, seed, t)
+    got, e, c = oracle.join_merge(X, st, smp, K, C)
+    ids, dists, flags, e_ref, c_ref = _join_merge_by_definition(X, st, smp, K)
+    assert e == e_ref and c == c_ref and c > 0
+    assert np.array_equal(got.ids, ids)
+    assert np.array_equal(got.dists, dists)
+    assert np.array_equal(got.flags, flags)
+
 
 def test_exact_knn_is_a_fixed_point(oracle_lib):
     """Feeding the exact K-NNG (all NEW) changes nothing: no proposal can beat it."""

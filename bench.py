@@ -133,14 +133,20 @@ def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted", threads=0):
     st = oracle.init(Xnp, w["K"], w["seed"])
     ev = 0
     iters = 0
+    thr = w["delta"] * Xnp.shape[0] * w["K"]
+    stopped = False
     while time.perf_counter() - t0 < budget_s and iters < w["max_iters"]:
         st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"], sampling)
         ev += e
         iters += 1
+        if c < thr:   # the build's own stop rule (Sec. 2: changes below delta*N*K)
+            stopped = True
+            break
     dt = time.perf_counter() - t0
+    how = "stop rule met" if stopped else ("iteration cap" if iters >= w["max_iters"] else "time budget")
     return {"value": ev / dt, "unit": "distance evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, full {w['workload']} input, init + iterations 1..{iters} "
-                      f"({ev} evals in {dt:.1f} s)"}
+            "sample": f"FP64 oracle, full {w['workload']} input, init + iterations 1..{iters} ({how}; "
+                      f"{ev} evals in {dt:.1f} s)"}
 
 
 def traffic_path(workload: str) -> str:
@@ -369,6 +375,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU oracle baseline (0: all host cores)")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="headline workload only (by default the low-d blobs4m_d3 build is timed beside it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the builds, copy this many MiB once (device to device) so that "
                          "HBM counters can be scaled by a kernel of known traffic")
@@ -391,17 +399,88 @@ def main():
         run_sweep(args)
         return
 
-    import numpy as np
-    import torch
-    import synth
-    import paper_2112_06630_amd as knng
-
     w = dict(WORKLOADS[args.workload])
-    if args.delta is not None:
-        w["delta"] = args.delta
     if args.workload == "batch512":
+        if args.delta is not None:
+            w["delta"] = args.delta
         bench_batch(args, w)
         return
+    out = measure(args, w, args.steps, args.warmup, args.recall_rows, not args.no_cpu)
+    if args.workload == WORKLOAD["workload"] and not args.no_secondary:
+        # the low-d gather-bound workload beside the headline, so that every
+        # default run also times it (fewer steps: one build is ~0.1 s)
+        lw = dict(WORKLOADS["blobs4m_d3"])
+        sec = measure(args, lw, max(3, min(args.steps, 10)), max(1, min(args.warmup, 2)), 2000, False)
+        out["secondary"] = {lw["workload"]: {k: sec[k] for k in (
+            "value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "iters", "evals_per_build",
+            "recall", "recall_rows", "ms_to_recall_0.99", "device_ms_per_build", "phase_ms", "roofline")}}
+    print(json.dumps(out), flush=True)
+
+
+def join_kernel_name(knng, s0, precision):
+    if precision == "bf16":
+        return "k_join_bf16"
+    return {knng.PATH_MFMA: "k_join_mfma", knng.PATH_MFMA_BF16X3: "k_join_split"}.get(s0["path"], "k_join_valu")
+
+
+def join_roofline(knng, w, s0, stats, members, precision):
+    """Roofline of the local join from its event-timed launches.
+
+    Algorithmic bytes per launch follow the per-unit figures of the method's
+    byte model: every member row gathered once per owner in FP32
+    (4 * d_pad bytes, no reuse across owners), its sample entry read (8 B),
+    and one 8-byte key written per emitted proposal. ``encoding`` prices the
+    rows as the kernel actually stores them (2 * d_pad bytes per split-BF16
+    plane read; the FP32 row otherwise) plus the 20 B of member metadata it
+    reads (sample entry 8, snapshot K-th key 8, norm 4): on data that is
+    exact in one BF16 plane this is about half the FP32 figure, and the
+    FP32-model fraction can then exceed 1 without the kernel moving more
+    than the memory system delivers. ``traffic`` is the counter-measured
+    L2-to-memory traffic of the same kernel (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled by a copy of known size), when the committed counter
+    summary was taken on the current source."""
+    import numpy as np
+    kernel = join_kernel_name(knng, s0, precision)
+    join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
+    dpad = s0["dpad"]
+    alg = [m * (4 * dpad + 8) + 8 * pr for m, pr in zip(members, s0["proposals"])]
+    enc_row = {"k_join_split": 2 * dpad * max(1, s0["planes"]), "k_join_bf16": 2 * dpad}.get(kernel, 4 * dpad)
+    enc = [m * (enc_row + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
+    flops = [e * 2 * w["d"] for e in s0["evals"]]
+    sec = sum(join_ms) / 1e3
+    ach = sum(alg) / sec / 1e9
+    ach_enc = sum(enc) / sec / 1e9
+    ach_fl = sum(flops) / sec / 1e12
+    n = len(join_ms)
+    traffic = traffic_record(kernel, w["workload"])
+    peak_fl = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "avg_launch_ms": round(sum(join_ms) / n, 4), "launches": n,
+            "bytes_per_launch": int(sum(alg) / n), "members_per_launch": int(sum(members) / n),
+            "proposals_per_launch": int(sum(s0["proposals"]) / n),
+            "encoding": {"row_bytes": enc_row, "bytes_per_launch": int(sum(enc) / n),
+                         "achieved": round(ach_enc, 1), "frac": round(ach_enc / PEAK_HBM_GBS, 4)},
+            "mfma": {"achieved": round(ach_fl, 3), "peak": peak_fl, "unit": "TFLOP/s",
+                     "frac": round(ach_fl / peak_fl, 4), "flops_per_launch": int(sum(flops) / n)}}
+    if traffic:
+        roof["traffic_achieved"] = round(traffic * n / sec / 1e9, 1)
+    if roof["frac"] > 1:
+        roof["note"] = ("the FP32 row model exceeds the HBM peak: the kernel reads a lossless "
+                        f"{enc_row // dpad}-byte-per-dimension encoding of the rows (see encoding)")
+    return roof
+
+
+def measure(args, w, steps, warmup, recall_rows, with_cpu):
+    """Times `steps` whole builds of workload `w` (inputs resident in HBM)
+    after `warmup` untimed ones; returns the result line as a dict."""
+    import numpy as np
+    import torch
+    import paper_2112_06630_amd as knng
+
+    w = dict(w)
+    if args.delta is not None:
+        w["delta"] = args.delta
     Xnp = w["gen"]()
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
@@ -413,16 +492,16 @@ def main():
     run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
                              path=args.path, workspace=ws, out=(ids, dists), precision=args.precision,
                              sampling=args.sampling)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run()
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         stats.append(run()[2])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / steps
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -435,48 +514,22 @@ def main():
         assert s["evals"] == stats[0]["evals"] and s["changes"] == stats[0]["changes"], "non-deterministic build"
     value = evals / (ms_per_step / 1e3)
 
-    # local-join roofline. The join gathers the member rows of every owner
-    # with a new member: its algorithmic bytes per launch (no reuse across
-    # owners) are sum_u m_u * (row bytes + 20 B of member metadata: sample
-    # entry 8, snapshot K-th key 8, norm 4) + 8 B per emitted proposal (its
-    # key). Row bytes: 2 d_pad per BF16 plane read (split form), 4 d_pad for
-    # FP32 rows. m_u per iteration comes from the step API, which replays the
-    # same deterministic trajectory (untimed).
     s0 = stats[len(stats) // 2]
-    join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
-    flops = [e * 2 * w["d"] for e in s0["evals"]]
-    kernel = {knng.PATH_MFMA: "k_join_mfma", knng.PATH_MFMA_BF16X3: "k_join_split"}.get(s0["path"], "k_join_valu")
-    if args.precision == "bf16":
-        kernel = "k_join_bf16"
-    row_bytes = {"k_join_split": 2 * s0["dpad"] * max(1, s0["planes"]), "k_join_bf16": 2 * s0["dpad"]}.get(
-        kernel, 4 * s0["dpad"])
-    members, curve_ids = member_counts_and_graphs(X, w, args, s0["iters"], not args.no_recall)
-    jbytes = [m * (row_bytes + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
-    achieved_bw = sum(jbytes) / (sum(join_ms) / 1e3) / 1e9
-    achieved_fl = sum(flops) / (sum(join_ms) / 1e3) / 1e12
-    traffic = traffic_record(kernel, w["workload"])
-    # the contraction itself, priced at the peak of the instructions it runs on (context)
-    peak_fl = PEAK_BF16_MFMA_TFLOPS if kernel in ("k_join_bf16", "k_join_split") else PEAK_FP32_MFMA_TFLOPS
-    roof = {"bound": "hbm", "achieved": round(achieved_bw, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved_bw / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel,
-            "avg_launch_ms": round(sum(join_ms) / len(join_ms), 4),
-            "bytes_per_launch": int(sum(jbytes) / len(jbytes)),
-            "members_per_launch": int(sum(members) / len(members)),
-            "mfma": {"achieved": round(achieved_fl, 3), "peak": peak_fl, "unit": "TFLOP/s",
-                     "frac": round(achieved_fl / peak_fl, 4), "flops_per_launch": int(sum(flops) / len(flops))}}
+    no_recall = args.no_recall or recall_rows <= 0
+    # per-iteration member counts (and graphs) from a step-API replay of the
+    # same deterministic trajectory (untimed)
+    members, curve_ids = member_counts_and_graphs(X, w, args, s0["iters"], not no_recall)
+    roof = join_roofline(knng, w, s0, stats, members, args.precision)
+    kernel = roof["kernel"]
 
     # time to recall 0.99: per-iteration graphs from the same step-API replay
-    rec = None
-    t99 = None
-    rcurve = None
-    derr = None
-    rec_plain = None
-    if not args.no_recall:
+    rec = t99 = rcurve = derr = rec_plain = None
+    if not no_recall:
         N = w["N"]
-        if N <= args.recall_rows:
+        if N <= recall_rows:
             rows = torch.arange(N, device=dev)
         else:
-            rows = torch.from_numpy(np.sort(np.random.default_rng(12345).choice(N, args.recall_rows,
+            rows = torch.from_numpy(np.sort(np.random.default_rng(12345).choice(N, recall_rows,
                                                                                 replace=False))).to(dev)
         tau, exact_ids = exact_kth(X, w["K"], rows)
         curve = [recall_of(X, ids_t, tau, rows) for ids_t in curve_ids]
@@ -502,22 +555,30 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) / 1e3) / 1e9
     del src, dst
-    cpu = None if args.no_cpu else cpu_baseline(Xnp, w, sampling=args.sampling, threads=args.cpu_threads)
+    cpu = cpu_baseline(Xnp, w, sampling=args.sampling, threads=args.cpu_threads) if with_cpu else None
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
+    if kernel == "k_join_split":
+        dtype = "f32" if s0["planes"] == 3 else f"bf16x{s0['planes']}+f32"
+    else:
+        dtype = {"k_join_bf16": "bf16+f32"}.get(kernel, "f32")
 
-    out = {
+    del ws, ids, dists, X
+    return {
         "metric": "distance evals/sec", "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": {"k_join_bf16": "bf16+f32", "k_join_split": "bf16x3+f32"}.get(kernel, "f32"),
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        # split form: the BF16 planes the join reads (all three carry FP32 values exactly)
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
-                   "reorder": bool(args.reorder), "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
+                   "reorder": bool(args.reorder),
+                   "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
                    "precision": args.precision, "sampling": args.sampling},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "recall_plain": rec_plain,
         "ms_to_recall_0.99": t99,
-        "recall_rows": None if args.no_recall else int(min(w["N"], args.recall_rows)),
+        "recall_rows": None if no_recall else int(min(w["N"], recall_rows)),
         "recall_curve": rcurve,   # [device ms since the build began, recall of G_t] per iteration
         # stored FP32 distances of the recall rows vs FP64: max absolute and max relative error
         "dist_err_vs_fp64": None if derr is None else {"abs": derr[0], "rel": derr[1]},
@@ -533,7 +594,6 @@ def main():
         "paper_gflops": round(evals * (3 * w["d"] - 1) / (ms_per_step / 1e3) / 1e9, 1),
         "copy_GBps": round(copy_gbs, 1),
     }
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

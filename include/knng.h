@@ -58,24 +58,9 @@ typedef enum {
  * Join paths. AUTO takes the VALU direct form when d < 48 or ceil(rho*K) > 32,
  * else (FP32 precision) the split-BF16 Gram form below, except that data
  * whose values need all three BF16 planes (counted at create) run on FP32
- * tiles (KNNG_PATH_MFMA) below d = 192, where those are faster; on the MFMA
- * side it would take the exact integer form when X qualifies (checked on the
- * device at create).
- *
- * Exact integer form (KNNG_PATH_MFMA_I8). X qualifies when every value is an
- * integer of magnitude <= 2^24 and max(X) - min(X) <= 255 over the whole input
- * (8-bit pixel data, for instance), and d <= 32768. The rows are shifted by one
- * constant (min(X) + 128) into int8; squared distances are shift invariant, so
- * ||x'||^2 + ||y'||^2 - 2 x'.y' computed in int32 (int8 MFMA tiles, int32
- * accumulation; no overflow for d <= 32768) is the exact squared distance, and
- * the stored FP32 distance is its correctly rounded value. Wherever the FP32
- * forms are exact (all partial sums below 2^24) the results are bit-identical
- * to theirs. Requesting it for an input that does not qualify fails with
- * KNNG_EINVAL at knng_create.
- *
- * In this release the exact integer form is disabled: a request for it fails
- * with KNNG_EINVAL (at knng_workspace_bytes and knng_create) and AUTO never
- * selects it.
+ * tiles (KNNG_PATH_MFMA) below d = 192, where those are faster.
+ * KNNG_PATH_MFMA_I8 is reserved (an exact int8 form that was withdrawn):
+ * requesting it fails with KNNG_EINVAL.
  */
 /*
  * Split-BF16 Gram form (KNNG_PATH_MFMA_BF16X3, what AUTO takes on the MFMA
@@ -97,7 +82,7 @@ typedef enum {
     KNNG_PATH_AUTO = 0,         /* see above */
     KNNG_PATH_VALU = 1,         /* sum_j (x_j - y_j)^2 on the vector ALUs */
     KNNG_PATH_MFMA = 2,         /* ||x||^2 + ||y||^2 - 2 x.y with FP32 MFMA tiles */
-    KNNG_PATH_MFMA_I8 = 3,      /* exact integer form: int8 MFMA tiles, int32 accumulation */
+    KNNG_PATH_MFMA_I8 = 3,      /* reserved: rejected with KNNG_EINVAL */
     KNNG_PATH_MFMA_BF16X3 = 4   /* split-BF16 Gram form on BF16 MFMA tiles, FP32 accumulation */
 } knng_path;
 

@@ -327,13 +327,25 @@ class Batch:
                                    (tuning or "auto").encode(), ctypes.c_void_p(self.stream.cuda_stream)))
         self._h = h
         self.captured = False
+        # the kernels use these buffers on self.stream: the caching allocator
+        # must not hand their memory out again before that work is done
+        for t in (self.ws, *self.ids, *self.dists, *self.Xs):
+            t.record_stream(self.stream)
 
     @property
     def tuning(self) -> str:
         return lib.knng_batch_tuning(self._h).decode()
 
+    def _order_after(self):
+        # work the caller queues next on its current stream (reading ids and
+        # dists, say) runs after the build
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        torch.cuda.current_stream(self.ws.device).wait_event(ev)
+
     def execute(self):
         _check(lib.knng_batch_execute(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._order_after()
 
     def capture(self):
         _check(lib.knng_batch_capture(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
@@ -341,6 +353,7 @@ class Batch:
 
     def launch(self):
         _check(lib.knng_batch_launch(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+        self._order_after()
 
     def synchronize(self):
         self.stream.synchronize()
@@ -359,6 +372,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
+            self.stream.synchronize()   # no launch of the plan's graph is still running
             lib.knng_batch_destroy(self._h)
             self._h = None
 

@@ -56,12 +56,10 @@ int32_t sample_cap(int32_t K, double rho) {
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Plan {
-    int path;        // resolved knng_path (MFMA until the create-time check picks MFMA_I8)
-    int want_i8;     // 0: no, 1: if X qualifies, 2: required (KNNG_PATH_MFMA_I8)
+    int path;        // resolved knng_path
     int reorder;
     int bf16;        // BF16-screened precision form
     int dp;
-    int dpi;         // int8 row length of the exact integer form
     int split;       // split-BF16 copies of the rows
     int turbo;       // turbosampling coin (knng_sampling)
     int rev_shift, rev_S, rev_B, rev_E;   // counting-sort reverse bucketing (rev_S = 0: atomics)
@@ -71,7 +69,7 @@ struct Plan {
     // byte offsets
     size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
-        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xi, o_ni, o_Xi2, o_ni2, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp;
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp;
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -92,11 +90,6 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     return KNNG_OK;
 }
 
-// The exact integer form is switched off: its first run at 60000 x 784 ended
-// in a device fault whose cause has not been found. Requests fail with
-// KNNG_EINVAL and AUTO never selects it; the kernels stay in the library.
-constexpr bool kInt8FormEnabled = false;
-
 // AUTO's join path, from the single-Gaussian sweeps (n = 16384, K = 20): the
 // direct form on the VALU up to d = 40, the matrix forms from d = 48; among
 // those, data that needs all three BF16 planes runs faster on FP32 tiles
@@ -104,7 +97,7 @@ constexpr bool kInt8FormEnabled = false;
 constexpr int kAutoMatrixMinD = 48;
 constexpr int kAutoSplit3MinD = 192;
 
-knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool allow_i8 = true) {
+knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     knng_status s = validate(N, d, p);
     if (s != KNNG_OK) return s;
     const int K = p->K;
@@ -112,16 +105,9 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     P.turbo = p->sampling == KNNG_SAMPLING_TURBO ? 1 : 0;
     int path = p->path;
     P.bf16 = p->precision == KNNG_BF16_SCREEN ? 1 : 0;
-    P.want_i8 = 0;
-    if (!kInt8FormEnabled) allow_i8 = false;
-    if (path == KNNG_PATH_MFMA_I8) {
-        if (!kInt8FormEnabled) return fail(KNNG_EINVAL, "the exact integer form is disabled in this release");
-        if (!allow_i8) return fail(KNNG_EINVAL, "the exact integer form is not available here");
-        if (P.bf16) return fail(KNNG_EINVAL, "the exact integer form excludes the BF16-screened form");
-        if (d > kMaxI8Dim) return fail(KNNG_EINVAL, "the exact integer form needs d <= 32768");
-        P.want_i8 = 2;
-        path = KNNG_PATH_MFMA;
-    }
+    // the exact integer form (int8 tiles) was withdrawn after a device fault
+    // whose cause was never shown; the value stays reserved
+    if (path == KNNG_PATH_MFMA_I8) return fail(KNNG_EINVAL, "the exact integer form is not available");
     if (P.bf16) {
         if (path == KNNG_PATH_VALU || path == KNNG_PATH_MFMA_BF16X3)
             return fail(KNNG_EINVAL, "the BF16-screened form runs on the FP32 MFMA path");
@@ -130,13 +116,11 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     if (path == KNNG_PATH_AUTO) {
         path = (d >= kAutoMatrixMinD && 2 * P.C <= 64) ? (P.bf16 ? KNNG_PATH_MFMA : KNNG_PATH_MFMA_BF16X3)
                                                         : KNNG_PATH_VALU;
-        if (path == KNNG_PATH_MFMA_BF16X3 && allow_i8 && d <= kMaxI8Dim) P.want_i8 = 1;
     }
     if ((path == KNNG_PATH_MFMA || path == KNNG_PATH_MFMA_BF16X3) && 2 * P.C > 64)
         return fail(KNNG_EINVAL, "MFMA path needs ceil(rho*K) <= 32");
     P.split = path == KNNG_PATH_MFMA_BF16X3 ? 1 : 0;
     P.path = path;
-    P.dpi = P.want_i8 ? (int)round_up(d, 64) : 0;
     P.reorder = p->reorder ? 1 : 0;
     P.dp = (int)(path != KNNG_PATH_VALU ? round_up(d, 32) : round_up(d, 4));
     if (path == KNNG_PATH_VALU) {
@@ -185,14 +169,6 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     if (P.split) {
         P.o_Xs = take((size_t)3 * N * P.dp * 2);
         if (p->reorder) P.o_Xs2 = take((size_t)3 * N * P.dp * 2);
-    }
-    if (P.want_i8) {
-        P.o_Xi = take((size_t)N * P.dpi);
-        P.o_ni = take((size_t)N * 4);
-        if (p->reorder) {
-            P.o_Xi2 = take((size_t)N * P.dpi);
-            P.o_ni2 = take((size_t)N * 4);
-        }
     }
     if (p->reorder) {   // permutation scratch only when the permutation is on
         P.o_comp = take((size_t)N * 4);
@@ -298,13 +274,6 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     if (P.split) {
         v.Xs = reinterpret_cast<uint16_t*>(b + P.o_Xs);
         if (P.reorder) v.Xs2 = reinterpret_cast<uint16_t*>(b + P.o_Xs2);
-    }
-    v.dpi = P.dpi;
-    if (P.want_i8) {   // v.Xi stays null until the create-time check selects the form
-        if (P.reorder) {
-            v.Xi2 = reinterpret_cast<int8_t*>(b + P.o_Xi2);
-            v.ni2 = reinterpret_cast<int32_t*>(b + P.o_ni2);
-        }
     }
     if (P.rev_S) {
         v.rev_shift = P.rev_shift;
@@ -420,10 +389,6 @@ knng_status do_permute(knng_ctx* c) {
     std::swap(v.lpos, v.lpos2);
     std::swap(v.Xb, v.Xb2);
     std::swap(v.nb, v.nb2);
-    if (v.Xi) {
-        std::swap(v.Xi, v.Xi2);
-        std::swap(v.ni, v.ni2);
-    }
     if (v.Xs) std::swap(v.Xs, v.Xs2);
     launch_perm_posof(v, s);
     HIP_TRY(hipEventRecord(c->ev[5], s));
@@ -468,8 +433,6 @@ knng_status enqueue_iteration(knng_ctx* c, int t, double thr) {
     launch_select(v, st, t, s);
     if (c->plan.bf16)
         launch_join_bf16(v, s, E[1], E[2]);
-    else if (c->plan.path == KNNG_PATH_MFMA_I8)
-        launch_join_i8(v, s, E[1], E[2]);
     else if (c->plan.path == KNNG_PATH_MFMA_BF16X3)
         launch_join_split(v, s, E[1], E[2]);
     else if (c->plan.path == KNNG_PATH_MFMA)
@@ -529,34 +492,8 @@ knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
 }
 
 int dist_mode(const knng_ctx* c) {
-    if (c->plan.path == KNNG_PATH_MFMA_I8) return kDistInt8;
     if (c->plan.path == KNNG_PATH_MFMA_BF16X3) return kDistGram;
     return (c->plan.path == KNNG_PATH_MFMA && !c->plan.bf16) ? kDistGram : kDistDirect;
-}
-
-// Exact integer form: check X on the device (integers, |x| <= 2^24, span <=
-// 255), then shift the rows into int8 and switch the join to the int8 tiles.
-knng_status select_int8(knng_ctx* c) {
-    Views& v = c->v;
-    launch_int_scan(c->dX, c->N * (int64_t)c->d, v.flag, c->stream);
-    HIP_TRY(hipGetLastError());
-    uint32_t fl[3] = {0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(fl, v.flag + 8, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const int32_t lo = (int32_t)fl[1], hi = (int32_t)fl[2];
-    const bool ok = fl[0] == 0u && (int64_t)hi - (int64_t)lo <= 255;
-    if (!ok) {
-        if (c->plan.want_i8 == 2)
-            return fail(KNNG_EINVAL, "the exact integer form needs integer X with max - min <= 255 and |x| <= 2^24");
-        return KNNG_OK;
-    }
-    char* b = static_cast<char*>(c->ws);
-    v.Xi = reinterpret_cast<int8_t*>(b + c->plan.o_Xi);
-    v.ni = reinterpret_cast<int32_t*>(b + c->plan.o_ni);
-    launch_make_i8(v, lo + 128, c->stream);
-    HIP_TRY(hipGetLastError());
-    c->plan.path = KNNG_PATH_MFMA_I8;
-    return KNNG_OK;
 }
 
 }  // namespace
@@ -635,16 +572,9 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
         const uint64_t used = c->hc[kCntSplit];
         c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
         c->stats.planes = c->v.planes;
-        if (c->v.planes > 1 || P.want_i8) launch_prep_rest(dX, c->v, c->stream);
+        if (c->v.planes > 1) launch_prep_rest(dX, c->v, c->stream);
         if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
             c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)
-    }
-    if (P.want_i8) {
-        knng_status is = select_int8(c);
-        if (is != KNNG_OK) {
-            knng_destroy(c);
-            return is;
-        }
     }
     c->stats.path = c->plan.path;
     *out = c;
@@ -882,7 +812,6 @@ knng_status batch_validate(const knng_dataset* descs, int32_t n, const knng_para
     if (!p) return fail(KNNG_EINVAL, "params is NULL");
     if (p->reorder) return fail(KNNG_EINVAL, "the batched form runs without the permutation");
     if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "the batched form runs in FP32");
-    if (p->path == KNNG_PATH_MFMA_I8) return fail(KNNG_EINVAL, "the batched form has no exact integer form");
     if (p->max_iters < 1) return fail(KNNG_EINVAL, "the batched form needs max_iters >= 1");
     for (int i = 0; i < n; ++i) {
         if (!descs[i].dX || !descs[i].d_ids || !descs[i].d_dists) return fail(KNNG_EINVAL, "dataset pointer is NULL");
@@ -923,7 +852,7 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
         gp.path = g.path;
         gp.reorder = 0;
         Plan P{};
-        knng_status s = make_plan(g.N, g.d, &gp, P, false);
+        knng_status s = make_plan(g.N, g.d, &gp, P);
         if (s != KNNG_OK) return s;
         g.plan = P;
         g.off = total;

@@ -25,16 +25,12 @@ enum Counter : int {
     kNumCounters = 8
 };
 
-// How a kernel outside the join computes a distance: the same formula as the
-// join of the resolved path, so a pair gets one key wherever it is evaluated
-// (exactly so for the VALU and integer forms).
+// How a kernel outside the join computes a distance: the formula of the
+// join of the resolved path (exactly the same value for the VALU form).
 enum DistMode : int {
     kDistDirect = 0,   // sum_j (x_j - y_j)^2, FP32 (VALU path)
-    kDistGram = 1,     // FP32 Gram form (FP32 MFMA path)
-    kDistInt8 = 2      // exact int32 Gram form of the shifted int8 rows
+    kDistGram = 1      // FP32 Gram form (matrix paths)
 };
-
-constexpr int kMaxI8Dim = 32768;   // d * 255^2 and the int32 Gram terms stay below 2^31
 
 // Views of the caller's workspace, carved by the host.
 struct Views {
@@ -46,9 +42,6 @@ struct Views {
     float2* nb;         // [N] BF16 rows: {squared norm, norm of the rounding error bf16(x) - x}
     uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
     int planes;         // split form: leading planes the join reads (1..3; the rest are all zero)
-    int dpi;            // int8 row length (multiple of 64), exact integer form
-    int8_t* Xi;         // [N, dpi] rows shifted into int8 (exact integer form), else null
-    int32_t* ni;        // [N] squared norms of the int8 rows
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
@@ -108,9 +101,7 @@ struct Views {
     float* nrm2;        // [N]
     uint16_t* Xb2;      // [N, dp]
     float2* nb2;        // [N]
-    int8_t* Xi2;        // [N, dpi]
     uint16_t* Xs2;      // [3, N, dp]
-    int32_t* ni2;       // [N]
     int32_t* orig2;     // [N]
     uint32_t* flag;     // small device flags
     uint32_t* stop;     // single build: set when the stop rule held (or a device
@@ -130,11 +121,6 @@ void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
 void launch_norms(const Views& v, hipStream_t s);
 void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s);
 void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int mode, hipStream_t s);
-// exact integer form: flag[8] |= 1 if some value is not an integer of
-// magnitude <= 2^24; flag[9] = min, flag[10] = max (int32) of the others
-void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t s);
-void launch_make_i8(const Views& v, int32_t shift, hipStream_t s);
-void launch_join_i8(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_make_split(const Views& v, hipStream_t s);
 // one pass over X for the MFMA forms: padded rows, norms, identity positions,
 // finiteness check and (split != 0) the split-BF16 planes
@@ -148,7 +134,6 @@ void launch_rev_hist(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr);
 void launch_batch_setup(const Views& v, hipStream_t s);
 void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s);
 void launch_batch_finalize(const Views& v, hipStream_t s);
-void launch_fill_i32(int32_t* p, int32_t val, int64_t n, hipStream_t s);
 void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
 void launch_rev_scatter(const Views& v, uint64_t st_sample, int t, hipStream_t s);
 // reverse buckets (roff, rev) by the counting sort; staging in the proposal buffer

@@ -222,23 +222,6 @@ __device__ __forceinline__ float dist_direct(const float* __restrict__ a, const 
     return (s0 + s1) + (s2 + s3);
 }
 
-// Exact integer form: int32 Gram form of two int8 rows (dpi % 16 == 0) with
-// four-way int8 dot products. Every term is exact, so the value is the exact
-// squared distance and its conversion the correctly rounded FP32 distance.
-__device__ __forceinline__ float dist_int8(const int8_t* __restrict__ a, const int8_t* __restrict__ b, int dpi,
-                                           int32_t na, int32_t nb) {
-    int32_t dot = 0;
-    for (int j = 0; j < dpi; j += 16) {
-        const int4 x = *reinterpret_cast<const int4*>(a + j);
-        const int4 y = *reinterpret_cast<const int4*>(b + j);
-        dot = __builtin_amdgcn_sdot4(x.x, y.x, dot, false);
-        dot = __builtin_amdgcn_sdot4(x.y, y.y, dot, false);
-        dot = __builtin_amdgcn_sdot4(x.z, y.z, dot, false);
-        dot = __builtin_amdgcn_sdot4(x.w, y.w, dot, false);
-    }
-    return (float)(na + nb - 2 * dot);
-}
-
 // q = a / b for 0 <= a < 2^31, 1 <= b, via a double reciprocal and one fix-up.
 __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t b, double rcp) {
     uint32_t q = (uint32_t)((double)a * rcp);
@@ -298,16 +281,6 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
 }
 
-__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
-}
-
 void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
@@ -365,88 +338,15 @@ void launch_norms(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_norms, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, v.Xp, v.N, v.dp, v.nrm);
 }
 
-// Exact integer form, input check: one pass over X, block-level reduction,
-// one atomic per block and flag word.
-__global__ __launch_bounds__(256) void k_int_scan(const float* __restrict__ X, int64_t total, uint32_t* flag) {
-    __shared__ int s_lo[4], s_hi[4];
-    __shared__ uint32_t s_bad[4];
-    bool bad = false;
-    int lo = INT_MAX, hi = INT_MIN;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const float x = X[i];
-        if (!(fabsf(x) <= 16777216.f) || x != rintf(x)) {
-            bad = true;
-        } else {
-            const int q = (int)x;
-            lo = min(lo, q);
-            hi = max(hi, q);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o));
-        hi = max(hi, __shfl_xor(hi, o));
-    }
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    const bool wbad = ballot(bad) != 0ull;
-    if (lane == 0) {
-        s_lo[w] = lo;
-        s_hi[w] = hi;
-        s_bad[w] = wbad ? 1u : 0u;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int j = 1; j < 4; ++j) {
-            lo = min(lo, s_lo[j]);
-            hi = max(hi, s_hi[j]);
-        }
-        const uint32_t b = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
-        if (b) atomicOr(&flag[8], 1u);
-        atomicMin(reinterpret_cast<int*>(&flag[9]), min(lo, s_lo[0]));
-        atomicMax(reinterpret_cast<int*>(&flag[10]), max(hi, s_hi[0]));
-    }
-}
-
-void launch_int_scan(const float* X, int64_t total, uint32_t* flag, hipStream_t s) {
-    launch_fill_u32(flag + 8, 0u, 1, s);
-    launch_fill_i32(reinterpret_cast<int32_t*>(flag) + 9, INT_MAX, 1, s);
-    launch_fill_i32(reinterpret_cast<int32_t*>(flag) + 10, INT_MIN, 1, s);
-    hipLaunchKernelGGL(k_int_scan, dim3(grid_for(total, 256 * 16, 2048)), dim3(256), 0, s, X, total, flag);
-}
-
-// int8 rows x' = x - shift (|x'| <= 128 by the host's check), zero padded to
-// dpi, and their int32 squared norms. One wave per row.
-__global__ __launch_bounds__(256) void k_make_i8(Views v, int32_t shift) {
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    for (int p = blockIdx.x * 4 + w; p < v.N; p += gridDim.x * 4) {
-        const float* x = v.Xp + (size_t)p * v.dp;
-        int8_t* y = v.Xi + (size_t)p * v.dpi;
-        int32_t sum = 0;
-        for (int j = 4 * lane; j < v.dpi; j += 256) {
-            uint32_t packed = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = j + q;
-                const int32_t val = c < v.d ? (int32_t)x[c] - shift : 0;
-                sum += val * val;
-                packed |= ((uint32_t)val & 0xffu) << (8 * q);
-            }
-            *reinterpret_cast<uint32_t*>(y + j) = packed;
-        }
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-        if (lane == 0) v.ni[p] = sum;
-    }
-}
-
-void launch_make_i8(const Views& v, int32_t shift, hipStream_t s) {
-    hipLaunchKernelGGL(k_make_i8, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, v, shift);
-}
-
 // ------------------------------------------------------------------ init (a1)
 
 constexpr int kRowWaves = 4;
 
-// 16-byte chunk c of a row as four or eight values, and their dot product
-// with another chunk (FP32 products and sums in a fixed order).
+// Dot product of 8 consecutive dimensions (chunk c of a row) with the same
+// dimensions of another row, FP32 products and sums in dimension order. The
+// FP32 rows (two float4) and the one-plane BF16 rows (one uint4) give the
+// same value whenever the FP32 values are exact in BF16, so a build that
+// reads the plane and one that reads the FP32 rows agree bit for bit.
 __device__ __forceinline__ float chunk_dot(const float4 a, const float4 b, float s) {
     s = fmaf(a.x, b.x, s);
     s = fmaf(a.y, b.y, s);
@@ -454,8 +354,16 @@ __device__ __forceinline__ float chunk_dot(const float4 a, const float4 b, float
     return fmaf(a.w, b.w, s);
 }
 
-__device__ __forceinline__ float chunk_dot(const uint4 a, const uint4 b, float s) {
-    const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+__device__ __forceinline__ float chunk8_dot(const float4* __restrict__ a, const float4* __restrict__ b, int c,
+                                            float s) {
+    s = chunk_dot(a[2 * c], b[2 * c], s);
+    return chunk_dot(a[2 * c + 1], b[2 * c + 1], s);
+}
+
+__device__ __forceinline__ float chunk8_dot(const uint4* __restrict__ a, const uint4* __restrict__ b, int c,
+                                            float s) {
+    const uint4 x = a[c], y = b[c];
+    const uint32_t av[4] = {x.x, x.y, x.z, x.w}, bv[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         s = fmaf(__uint_as_float(av[q] << 16), __uint_as_float(bv[q] << 16), s);
@@ -465,25 +373,25 @@ __device__ __forceinline__ float chunk_dot(const uint4 a, const uint4 b, float s
 }
 
 // Gram-form distances of row u to the K rows pid (lane k < K holds pid of
-// neighbour k), the wave streaming each row: lane l takes 16-byte chunks
-// l, l + 64, ..., four rows at a time; each row's lane sums are added by a
-// fixed xor tree. Returns lane k's distance. T = float4 (FP32 rows) or uint4
-// (one-plane BF16 rows, exact products).
+// neighbour k), the wave streaming each row: lane l takes the 8-dimension
+// chunks l, l + 64, ..., four rows at a time; each row's lane sums are added
+// by a fixed xor tree. Returns lane k's distance. T = float4 (FP32 rows,
+// `stride` = d_pad / 4) or uint4 (one-plane BF16 rows, exact products,
+// `stride` = d_pad / 8); `chunks` = d_pad / 8 either way.
 template <typename T>
-__device__ __forceinline__ float wave_gram_dists(const T* __restrict__ rows, int chunks, int u, uint32_t pid, int K,
-                                                 const float* __restrict__ nrm) {
+__device__ __forceinline__ float wave_gram_dists(const T* __restrict__ rows, int stride, int chunks, int u,
+                                                 uint32_t pid, int K, const float* __restrict__ nrm) {
     const int lane = lane_id();
-    const T* a = rows + (size_t)u * chunks;
+    const T* a = rows + (size_t)u * stride;
     float mine = 0.f;
     for (int k0 = 0; k0 < K; k0 += 4) {
         const T* b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * chunks;
+        for (int q = 0; q < 4; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * stride;
         float s[4] = {0.f, 0.f, 0.f, 0.f};
         for (int c = lane; c < chunks; c += 64) {
-            const T x = a[c];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s[q] = chunk_dot(x, b[q][c], s[q]);
+            for (int q = 0; q < 4; ++q) s[q] = chunk8_dot(a, b[q], c, s[q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -507,15 +415,13 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     float Dg = 0.f;
     if (mode == kDistGram) {   // whole wave
         if (v.Xs && v.planes == 1)
-            Dg = wave_gram_dists(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, u, pid, K, v.nrm);
+            Dg = wave_gram_dists(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, v.dp >> 3, u, pid, K, v.nrm);
         else
-            Dg = wave_gram_dists(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, u, pid, K, v.nrm);
+            Dg = wave_gram_dists(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, v.dp >> 3, u, pid, K, v.nrm);
     }
     if (lane < K) {
         float D;
-        if (mode == kDistInt8) {
-            D = dist_int8(v.Xi + (size_t)u * v.dpi, v.Xi + (size_t)pid * v.dpi, v.dpi, v.ni[u], v.ni[pid]);
-        } else if (mode == kDistGram) {
+        if (mode == kDistGram) {
             D = Dg;
         } else {
             D = dist_direct(v.Xp + (size_t)u * v.dp, v.Xp + (size_t)pid * v.dp, v.dp);
@@ -1734,127 +1640,6 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
         wave_sync();
         emit_clear(el, m);
     }
-}
-
-// Exact integer form of the high-d join: the same tiles as the FP32 kernel
-// above on int8 rows with v_mfma_i32_16x16x64_i8 (int32 accumulation). Lane
-// (c = lane%16, g = lane/16) holds bytes [k0 + 16g, k0 + 16g + 16) of member
-// 16*tile + c; A and B take the same lane-to-k map, so each instruction adds
-// the dot products over 64 dimensions. Rows are fetched several 64-byte steps
-// ahead of the instructions that use them (kI8Ahead steps). Every operation is exact:
-// D = n'_a + n'_b - 2 a'.b' is the exact squared distance.
-typedef int int32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kI8Ahead = 2;   // 64-byte steps loaded before their instructions
-
-__global__ __launch_bounds__(256, 3) void k_join_i8(Views v) {
-    if (stopped(v)) return;
-    __shared__ uint64_t s_thr[kJoinWaves][64];
-    __shared__ uint32_t s_oid[kJoinWaves][64];
-    __shared__ uint32_t s_pos[kJoinWaves][64];
-    __shared__ int32_t s_nrm[kJoinWaves][64];
-    __shared__ uint32_t s_emit[kJoinWaves][3][64];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int C2 = 2 * v.C, dpi = v.dpi, K = v.K;
-    const int c16 = lane & 15, g = lane >> 4;
-    EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
-    emit_clear(el, 64);
-    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
-    for (int u = xr.next; u < xr.end; u += xr.step) {
-        const uint32_t nn = v.nn[u];
-        const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
-        if (nnew == 0) continue;
-        if (m > C2) {   // not a sampled neighbourhood: reported, never read
-            if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 256ull);
-            continue;
-        }
-        const uint2* cs = v.cand + (size_t)u * C2;
-        if (lane < m) {
-            const uint2 c = cs[lane];
-            s_oid[w][lane] = c.x;
-            s_pos[w][lane] = c.y;
-            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
-            s_nrm[w][lane] = v.ni[c.y];
-        }
-        wave_sync();
-        const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
-        // lanes past the last member read member m-1; their outputs are never used
-        const int8_t* rp[kMfmaMaxCT];
-#pragma unroll
-        for (int ct = 0; ct < kMfmaMaxCT; ++ct)
-            rp[ct] = v.Xi + (size_t)s_pos[w][min(ct * 16 + c16, m - 1)] * dpi + g * 16;
-        int32x4 acc[kMfmaMaxCT * (kMfmaMaxCT + 1) / 2];
-#pragma unroll
-        for (int t = 0; t < kMfmaMaxCT * (kMfmaMaxCT + 1) / 2; ++t) acc[t] = int32x4{0, 0, 0, 0};
-        int k0 = 0;
-        for (; k0 + 64 * kI8Ahead <= dpi; k0 += 64 * kI8Ahead) {
-            int32x4 f[kI8Ahead][kMfmaMaxCT];
-#pragma unroll
-            for (int q = 0; q < kI8Ahead; ++q)
-#pragma unroll
-                for (int ct = 0; ct < kMfmaMaxCT; ++ct)
-                    f[q][ct] = ct < CT ? *reinterpret_cast<const int32x4*>(rp[ct] + k0 + 64 * q) : int32x4{0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < kI8Ahead; ++q) {
-                int t = 0;
-#pragma unroll
-                for (int rt = 0; rt < kMfmaMaxCT; ++rt)
-#pragma unroll
-                    for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t)
-                        if (rt < RT && ct < CT)
-                            acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[q][rt], f[q][ct], acc[t], 0, 0, 0);
-            }
-        }
-        for (; k0 < dpi; k0 += 64) {
-            int32x4 f[kMfmaMaxCT];
-#pragma unroll
-            for (int ct = 0; ct < kMfmaMaxCT; ++ct)
-                f[ct] = ct < CT ? *reinterpret_cast<const int32x4*>(rp[ct] + k0) : int32x4{0, 0, 0, 0};
-            int t = 0;
-#pragma unroll
-            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
-#pragma unroll
-                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t)
-                    if (rt < RT && ct < CT) acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[rt], f[ct], acc[t], 0, 0, 0);
-        }
-        // epilogue: as in the FP32 kernel (rows 16rt + 4g + r, column 16ct + c16)
-        for (int pass = 0; pass < 2; ++pass) {
-            int t = 0;
-#pragma unroll
-            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
-#pragma unroll
-                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t) {
-                    if (!(rt < RT && ct < CT)) continue;
-                    const int j = ct * 16 + c16;
-                    if (j >= m) continue;
-                    const uint32_t oj = s_oid[w][j];
-                    const uint64_t tj = s_thr[w][j];
-                    const int32_t nj = s_nrm[w][j];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = rt * 16 + g * 4 + r;
-                        if (i >= nnew || (j < nnew && j <= i)) continue;
-                        const float D = (float)(s_nrm[w][i] + nj - 2 * acc[t][r]);
-                        const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
-                        const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
-                        if (pass == 0) {
-                            if (ki < s_thr[w][i]) emit_count(el, i);
-                            if (kj < tj) emit_count(el, j);
-                        } else {
-                            if (ki < s_thr[w][i]) emit_write(v, el, i, ki);
-                            if (kj < tj) emit_write(v, el, j, kj);
-                        }
-                    }
-                }
-            if (pass == 0) emit_reserve(v, el, s_pos[w], m);
-        }
-        wave_sync();
-        emit_clear(el, m);
-    }
-}
-
-void launch_join_i8(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed(k_join_i8, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
 }
 
 void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -3087,18 +2872,6 @@ __global__ void k_perm_rows_bf16(Views v) {
     }
 }
 
-__global__ void k_perm_rows_i8(Views v) {
-    const int dpi16 = v.dpi >> 4;   // 16-byte groups (dpi % 64 == 0)
-    const int64_t total = (int64_t)v.N * dpi16;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int p = (int)(i / dpi16), c = (int)(i - (int64_t)p * dpi16);
-        const int q = v.newpos[p];
-        if (q < 0 || q >= v.N) continue;  // reported by k_perm_rows
-        reinterpret_cast<uint4*>(v.Xi2 + (size_t)q * v.dpi)[c] = reinterpret_cast<const uint4*>(v.Xi + (size_t)p * v.dpi)[c];
-        if (c == 0) v.ni2[q] = v.ni[p];
-    }
-}
-
 __global__ void k_perm_rows_split(Views v) {
     const int dp8 = v.dp >> 3;   // 16-byte groups per plane row (dp % 32 == 0)
     const int64_t per = (int64_t)v.N * dp8, total = (int64_t)v.planes * per;   // planes in use
@@ -3168,9 +2941,6 @@ void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s) {
     if (v.Xs)
         hipLaunchKernelGGL(k_perm_rows_split, dim3(grid_for(3 * (int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256),
                            0, s, v);
-    if (v.Xi)
-        hipLaunchKernelGGL(k_perm_rows_i8, dim3(grid_for((int64_t)v.N * (v.dpi >> 4), 256, 16384)), dim3(256), 0, s,
-                           v);
 }
 
 void launch_perm_posof(const Views& v, hipStream_t s) {

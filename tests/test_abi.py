@@ -61,7 +61,7 @@ def _params(**kw):
     (100, 784, dict(path=5), "unknown path"),
     (100, 784, dict(path="bf16x3", precision="bf16"), "FP32 MFMA"),
     (100, 784, dict(K=64, rho=1.0, path="bf16x3"), "MFMA"),
-    (100, 784, dict(path="mfma_i8"), "disabled"),
+    (100, 784, dict(path="mfma_i8"), "not available"),
     (100, 8, dict(sampling=2), "unknown sampling"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
@@ -103,7 +103,7 @@ def test_workspace_grows_with_size():
 
 
 def test_integer_form_workspace():
-    """The exact integer form is switched off: AUTO reserves no int8 rows; at
+    """The exact integer form is withdrawn: AUTO reserves no int8 rows; at
     high d it reserves the three BF16 planes of the split form (3 * N * dp * 2
     bytes, dp = round_up(d, 32)) on top of the FP32 MFMA layout."""
     import paper_2112_06630_amd as knng

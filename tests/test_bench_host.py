@@ -60,3 +60,29 @@ def test_counter_summary_scaling_and_early_exits(tmp_path, monkeypatch):
 def test_traffic_file_names():
     assert bench.traffic_path("image60k_d784").endswith(os.path.join("profiles", "traffic.json"))
     assert bench.traffic_path("blobs4m_d3").endswith(os.path.join("profiles", "traffic_blobs4m_d3.json"))
+
+
+def test_join_roofline_byte_model():
+    """Algorithmic join bytes: FP32 rows (4 d_pad) + 8 B sample entry per
+    member gathered, 8 B per proposal; the encoding figure prices the rows the
+    kernel reads (2 d_pad per split plane) plus 20 B of member metadata."""
+    class K:
+        PATH_VALU, PATH_MFMA, PATH_MFMA_BF16X3 = 1, 2, 4
+    w = {"d": 784, "workload": "none"}
+    s0 = {"path": 4, "dpad": 800, "planes": 1, "iters": 2, "proposals": [100, 50], "evals": [1000, 500]}
+    stats = [{"join_ms": [0.001, 0.001]}]
+    members = [10_000, 20_000]
+    r = bench.join_roofline(K, w, s0, stats, members, "fp32")
+    alg = 10_000 * (3200 + 8) + 800 + 20_000 * (3200 + 8) + 400
+    assert r["kernel"] == "k_join_split"
+    assert r["bytes_per_launch"] == alg // 2
+    assert r["achieved"] == round(alg / 2e-6 / 1e9, 1)
+    assert r["frac"] == round(r["achieved"] / 8000.0, 4)
+    enc = 10_000 * (1600 + 20) + 800 + 20_000 * (1600 + 20) + 400
+    assert r["encoding"]["bytes_per_launch"] == enc // 2 and r["encoding"]["row_bytes"] == 1600
+    assert r["frac"] > 1 and "encoding" in r["note"]
+    assert r["mfma"]["flops_per_launch"] == (1000 + 500) * 2 * 784 // 2
+    s0["path"] = 1
+    s0["dpad"] = 4
+    r = bench.join_roofline(K, {"d": 3, "workload": "none"}, s0, stats, members, "fp32")
+    assert r["kernel"] == "k_join_valu" and r["encoding"]["row_bytes"] == 16 and "note" not in r

@@ -75,6 +75,32 @@ def test_batch_integer_data_matches_oracle(knng, tuning):
     b.close()
 
 
+def test_batch_bf16_exact_noninteger_matches_single(knng):
+    """Values exact in BF16 but not integers (8-bit mantissas over eleven
+    binades), so FP32 sums round: a single build reads the one BF16 plane
+    that holds them, the batch the FP32 rows; both sum every dot product in
+    the same dimension order, so the graphs agree bit for bit."""
+    rng = np.random.default_rng(21)
+    data = []
+    for n, d, s in zip([400, 900, 650, 300], [64, 64, 128, 128], [5, 6, 7, 8]):
+        m = rng.integers(128, 256, (n, d)).astype(np.float64)
+        e = rng.integers(-10, 1, (n, d)).astype(np.float64)
+        X = (m * 2.0 ** e * rng.choice([-1.0, 1.0], (n, d))).astype(np.float32)
+        X[: n // 2, : d // 4] *= np.float32(8.0)   # two coarse groups (a power of two keeps BF16 exactness)
+        data.append((X, s))
+    Xs = [dev(X) for X, _ in data]
+    b = knng.Batch(Xs, [s for _, s in data], 12, 1.0, 0.001, 20, tuning="64:bf16x3,128:bf16x3")
+    b.execute()
+    b.synchronize()
+    st = b.stats()
+    for i, (X, s) in enumerate(data):
+        ids, dists, ss = knng.build(Xs[i], 12, 1.0, 0.001, 20, s, path="bf16x3")
+        assert ss["planes"] == 1
+        assert torch.equal(b.ids[i], ids) and torch.equal(b.dists[i], dists), i
+        assert st["evals"][i] == ss["evals"] and st["changes"][i] == ss["changes"]
+    b.close()
+
+
 def test_batch_graph_replays(knng):
     """Captured graph, replayed three times with eager work in between: every
     replay must equal the eager execution."""

@@ -14,10 +14,10 @@ from parity import check_rows, fp32_bound
 
 pytestmark = pytest.mark.gpu
 
-# The exact integer form (int8 MFMA) is switched off in the library: its first
+# The exact integer form (int8 MFMA) was withdrawn from the library: its first
 # GPU run ended in a device fault whose cause has not been found, so its
 # tests stay skipped until one is.
-I8_OFF = pytest.mark.skip(reason="exact integer form switched off (unresolved device fault)")
+I8_OFF = pytest.mark.skip(reason="exact integer form withdrawn (unresolved device fault)")
 
 
 @pytest.fixture(scope="module")

@@ -174,7 +174,7 @@ def member_counts_and_graphs(X, w, args, iters, keep_graphs):
     the join (sum over owners with a new member of n_new + n_old) and, if
     asked, the graph G_t."""
     import paper_2112_06630_amd as knng
-    ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+    ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
                        path=args.path, precision=args.precision, sampling=args.sampling)
     ctx.init()
     members, graphs = [], []
@@ -362,7 +362,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--reorder", type=int, default=0)
+    ap.add_argument("--reorder", type=int, default=0,
+                    help="graph-ordered permutation once after iteration t_p (0: off)")
     ap.add_argument("--workload", default="image60k_d784", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "bf16x3"])
@@ -484,12 +485,12 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
     Xnp = w["gen"]()
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
-    p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+    p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
                          path=args.path, precision=args.precision, sampling=args.sampling)
     ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
     ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
     dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
-    run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], bool(args.reorder),
+    run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
                              path=args.path, workspace=ws, out=(ids, dists), precision=args.precision,
                              sampling=args.sampling)
     for _ in range(warmup):
@@ -573,7 +574,7 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
         "data": "synthetic",
         "config": {"workload": w["workload"], "N": w["N"], "d": w["d"], "K": w["K"], "rho": w["rho"],
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
-                   "reorder": bool(args.reorder),
+                   "reorder": int(args.reorder),
                    "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
                    "precision": args.precision, "sampling": args.sampling},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "recall_plain": rec_plain,

@@ -77,6 +77,17 @@ typedef enum {
  * x2 = 0 (values exact in BF16, such as 8-bit pixels), the join reads only the
  * planes that are not all zero and skips the products that are exactly zero:
  * the result is bit-identical to the three-plane evaluation (stats.planes).
+ *
+ * Accuracy of the matrix forms. On data whose FP32 sums are all exact
+ * (integers with every squared norm at most 2^23, such as 8-bit pixels) the
+ * tiles accumulate in FP32 and every distance is exact. On other data the
+ * FP32 Gram form loses accuracy relative to the distance when the points sit
+ * far from the origin (its rounding scales with ||x||^2 + ||y||^2), so the
+ * matrix forms then keep FP64 squared norms, take each 32-dimension step's
+ * MFMA partial dot product into an FP64 accumulator and form
+ * ||x||^2 + ||y||^2 - 2 x.y in FP64 before rounding the distance to FP32
+ * (stats.accurate = 1). Both ways a pair gets the same value whichever side
+ * of a tile it is on.
  */
 typedef enum {
     KNNG_PATH_AUTO = 0,         /* see above */
@@ -116,7 +127,8 @@ typedef struct {
     int32_t max_iters;  /* iteration cap T_max >= 0; 0 returns the random initial graph */
     uint64_t seed;      /* seed of the counter-based hash */
     int32_t precision;  /* knng_precision */
-    int32_t reorder;    /* 1: graph-ordered point permutation after iteration 1 (Sec. 3.2) */
+    int32_t reorder;    /* t_p >= 1: graph-ordered point permutation once, after iteration t_p
+                           (Sec. 3.2 applies it after the first); 0: off; at most 64 */
     int32_t path;       /* knng_path */
     int32_t sampling;   /* knng_sampling (Sec. 3.1) */
 } knng_params;
@@ -132,6 +144,10 @@ typedef struct {
     int32_t dpad;                         /* padded row length in floats */
     int32_t precision;                    /* knng_precision used */
     int32_t planes;                       /* split-BF16 form: BF16 planes the join reads (1..3), else 0 */
+    int32_t accurate;                     /* matrix paths: 1 when FP32 sums of X are not exact (see
+                                             knng_path), so dot products are summed in FP64 per
+                                             32 dimensions; 0 where every FP32 sum is exact */
+    int32_t reserved;
     int64_t evals[KNNG_MAX_ITERS];        /* e_t: distance evaluations of iteration t */
     int64_t changes[KNNG_MAX_ITERS];      /* c_t: ids that entered a list */
     int64_t proposals[KNNG_MAX_ITERS];    /* proposals that passed the snapshot filter */
@@ -181,7 +197,7 @@ knng_status knng_init_graph(knng_ctx* ctx);
 knng_status knng_load_graph(knng_ctx* ctx, const int32_t* d_ids, const uint8_t* d_flags, int32_t t);
 
 /* One synchronous iteration t+1: sample (Sec. 3.1), local join (Sec. 2,
- * Sec. 3.3), merge. Applies the permutation after iteration 1 when
+ * Sec. 3.3), merge. Applies the permutation after iteration t_p when
  * params.reorder is set. Synchronises `stream` once. Writes e_t and c_t
  * (host, nullable). */
 knng_status knng_iterate(knng_ctx* ctx, int64_t* evals, int64_t* changes);

@@ -171,6 +171,23 @@ def sample(state: State, K: int, C: int, seed: int, t: int, sampling: str = "wei
                   [cold[u, :nold[u]].copy() for u in range(N)], f2)
 
 
+def sample_arrays(state: State, K: int, C: int, seed: int, t: int, sampling: str = "weighted"):
+    """The sampling step as arrays (large inputs): cnew, cold [N, C] (ids of
+    the sampled members, the first nnew / nold of each row valid), nnew,
+    nold [N] and the flags after the flip [N, K]."""
+    N = state.ids.shape[0]
+    cnew = np.full((N, C), -1, np.int32)
+    cold = np.full((N, C), -1, np.int32)
+    nnew = np.empty(N, np.int32)
+    nold = np.empty(N, np.int32)
+    f2 = np.empty((N, K), np.uint8)
+    ids = np.ascontiguousarray(state.ids, np.int32)
+    fl = np.ascontiguousarray(state.flags, np.uint8)
+    _check(_load().orc_sample(_ptr(ids), _ptr(fl), N, K, C, seed, t, _ptr(cnew), _ptr(nnew),
+                              _ptr(cold), _ptr(nold), _ptr(f2), _mode(sampling)), "sample")
+    return cnew, nnew, cold, nold, f2
+
+
 def join_merge(X, state: State, smp: Sample, K: int, C: int) -> tuple[State, int, int]:
     """Join and merge (Sec. 2 calculation step) of one iteration on the sampled
     sets ``smp`` of ``state`` (its flags replaced by ``smp.flags``, the flags

@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("dpad", ctypes.c_int32), ("precision", ctypes.c_int32), ("planes", ctypes.c_int32),
+                ("accurate", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("evals", ctypes.c_int64 * MAX_ITERS), ("changes", ctypes.c_int64 * MAX_ITERS),
                 ("proposals", ctypes.c_int64 * MAX_ITERS), ("rescored", ctypes.c_int64 * MAX_ITERS),
                 ("iter_ms", ctypes.c_float * MAX_ITERS), ("sample_ms", ctypes.c_float * MAX_ITERS),
@@ -105,13 +106,14 @@ _PRECISIONS = {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16_SCREEN}
 
 
 def make_params(K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
-                reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32",
+                reorder: bool | int = False, path: str | int = "auto", precision: str | int = "fp32",
                 sampling: str | int = "weighted") -> Params:
     pth = _PATHS[path] if isinstance(path, str) else int(path)
     prc = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     smp = _SAMPLING[sampling] if isinstance(sampling, str) else int(sampling)
+    # reorder: False/0 off, True/1 after iteration 1, an int t_p after iteration t_p
     return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, prc,
-                  1 if reorder else 0, pth, smp)
+                  int(reorder), pth, smp)
 
 
 def sample_cap(K: int, rho: float) -> int:
@@ -139,7 +141,7 @@ def _check_x(X: torch.Tensor):
 def _stats_dict(s: _Stats) -> dict:
     it = s.iters
     return dict(iters=it, converged=bool(s.converged), path=s.path, dpad=s.dpad, precision=s.precision,
-                planes=s.planes,
+                planes=s.planes, accurate=s.accurate,
                 evals=list(s.evals[:it]), changes=list(s.changes[:it]), proposals=list(s.proposals[:it]),
                 rescored=list(s.rescored[:it]),
                 iter_ms=list(s.iter_ms[:it]), sample_ms=list(s.sample_ms[:it]), join_ms=list(s.join_ms[:it]),
@@ -148,7 +150,7 @@ def _stats_dict(s: _Stats) -> dict:
 
 
 def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
-          reorder: bool = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
+          reorder: bool | int = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
           out: tuple | None = None, precision: str | int = "fp32", sampling: str | int = "weighted"):
     """K-NN graph of the rows of X (device float32 [N, d]).
 
@@ -185,7 +187,7 @@ class Context:
     """Step API: one build whose state lives in a caller-held workspace."""
 
     def __init__(self, X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
-                 seed: int = 0, reorder: bool = False, path: str | int = "auto", precision: str | int = "fp32",
+                 seed: int = 0, reorder: bool | int = False, path: str | int = "auto", precision: str | int = "fp32",
                  sampling: str | int = "weighted"):
         _check_x(X)
         self.X = X

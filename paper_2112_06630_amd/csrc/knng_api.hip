@@ -67,7 +67,7 @@ struct Plan {
     int64_t pmax;    // proposal slots
     size_t total;
     // byte offsets
-    size_t o_Xp, o_nrm, o_orig, o_posof, o_lkey, o_lpos, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
+    size_t o_Xp, o_nrm, o_nrm64, o_nrm64_2, o_orig, o_posof, o_lkey, o_lpos, o_kth, o_kth2, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
         o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp;
 };
@@ -84,6 +84,7 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
         return fail(KNNG_EINVAL, "max_iters must be in [0, 64]");
     if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_BF16X3) return fail(KNNG_EINVAL, "unknown path");
+    if (p->reorder < 0 || p->reorder > KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "reorder must be in [0, 64]");
     if (p->sampling != KNNG_SAMPLING_WEIGHTED && p->sampling != KNNG_SAMPLING_TURBO)
         return fail(KNNG_EINVAL, "unknown sampling rule");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
@@ -142,10 +143,12 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     const size_t NK = (size_t)N * K;
     P.o_Xp = take((size_t)N * P.dp * 4);
     P.o_nrm = take((size_t)N * 4);
+    P.o_nrm64 = path != KNNG_PATH_VALU ? take((size_t)N * 8) : 0;
     P.o_orig = take((size_t)N * 4);
     P.o_posof = take((size_t)N * 4);
     P.o_lkey = take(NK * 8);
     P.o_lpos = take(NK * 4);
+    P.o_kth = take((size_t)N * 8);
     P.o_cnt4 = take((size_t)N * 4 * 4);   // rdeg, rcur, cap, pcnt: one fill
     P.o_roff = take(((size_t)N + 1) * 4);
     P.o_rev = take(NK * 16);
@@ -182,8 +185,10 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
         P.o_newpos = take((size_t)N * 4);
         P.o_lkey2 = take(NK * 8);
         P.o_lpos2 = take(NK * 4);
+        P.o_kth2 = take((size_t)N * 8);
         P.o_Xp2 = take((size_t)N * P.dp * 4);
         P.o_nrm2 = take((size_t)N * 4);
+        P.o_nrm64_2 = path != KNNG_PATH_VALU ? take((size_t)N * 8) : 0;
         P.o_orig2 = take((size_t)N * 4);
     }
     // counting-sort reverse bucketing: super-buckets of 2^shift positions, at
@@ -226,10 +231,12 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.turbo = P.turbo;
     v.Xp = reinterpret_cast<float*>(b + P.o_Xp);
     v.nrm = reinterpret_cast<float*>(b + P.o_nrm);
+    if (P.path != KNNG_PATH_VALU) v.nrm64 = reinterpret_cast<double*>(b + P.o_nrm64);
     v.orig = reinterpret_cast<int32_t*>(b + P.o_orig);
     v.posof = reinterpret_cast<int32_t*>(b + P.o_posof);
     v.lkey = reinterpret_cast<uint64_t*>(b + P.o_lkey);
     v.lpos = reinterpret_cast<uint32_t*>(b + P.o_lpos);
+    v.kth = reinterpret_cast<uint64_t*>(b + P.o_kth);
     uint32_t* c4 = reinterpret_cast<uint32_t*>(b + P.o_cnt4);
     v.rdeg = c4;
     v.rcur = c4 + N;
@@ -266,8 +273,10 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
         v.newpos = reinterpret_cast<int32_t*>(b + P.o_newpos);
         v.lkey2 = reinterpret_cast<uint64_t*>(b + P.o_lkey2);
         v.lpos2 = reinterpret_cast<uint32_t*>(b + P.o_lpos2);
+        v.kth2 = reinterpret_cast<uint64_t*>(b + P.o_kth2);
         v.Xp2 = reinterpret_cast<float*>(b + P.o_Xp2);
         v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
+        if (P.path != KNNG_PATH_VALU) v.nrm64_2 = reinterpret_cast<double*>(b + P.o_nrm64_2);
         v.orig2 = reinterpret_cast<int32_t*>(b + P.o_orig2);
     }
     v.planes = 3;   // until the create-time count (single builds)
@@ -384,13 +393,16 @@ knng_status do_permute(knng_ctx* c) {
     launch_perm_finish(v, fl[2], s);
     std::swap(v.Xp, v.Xp2);
     std::swap(v.nrm, v.nrm2);
+    std::swap(v.nrm64, v.nrm64_2);
     std::swap(v.orig, v.orig2);
     std::swap(v.lkey, v.lkey2);
     std::swap(v.lpos, v.lpos2);
+    std::swap(v.kth, v.kth2);
     std::swap(v.Xb, v.Xb2);
     std::swap(v.nb, v.nb2);
     if (v.Xs) std::swap(v.Xs, v.Xs2);
     launch_perm_posof(v, s);
+    v.permuted = 1;
     HIP_TRY(hipEventRecord(c->ev[5], s));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
@@ -476,7 +488,8 @@ knng_status finish_iteration(knng_ctx* c, int t, int64_t* evals, int64_t* change
     return KNNG_OK;
 }
 
-bool permute_after(const knng_ctx* c, int t) { return t == 1 && c->p.reorder && !c->permuted; }
+// params.reorder = t_p >= 1: the permutation runs once, after iteration t_p
+bool permute_after(const knng_ctx* c, int t) { return c->p.reorder > 0 && t == c->p.reorder && !c->permuted; }
 
 // One iteration, host-driven (step API): no look-ahead.
 knng_status do_iterate(knng_ctx* c, int64_t* evals, int64_t* changes) {
@@ -567,6 +580,11 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     if (c->hc[kCntNonFinite]) {
         knng_destroy(c);
         return fail(KNNG_EINVAL, "X holds a NaN or an infinity");
+    }
+    if (P.path != KNNG_PATH_VALU && !P.bf16) {
+        // FP32 Gram sums are exact only for integers with squared norms <= 2^23
+        c->v.acc = (c->hc[kCntSplit] & kLayoutInexact) ? 1 : 0;
+        c->stats.accurate = c->v.acc;
     }
     if (P.split) {
         const uint64_t used = c->hc[kCntSplit];
@@ -872,6 +890,10 @@ knng_status batch_upload(knng_batch* b, hipStream_t s) {
         g.v = carve(g.plan, g.N, g.d, b->p.K, base);
         char* tb = base + g.tables_off;
         Views& v = g.v;
+        // matrix paths: FP64 accumulation for every group (on data whose FP32
+        // sums are exact it gives the same values as FP32, so every dataset
+        // matches its single build either way)
+        v.acc = g.path != KNNG_PATH_VALU ? 1 : 0;
         v.nds = nds;
         v.ds = reinterpret_cast<uint32_t*>(tb + L.ds);
         v.dsbase = reinterpret_cast<uint32_t*>(tb + L.dsbase);

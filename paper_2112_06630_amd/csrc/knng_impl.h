@@ -11,6 +11,8 @@ constexpr uint32_t kPosMask = 0x7fffffffu;
 constexpr uint32_t kPosUnknown = 0xffffffffu;  // merge: NEW entry whose position is found from its id
 constexpr int kWave = 64;
 constexpr int kSelectStage = 512;           // pool entries a select wave stages in LDS
+// layout-pass bits (counter kCntSplit) that make FP32 Gram sums inexact
+constexpr uint64_t kLayoutInexact = 4u | 8u;
 
 // Device counters of one iteration (uint64 slots).
 enum Counter : int {
@@ -19,7 +21,8 @@ enum Counter : int {
     kCntPairs2 = 2,      // 2 * e_t
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
-    kCntSplit = 5,       // split-BF16 copies: bit 0 some x2 != 0, bit 1 some x3 != 0
+    kCntSplit = 5,       // layout pass: bit 0 some x2 != 0, bit 1 some x3 != 0 (split-BF16 copies),
+                         // bit 2 some value is not an integer, bit 3 some squared norm exceeds 2^23
     kCntHubs = 6,        // targets whose proposal bucket is merged by a workgroup
     kCntRescored = 7,    // precision form: pairs that passed the BF16 screen and were rescored
     kNumCounters = 8
@@ -37,15 +40,20 @@ struct Views {
     int N, d, dp, K, C;
     int turbo;          // 1: turbosampling coin in the sampling step (Sec. 3.1)
     float* Xp;          // [N, dp] rows in position order, zero padded
-    float* nrm;         // [N] squared norms (Gram path)
+    float* nrm;         // [N] squared norms (Gram path), FP32
+    double* nrm64;      // [N] squared norms in FP64 (Gram path)
+    int acc;            // Gram path: 1 = FP64 accumulation per 32 dimensions (FP32 sums of X not exact)
     uint16_t* Xb;       // [N, dp] BF16 copies of the rows (precision form), else null
     float2* nb;         // [N] BF16 rows: {squared norm, norm of the rounding error bf16(x) - x}
     uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
     int planes;         // split form: leading planes the join reads (1..3; the rest are all zero)
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
+    int permuted;       // 0 until the graph-ordered permutation ran: position = original id
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
     uint32_t* lpos;     // [N, K] position of the neighbour | kNewBit
+    uint64_t* kth;      // [N] the list's K-th key (lkey[p, K-1]), written with the list: the joins'
+                        // snapshot filter reads 8 bytes per member instead of a line of its list
     uint32_t* rdeg;     // [N] reverse in-degree
     uint32_t* roff;     // [N + 1] reverse bucket offsets
     uint32_t* rcur;     // [N] reverse bucket cursors
@@ -97,8 +105,10 @@ struct Views {
     int32_t* newpos;    // [N]
     uint64_t* lkey2;    // [N, K] permuted copies (swapped with the originals)
     uint32_t* lpos2;    // [N, K]
+    uint64_t* kth2;     // [N]
     float* Xp2;         // [N, dp]
     float* nrm2;        // [N]
+    double* nrm64_2;    // [N]
     uint16_t* Xb2;      // [N, dp]
     float2* nb2;        // [N]
     uint16_t* Xs2;      // [3, N, dp]

@@ -313,29 +313,33 @@ void launch_pad_rows(const float* X, const Views& v, hipStream_t s) {
 }
 
 // Squared norms of padded rows, one wave per row, in the order k_prep uses
-// (lane sums over j mod 4, then a fixed xor tree): one value per row
+// (FP64 lane sums over j mod 4, then a fixed xor tree): one value per row
 // whichever kernel laid the rows out.
-__global__ __launch_bounds__(256) void k_norms(const float* __restrict__ Xp, int N, int dp, float* __restrict__ nrm) {
+__global__ __launch_bounds__(256) void k_norms(const float* __restrict__ Xp, int N, int dp, float* __restrict__ nrm,
+                                               double* __restrict__ nrm64) {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     for (int r = blockIdx.x * 4 + w; r < N; r += gridDim.x * 4) {
         const float* y = Xp + (size_t)r * dp;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int j = 4 * lane; j < dp; j += 256) {
             const float4 q = *reinterpret_cast<const float4*>(y + j);
-            s0 = fmaf(q.x, q.x, s0);
-            s1 = fmaf(q.y, q.y, s1);
-            s2 = fmaf(q.z, q.z, s2);
-            s3 = fmaf(q.w, q.w, s3);
+            s0 = fma((double)q.x, (double)q.x, s0);
+            s1 = fma((double)q.y, (double)q.y, s1);
+            s2 = fma((double)q.z, (double)q.z, s2);
+            s3 = fma((double)q.w, (double)q.w, s3);
         }
-        float sn = (s0 + s1) + (s2 + s3);
+        double sn = (s0 + s1) + (s2 + s3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o);
-        if (lane == 0) nrm[r] = sn;
+        if (lane == 0) {
+            nrm64[r] = sn;
+            nrm[r] = (float)sn;
+        }
     }
 }
 
 void launch_norms(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_norms, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, v.Xp, v.N, v.dp, v.nrm);
+    hipLaunchKernelGGL(k_norms, dim3(grid_for(v.N, 4, 16384)), dim3(256), 0, s, v.Xp, v.N, v.dp, v.nrm, v.nrm64);
 }
 
 // ------------------------------------------------------------------ init (a1)
@@ -406,6 +410,61 @@ __device__ __forceinline__ float wave_gram_dists(const T* __restrict__ rows, int
     return mine;
 }
 
+// The same distances with FP64 products and sums and FP64 norms, rounded to
+// FP32 once (data whose FP32 Gram sums are not exact).
+__device__ __forceinline__ double chunk8_dot64(const float4* __restrict__ a, const float4* __restrict__ b, int c,
+                                               double s) {
+    const float4 x0 = a[2 * c], y0 = b[2 * c], x1 = a[2 * c + 1], y1 = b[2 * c + 1];
+    s = fma((double)x0.x, (double)y0.x, s);
+    s = fma((double)x0.y, (double)y0.y, s);
+    s = fma((double)x0.z, (double)y0.z, s);
+    s = fma((double)x0.w, (double)y0.w, s);
+    s = fma((double)x1.x, (double)y1.x, s);
+    s = fma((double)x1.y, (double)y1.y, s);
+    s = fma((double)x1.z, (double)y1.z, s);
+    return fma((double)x1.w, (double)y1.w, s);
+}
+
+__device__ __forceinline__ double chunk8_dot64(const uint4* __restrict__ a, const uint4* __restrict__ b, int c,
+                                               double s) {
+    const uint4 x = a[c], y = b[c];
+    const uint32_t av[4] = {x.x, x.y, x.z, x.w}, bv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s = fma((double)__uint_as_float(av[q] << 16), (double)__uint_as_float(bv[q] << 16), s);
+        s = fma((double)__uint_as_float(av[q] & 0xffff0000u), (double)__uint_as_float(bv[q] & 0xffff0000u), s);
+    }
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ float wave_gram_dists64(const T* __restrict__ rows, int stride, int chunks, int u,
+                                                   uint32_t pid, int K, const double* __restrict__ nrm64) {
+    const int lane = lane_id();
+    const T* a = rows + (size_t)u * stride;
+    float mine = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const T* b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * stride;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = lane; c < chunks; c += 64) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = chunk8_dot64(a, b[q], c, s[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o);
+            if (lane == k0 + q) {
+                const float D = (float)((nrm64[u] + nrm64[pid]) - 2.0 * s[q]);
+                mine = D > 0.f ? D : 0.f;
+            }
+        }
+    }
+    return mine;
+}
+
 // Lanes < K hold one entry each (position `pid` of the neighbour, NEW flag in
 // pf). Computes D against row u, ranks the K keys and writes the sorted row.
 __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, uint32_t pf, int mode) {
@@ -414,7 +473,12 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     uint64_t key = ~0ull;
     float Dg = 0.f;
     if (mode == kDistGram) {   // whole wave
-        if (v.Xs && v.planes == 1)
+        const bool plane = v.Xs && v.planes == 1;
+        if (v.acc && plane)
+            Dg = wave_gram_dists64(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, v.dp >> 3, u, pid, K, v.nrm64);
+        else if (v.acc)
+            Dg = wave_gram_dists64(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, v.dp >> 3, u, pid, K, v.nrm64);
+        else if (plane)
             Dg = wave_gram_dists(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, v.dp >> 3, u, pid, K, v.nrm);
         else
             Dg = wave_gram_dists(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, v.dp >> 3, u, pid, K, v.nrm);
@@ -433,6 +497,7 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     if (lane < K) {
         v.lkey[(size_t)u * K + rank] = key;
         v.lpos[(size_t)u * K + rank] = pid | pf;
+        if (rank == K - 1) v.kth[u] = key;
     }
 }
 
@@ -1470,7 +1535,7 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
     if (stopped(v)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int C2 = 2 * v.C, dp = v.dp, dp4 = dp >> 2, K = v.K;
+    const int C2 = 2 * v.C, dp = v.dp, dp4 = dp >> 2;
     const double rdp4 = 1.0 / dp4;
     unsigned char* base = smem + (size_t)w * join_valu_wave_bytes(v);
     float* rows = reinterpret_cast<float*>(base);
@@ -1493,7 +1558,7 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
             const uint2 c = cs[i];
             oid[i] = c.x;
             opos[i] = c.y;
-            thr[i] = v.lkey[(size_t)c.y * K + K - 1];
+            thr[i] = v.kth[c.y];
         }
         wave_sync();
         for (int idx = lane; idx < m * dp4; idx += 64) {
@@ -1541,15 +1606,20 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaMaxCT = 4;   // m = 2C <= 64
 
+// Acc: as in the split form, partial dot products of 16 dimensions (four
+// instructions from zero) are added to FP64 accumulators and the distance is
+// formed in FP64.
+template <bool Acc>
 __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
     if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
     __shared__ float s_nrm[kJoinWaves][64];
+    __shared__ double s_n64[kJoinWaves][Acc ? 64 : 1];
     __shared__ uint32_t s_emit[kJoinWaves][3][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int C2 = 2 * v.C, dp = v.dp, K = v.K;
+    const int C2 = 2 * v.C, dp = v.dp;
     const int c16 = lane & 15, g = lane >> 4;
     EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
     emit_clear(el, 64);
@@ -1567,8 +1637,11 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
             const uint2 c = cs[lane];
             s_oid[w][lane] = c.x;
             s_pos[w][lane] = c.y;
-            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
-            s_nrm[w][lane] = v.nrm[c.y];
+            s_thr[w][lane] = v.kth[c.y];
+            if constexpr (Acc)
+                s_n64[w][lane] = v.nrm64[c.y];
+            else
+                s_nrm[w][lane] = v.nrm[c.y];
         }
         wave_sync();
         const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
@@ -1579,8 +1652,16 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
             rv[ct] = ct < CT && j < m;
             rp[ct] = v.Xp + (size_t)(rv[ct] ? s_pos[w][j] : 0u) * dp + g * 8;
         }
-        floatx4 acc[kMfmaMaxCT * (kMfmaMaxCT + 1) / 2];
-        for (int t = 0; t < kMfmaMaxCT * (kMfmaMaxCT + 1) / 2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        constexpr int kTiles = kMfmaMaxCT * (kMfmaMaxCT + 1) / 2;
+        floatx4 acc[kTiles];
+        double a64[Acc ? kTiles : 1][4];
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t) {
+            acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (Acc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a64[t][r] = 0.0;
+        }
         for (int k0 = 0; k0 < dp; k0 += 32) {
             float f[kMfmaMaxCT][8];
             for (int ct = 0; ct < kMfmaMaxCT; ++ct) {
@@ -1602,6 +1683,20 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
                     for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t)
                         if (rt < RT && ct < CT)
                             acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[rt][q], f[ct][q], acc[t], 0, 0, 0);
+                if constexpr (Acc) {
+                    if (q == 3 || q == 7) {
+                        int t2 = 0;
+#pragma unroll
+                        for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+#pragma unroll
+                            for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t2) {
+                                if (!(rt < RT && ct < CT)) continue;
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) a64[t2][r] += (double)acc[t2][r];
+                                acc[t2] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            }
+                    }
+                }
             }
         }
         // epilogue: lane holds rows 16rt + 4g + r, column 16ct + c16 of tile t;
@@ -1617,12 +1712,17 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
                     if (j >= m) continue;
                     const uint32_t oj = s_oid[w][j];
                     const uint64_t tj = s_thr[w][j];
-                    const float nj = s_nrm[w][j];
+                    const float nj = Acc ? 0.f : s_nrm[w][j];
+                    const double nj64 = Acc ? s_n64[w][j] : 0.0;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int i = rt * 16 + g * 4 + r;
                         if (i >= nnew || (j < nnew && j <= i)) continue;
-                        float D = (s_nrm[w][i] + nj) - 2.0f * acc[t][r];
+                        float D;
+                        if constexpr (Acc)
+                            D = (float)((s_n64[w][i] + nj64) - 2.0 * a64[t][r]);
+                        else
+                            D = (s_nrm[w][i] + nj) - 2.0f * acc[t][r];
                         D = D > 0.f ? D : 0.f;
                         const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
                         const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
@@ -1643,7 +1743,11 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
 }
 
 void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed(k_join_mfma, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
+    const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
+    if (v.acc)
+        launch_timed(k_join_mfma<true>, g, dim3(256), 0, s, e0, e1, v);
+    else
+        launch_timed(k_join_mfma<false>, g, dim3(256), 0, s, e0, e1, v);
 }
 
 // ------------------------------------------------------------------ precision form (a9)
@@ -1757,7 +1861,7 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     __shared__ uint32_t s_surv[kJoinWaves][kBfMaxSurv];   // survivors: i | j << 8 | directions << 16
     __shared__ float s_sd[kJoinWaves][kBfMaxSurv];        // their rescored FP32 distances
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int C2 = 2 * v.C, dp = v.dp, K = v.K;
+    const int C2 = 2 * v.C, dp = v.dp;
     const int c16 = lane & 15, g = lane >> 4;
     EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
     emit_clear(el, 64);
@@ -1777,7 +1881,7 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
             const uint2 c = cs[lane];
             s_oid[w][lane] = c.x;
             s_pos[w][lane] = c.y;
-            const uint64_t thr = v.lkey[(size_t)c.y * K + K - 1];
+            const uint64_t thr = v.kth[c.y];
             const float2 nb = v.nb[c.y];
             s_thr[w][lane] = thr;
             s_nb[w][lane] = nb.x;
@@ -1957,7 +2061,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
     for (int r = blockIdx.x * 4 + w; r < v.N; r += gridDim.x * 4) {
         const float* x = X + (size_t)r * d;
         float* y = v.Xp + (size_t)r * dp;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int j = 4 * lane; j < dp; j += 256) {
             float4 q;
             q.x = j < d ? x[j] : 0.f;
@@ -1968,10 +2072,12 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
                    (__float_as_uint(q.y) & 0x7f800000u) == 0x7f800000u ||
                    (__float_as_uint(q.z) & 0x7f800000u) == 0x7f800000u ||
                    (__float_as_uint(q.w) & 0x7f800000u) == 0x7f800000u;
-            s0 = fmaf(q.x, q.x, s0);
-            s1 = fmaf(q.y, q.y, s1);
-            s2 = fmaf(q.z, q.z, s2);
-            s3 = fmaf(q.w, q.w, s3);
+            // squares exact in FP64; integrality decides whether FP32 Gram sums are exact
+            s0 = fma((double)q.x, (double)q.x, s0);
+            s1 = fma((double)q.y, (double)q.y, s1);
+            s2 = fma((double)q.z, (double)q.z, s2);
+            s3 = fma((double)q.w, (double)q.w, s3);
+            if (q.x != rintf(q.x) || q.y != rintf(q.y) || q.z != rintf(q.z) || q.w != rintf(q.w)) used |= 4u;
             if (split) {
                 const float e[4] = {q.x, q.y, q.z, q.w};
                 uint16_t b1[4];
@@ -1989,18 +2095,21 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
                 *reinterpret_cast<float4*>(y + j) = q;
             }
         }
-        float sn = (s0 + s1) + (s2 + s3);
+        double sn = (s0 + s1) + (s2 + s3);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o);
+        if (sn > 8388608.0) used |= 8u;   // above 2^23: n(x) + n(y) may round in FP32
         if (lane == 0) {
-            v.nrm[r] = sn;
+            v.nrm64[r] = sn;
+            v.nrm[r] = (float)sn;
             v.orig[r] = r;
             v.posof[r] = r;
         }
     }
     const uint64_t m1 = ballot((used & 1u) != 0), m2 = ballot((used & 2u) != 0), mb = ballot(bad);
+    const uint64_t m4 = ballot((used & 4u) != 0), m8 = ballot((used & 8u) != 0);
     if (lane == 0) {
-        const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u);
+        const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u) | (m4 ? 4u : 0u) | (m8 ? 8u : 0u);
         if (wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
         if (mb) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
     }
@@ -2054,17 +2163,25 @@ void launch_prep_rest(const float* X, const Views& v, hipStream_t s) {
 // Epilogue as in the FP32 kernel.
 // MaxCT column tiles (m = 2C <= 16 MaxCT); rows are new members, nnew <= 32,
 // so row tiles 0 and 1 only: 2 MaxCT - 1 tiles.
-template <int MaxCT, int Planes>
-__global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v) {
+// Acc (data whose FP32 sums are not exact): S, the dominant x1.y1 term,
+// restarts at zero every 32-dimension step and each step's S is added to an
+// FP64 accumulator; R and Q (cross terms at most 2^-8 of it) accumulate in
+// FP32 over all steps as before. x.y = S64 + (R + Q) in FP64 is still the
+// same value with x and y exchanged, and the distance is formed from FP64
+// norms in FP64 and rounded once.
+template <int MaxCT, int Planes, bool Acc>
+__global__ __launch_bounds__(256, MaxCT <= 2 ? ((Acc && Planes == 3) ? 3 : 4) : (MaxCT <= 3 && !(Acc && Planes >= 2)) ? 3 : 2)
+void k_join_split(Views v) {
     if (stopped(v)) return;
     constexpr int kSplitTiles = 2 * MaxCT - 1;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
     __shared__ uint32_t s_pos[kJoinWaves][64];
     __shared__ float s_nrm[kJoinWaves][64];
+    __shared__ double s_n64[kJoinWaves][Acc ? 64 : 1];
     __shared__ uint32_t s_emit[kJoinWaves][3][64];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int C2 = 2 * v.C, dp = v.dp, K = v.K;
+    const int C2 = 2 * v.C, dp = v.dp;
     const size_t plane = (size_t)v.N * dp;
     const int c16 = lane & 15, g = lane >> 4;
     EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
@@ -2083,8 +2200,11 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
             const uint2 c = cs[lane];
             s_oid[w][lane] = c.x;
             s_pos[w][lane] = c.y;
-            s_thr[w][lane] = v.lkey[(size_t)c.y * K + K - 1];
-            s_nrm[w][lane] = v.nrm[c.y];
+            s_thr[w][lane] = v.kth[c.y];
+            if constexpr (Acc)
+                s_n64[w][lane] = v.nrm64[c.y];
+            else
+                s_nrm[w][lane] = v.nrm[c.y];
         }
         wave_sync();
         const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
@@ -2094,11 +2214,15 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
         for (int ct = 0; ct < MaxCT; ++ct)
             rp[ct] = v.Xs + (size_t)s_pos[w][min(ct * 16 + c16, m - 1)] * dp + g * 8;
         floatx4 aS[kSplitTiles], aR[kSplitTiles], aQ[kSplitTiles];
+        double a64[Acc ? kSplitTiles : 1][4];
 #pragma unroll
         for (int t = 0; t < kSplitTiles; ++t) {
             aS[t] = floatx4{0.f, 0.f, 0.f, 0.f};
             aR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
             aQ[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (Acc)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a64[t][r] = 0.0;
         }
         for (int k0 = 0; k0 < dp; k0 += 32) {
             bf16x8 f[Planes][MaxCT];
@@ -2133,6 +2257,18 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
                         if (q == 3) aS[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[0][rt], f[0][ct], aS[t], 0, 0, 0);
                     }
             }
+            if constexpr (Acc) {
+                int t = 0;
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = rt; ct < MaxCT; ++ct, ++t) {
+                        if (!(rt < RT && ct < CT)) continue;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) a64[t][r] += (double)aS[t][r];
+                        aS[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
         }
         for (int pass = 0; pass < 2; ++pass) {
             int t = 0;
@@ -2145,13 +2281,21 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
                     if (j >= m) continue;
                     const uint32_t oj = s_oid[w][j];
                     const uint64_t tj = s_thr[w][j];
-                    const float nj = s_nrm[w][j];
+                    const float nj = Acc ? 0.f : s_nrm[w][j];
+                    const double nj64 = Acc ? s_n64[w][j] : 0.0;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int i = rt * 16 + g * 4 + r;
                         if (i >= nnew || (j < nnew && j <= i)) continue;
-                        const float dot = Planes == 1 ? aS[t][r] + 0.0f : aS[t][r] + (aR[t][r] + aQ[t][r]);
-                        float D = (s_nrm[w][i] + nj) - 2.0f * dot;
+                        float D;
+                        if constexpr (Acc) {
+                            const double dot = Planes == 1 ? a64[t][r]
+                                                           : a64[t][r] + ((double)aR[t][r] + (double)aQ[t][r]);
+                            D = (float)((s_n64[w][i] + nj64) - 2.0 * dot);
+                        } else {
+                            const float dot = Planes == 1 ? aS[t][r] + 0.0f : aS[t][r] + (aR[t][r] + aQ[t][r]);
+                            D = (s_nrm[w][i] + nj) - 2.0f * dot;
+                        }
                         D = D > 0.f ? D : 0.f;
                         const uint64_t kb = (uint64_t)__float_as_uint(D) << 32;
                         const uint64_t ki = kb | oj, kj = kb | s_oid[w][i];
@@ -2171,22 +2315,24 @@ __global__ __launch_bounds__(256, MaxCT <= 3 ? 3 : 2) void k_join_split(Views v)
     }
 }
 
-template <int MaxCT>
+template <int MaxCT, bool Acc>
 static void launch_join_split_ct(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
     if (v.planes == 1)
-        launch_timed(k_join_split<MaxCT, 1>, g, dim3(256), 0, s, e0, e1, v);
+        launch_timed(k_join_split<MaxCT, 1, Acc>, g, dim3(256), 0, s, e0, e1, v);
     else if (v.planes == 2)
-        launch_timed(k_join_split<MaxCT, 2>, g, dim3(256), 0, s, e0, e1, v);
+        launch_timed(k_join_split<MaxCT, 2, Acc>, g, dim3(256), 0, s, e0, e1, v);
     else
-        launch_timed(k_join_split<MaxCT, 3>, g, dim3(256), 0, s, e0, e1, v);
+        launch_timed(k_join_split<MaxCT, 3, Acc>, g, dim3(256), 0, s, e0, e1, v);
 }
 
 void launch_join_split(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (2 * v.C <= 48)
-        launch_join_split_ct<3>(v, s, e0, e1);
+    if (2 * v.C <= 32)
+        v.acc ? launch_join_split_ct<2, true>(v, s, e0, e1) : launch_join_split_ct<2, false>(v, s, e0, e1);
+    else if (2 * v.C <= 48)
+        v.acc ? launch_join_split_ct<3, true>(v, s, e0, e1) : launch_join_split_ct<3, false>(v, s, e0, e1);
     else
-        launch_join_split_ct<4>(v, s, e0, e1);
+        v.acc ? launch_join_split_ct<4, true>(v, s, e0, e1) : launch_join_split_ct<4, false>(v, s, e0, e1);
 }
 
 // ------------------------------------------------------------------ merge (a5)
@@ -2376,7 +2522,8 @@ __device__ __forceinline__ void merge_chunks(const uint64_t* pks, uint32_t c0, u
 // those that entered are compared), and counts the entered ids (c_t). An
 // entry entered exactly when it came from a proposal (position word
 // kPosUnknown); it gets its position from the id: the dataset's first
-// position plus the id (batched form), else posof.
+// position plus the id (batched form), the id itself until the permutation
+// has run (positions are the identity), else posof.
 __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uint64_t key, uint32_t pf) {
     const int lane = lane_id(), K = v.K;
     const size_t row = (size_t)p * K;
@@ -2388,7 +2535,7 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
     if (lost) pf = kNewBit;   // position 0: the build reports the error after this iteration
     if (lane < K && pf == kPosUnknown) {
         const uint32_t id = (uint32_t)key;
-        pf = (v.ds ? base + id : (uint32_t)v.posof[id]) | kNewBit;
+        pf = (v.ds ? base + id : v.permuted ? (uint32_t)v.posof[id] : id) | kNewBit;
     }
     bool twice = false;
     for (uint64_t m = em; m; m &= m - 1) {
@@ -2400,6 +2547,7 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
     if (lane < K) {
         v.lkey[row + lane] = key;
         v.lpos[row + lane] = pf;
+        if (lane == K - 1) v.kth[row / K] = key;
     }
     const uint64_t c = (uint64_t)__popcll(em);
     if (v.chg && lane == 0) v.chg[row / K] = (uint32_t)c;   // batched form: changes per target
@@ -2856,6 +3004,7 @@ __global__ void k_perm_rows(Views v) {
         if (c == 0) {
             v.orig2[q] = v.orig[p];
             v.nrm2[q] = v.nrm[p];
+            if (v.nrm64) v.nrm64_2[q] = v.nrm64[p];
         }
     }
 }
@@ -2902,6 +3051,7 @@ __global__ void k_perm_lists(Views v) {
         const size_t to = (size_t)q * v.K + k;
         v.lkey2[to] = v.lkey[e];
         v.lpos2[to] = (uint32_t)qn | (pf & kNewBit);
+        if (k == v.K - 1) v.kth2[q] = v.lkey[e];
     }
 }
 

@@ -63,6 +63,8 @@ def _params(**kw):
     (100, 784, dict(K=64, rho=1.0, path="bf16x3"), "MFMA"),
     (100, 784, dict(path="mfma_i8"), "not available"),
     (100, 8, dict(sampling=2), "unknown sampling"),
+    (100, 8, dict(reorder=-1), "reorder"),
+    (100, 8, dict(reorder=65), "reorder"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
     import paper_2112_06630_amd as knng
@@ -92,6 +94,18 @@ def test_sample_cap_matches_oracle(oracle_lib):
     for K in (1, 2, 7, 10, 15, 20, 64):
         for rho in (0.01, 0.3, 0.5, 0.77, 1.0):
             assert knng.sample_cap(K, rho) == oracle.cap(K, rho)
+
+
+def test_workspace_takes_reorder_iteration():
+    """reorder = t_p >= 1 runs the permutation after iteration t_p; every t_p
+    needs the same workspace (the permuted copies)."""
+    a = knng_ws(_params(reorder=1))
+    assert a == knng_ws(_params(reorder=3)) == knng_ws(_params(reorder=64)) > knng_ws(_params(reorder=0))
+
+
+def knng_ws(p, N=1000, d=8):
+    import paper_2112_06630_amd as knng
+    return knng.workspace_bytes(N, d, p)
 
 
 def test_workspace_grows_with_size():

@@ -178,6 +178,25 @@ knng_status knng_build(const float* dX, int64_t N, int32_t d, const knng_params*
                        int32_t* d_ids, float* d_dists, void* d_ws, size_t ws_bytes,
                        void* stream, knng_stats* stats);
 
+/* Allocation-free build, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): knng_build with its workspace taken from a static device array
+ * of KNNG_NOALLOC_MAX_BYTES that the library holds on every device it runs
+ * on, for the life of the process. The caller passes inputs and outputs as
+ * for knng_build (device memory, caller-owned). The call allocates nothing
+ * (no hipMalloc, hipFree, pinned memory or events): the per-iteration
+ * counters are read back from the same array; stats (nullable) carry counts
+ * but no timings. Fails with KNNG_ENOMEM, before any device work, when
+ * knng_workspace_bytes(N, d, params) + 4160 bytes exceed the array: a build
+ * of 2000 points with K = 10 needs 7 MiB, 6000 points with K = 15 about
+ * 50 MiB. Every call on one device shares that device's array and leaves its
+ * contents behind (the build initialises what it reads), so calls that
+ * overlap in time on one device race and must be serialised by the caller.
+ * Synchronises `stream` once per iteration. */
+#define KNNG_NOALLOC_MAX_BYTES (64u << 20)
+knng_status knng_build_noalloc(const float* dX, int64_t N, int32_t d, const knng_params* params,
+                               int32_t* d_ids, float* d_dists, void* stream, knng_stats* stats);
+
 /* ---- step API: one context per build, the state lives in the workspace ---- */
 
 /* Bind a context to (dX, N, d, params, workspace, stream); pads the rows and

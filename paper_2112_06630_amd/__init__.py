@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import torch
 
-__all__ = ["build", "Context", "Params", "workspace_bytes", "sample_cap", "KnngError", "LIB_PATH",
+__all__ = ["build", "build_noalloc", "Context", "Params", "workspace_bytes", "sample_cap", "KnngError", "LIB_PATH",
            "PATH_AUTO", "PATH_VALU", "PATH_MFMA", "PATH_MFMA_I8", "PATH_MFMA_BF16X3", "MAX_ITERS", "lib",
            "SAMPLING_WEIGHTED", "SAMPLING_TURBO"]
 
@@ -31,6 +31,7 @@ _PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_i8": PA
 SAMPLING_WEIGHTED, SAMPLING_TURBO = 0, 1
 _SAMPLING = {"weighted": SAMPLING_WEIGHTED, "turbo": SAMPLING_TURBO}
 MAX_ITERS = 64
+MAX_NOALLOC_BYTES = 64 << 20   # KNNG_NOALLOC_MAX_BYTES
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV = 0, 1, 2, 3, 4
 
@@ -69,6 +70,7 @@ def _load() -> ctypes.CDLL:
     L.knng_workspace_bytes.argtypes = [i64, i32, PP]
     L.knng_workspace_bytes.restype = sz
     L.knng_build.argtypes = [P, i64, i32, PP, P, P, P, sz, P, ctypes.POINTER(_Stats)]
+    L.knng_build_noalloc.argtypes = [P, i64, i32, PP, P, P, P, ctypes.POINTER(_Stats)]
     L.knng_create.argtypes = [ctypes.POINTER(P), P, i64, i32, PP, P, sz, P]
     L.knng_init_graph.argtypes = [P]
     L.knng_load_graph.argtypes = [P, P, P, i32]
@@ -174,6 +176,29 @@ def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_i
                           ctypes.c_void_p(dists.data_ptr()), ctypes.c_void_p(workspace.data_ptr()), ws,
                           ctypes.c_void_p(_stream_ptr(X.device)), ctypes.byref(st)), allow=(OK, ENOTCONV))
     return ids, dists, _stats_dict(st)
+
+
+def build_noalloc(X: torch.Tensor, K: int, ids: torch.Tensor, dists: torch.Tensor, rho: float = 1.0,
+                  delta: float = 0.001, max_iters: int = 30, seed: int = 0, reorder: bool | int = False,
+                  path: str | int = "auto", precision: str | int = "fp32", sampling: str | int = "weighted") -> dict:
+    """knng_build_noalloc: the build with the library's static device scratch
+    as workspace (nothing allocated). The caller passes the outputs ids
+    (int32 [N, K]) and dists (float32 [N, K]); returns the stats dict (no
+    timings). Raises KnngError (ENOMEM) when the build does not fit the
+    scratch (MAX_NOALLOC_BYTES)."""
+    _check_x(X)
+    N, d = X.shape
+    if tuple(ids.shape) != (N, K) or tuple(dists.shape) != (N, K) or ids.dtype != torch.int32 \
+            or dists.dtype != torch.float32:
+        raise ValueError("ids / dists must be int32 / float32 [N, K]")
+    if not (ids.is_contiguous() and dists.is_contiguous()):
+        raise ValueError("ids / dists must be contiguous")
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
+    st = _Stats()
+    _check(lib.knng_build_noalloc(ctypes.c_void_p(X.data_ptr()), N, d, ctypes.byref(p),
+                                  ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dists.data_ptr()),
+                                  ctypes.c_void_p(_stream_ptr(X.device)), ctypes.byref(st)), allow=(OK, ENOTCONV))
+    return _stats_dict(st)
 
 
 @dataclass

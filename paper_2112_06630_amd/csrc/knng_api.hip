@@ -323,7 +323,9 @@ struct knng_ctx {
     hipEvent_t ev[10];   // phase events of odd (0..3) and even (6..9) iterations; 4, 5: permutation
     uint64_t hc[kNumCounters];
     uint64_t* hslot;     // pinned: the counters of iteration t at hslot[t * kNumCounters]
-    uint64_t* dslot;     // the same memory as the device addresses it
+    uint64_t* dslot;     // the same memory as the device addresses it (allocation-free
+                         // build: device slots in the static scratch, no host mapping)
+    bool noalloc;        // allocation-free build: no events, no pinned slots, no timings
 };
 
 namespace {
@@ -380,7 +382,7 @@ float ms_between(hipEvent_t a, hipEvent_t b) {
 knng_status do_permute(knng_ctx* c) {
     Views& v = c->v;
     hipStream_t s = c->stream;
-    HIP_TRY(hipEventRecord(c->ev[4], s));
+    if (!c->noalloc) HIP_TRY(hipEventRecord(c->ev[4], s));
     launch_perm_begin(v, s);
     uint32_t fl[4] = {0, 0, 0, 0};
     for (int l = 0; l < perm_levels_max(); l += 4) {
@@ -403,10 +405,10 @@ knng_status do_permute(knng_ctx* c) {
     if (v.Xs) std::swap(v.Xs, v.Xs2);
     launch_perm_posof(v, s);
     v.permuted = 1;
-    HIP_TRY(hipEventRecord(c->ev[5], s));
+    if (!c->noalloc) HIP_TRY(hipEventRecord(c->ev[5], s));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    c->stats.reorder_ms = ms_between(c->ev[4], c->ev[5]);
+    c->stats.reorder_ms = c->noalloc ? 0.f : ms_between(c->ev[4], c->ev[5]);
     c->perm_levels = (int)fl[2];
     knng_status rs = read_counters(c);
     if (rs != KNNG_OK) return rs;
@@ -461,8 +463,14 @@ knng_status enqueue_iteration(knng_ctx* c, int t, double thr) {
 // statistics.
 knng_status finish_iteration(knng_ctx* c, int t, int64_t* evals, int64_t* changes) {
     hipEvent_t* E = phase_events(c, t);
-    HIP_TRY(hipEventSynchronize(E[3]));
-    std::memcpy(c->hc, c->hslot + (size_t)t * kNumCounters, sizeof(c->hc));
+    if (c->noalloc) {
+        HIP_TRY(hipMemcpyAsync(c->hc, c->dslot + (size_t)t * kNumCounters, sizeof(c->hc), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        HIP_TRY(hipEventSynchronize(E[3]));
+        std::memcpy(c->hc, c->hslot + (size_t)t * kNumCounters, sizeof(c->hc));
+    }
     if (c->hc[kCntError]) {
         char buf[96];
         snprintf(buf, sizeof buf, "device invariant failed in iteration %d (code %llu)", t,
@@ -477,10 +485,12 @@ knng_status finish_iteration(knng_ctx* c, int t, int64_t* evals, int64_t* change
     S.changes[i] = ch;
     S.proposals[i] = (int64_t)c->hc[kCntProposals];
     S.rescored[i] = (int64_t)c->hc[kCntRescored];
-    S.sample_ms[i] = ms_between(E[0], E[1]);
-    S.join_ms[i] = ms_between(E[1], E[2]);
-    S.merge_ms[i] = ms_between(E[2], E[3]);
-    S.iter_ms[i] = ms_between(E[0], E[3]);
+    if (!c->noalloc) {
+        S.sample_ms[i] = ms_between(E[0], E[1]);
+        S.join_ms[i] = ms_between(E[1], E[2]);
+        S.merge_ms[i] = ms_between(E[2], E[3]);
+        S.iter_ms[i] = ms_between(E[0], E[3]);
+    }
     S.iters = t;
     c->t = t;
     if (evals) *evals = e;
@@ -511,6 +521,96 @@ int dist_mode(const knng_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// The allocation-free build's workspace: a static device array that every
+// device the library runs on holds for the life of the process. In host code
+// `scratch` names a host-side stand-in, never a device address: the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr size_t kScratchBytes = (size_t)KNNG_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+knng_status scratch_base(char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(KNNG_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(KNNG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch[dev];
+    return KNNG_OK;
+}
+
+// init, iterations until the stop rule or max_iters, write-out (the body of
+// both build entry points). Events only when the context has them.
+knng_status run_build(knng_ctx* c, const knng_params* params, int32_t* d_ids, float* d_dists, knng_stats* stats) {
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (!c->noalloc &&
+        (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess)) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return fail(KNNG_EDEVICE, "hipEventCreate failed");
+    }
+    auto done = [&](knng_status st) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (e2) (void)hipEventDestroy(e2);
+        return st;
+    };
+    if (e0) (void)hipEventRecord(e0, c->stream);
+    knng_status s = knng_init_graph(c);
+    if (s != KNNG_OK) return done(s);
+    if (e1) (void)hipEventRecord(e1, c->stream);
+    const int64_t N = c->N;
+    const double thr = (double)params->delta * (double)N * (double)params->K;
+    const int T = std::min(params->max_iters, KNNG_MAX_ITERS);
+    bool conv = false;
+    // One iteration ahead: iteration t + 1 is enqueued before the host reads
+    // iteration t's counters, and returns at once on the device if t met the
+    // stop rule (the same test, c_t < delta N K, on both sides). Not across
+    // the permutation.
+    if (T > 0 && (s = enqueue_iteration(c, 1, thr)) != KNNG_OK) return done(s);
+    for (int t = 1; t <= T; ++t) {
+        const bool ahead = t < T && !permute_after(c, t);
+        if (ahead && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) return done(s);
+        int64_t e = 0, ch = 0;
+        s = finish_iteration(c, t, &e, &ch);
+        if (s == KNNG_OK && permute_after(c, t)) s = do_permute(c);
+        if (s != KNNG_OK) return done(s);
+        if ((double)ch < thr) {
+            conv = true;
+            break;
+        }
+        if (!ahead && t < T && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) return done(s);
+    }
+    launch_finalize(c->v, d_ids, d_dists, nullptr, c->stream);
+    if (e2) (void)hipEventRecord(e2, c->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return done(fail(KNNG_EDEVICE, "finalize failed"));
+    c->stats.converged = conv ? 1 : 0;
+    if (e0) {
+        c->stats.init_ms = ms_between(e0, e1);
+        c->stats.total_ms = ms_between(e0, e2);
+        float acc = c->stats.init_ms + c->stats.reorder_ms;
+        for (int i = 0; i < c->stats.iters; ++i) acc += c->stats.iter_ms[i];
+        c->stats.finalize_ms = c->stats.total_ms - acc > 0.f ? c->stats.total_ms - acc : 0.f;
+    }
+    if (stats) *stats = c->stats;
+    return done((conv || params->max_iters == 0) ? KNNG_OK : KNNG_ENOTCONV);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* knng_last_error(void) { return g_err.c_str(); }
@@ -522,6 +622,85 @@ size_t knng_workspace_bytes(int64_t N, int32_t d, const knng_params* params) {
     if (make_plan(N, d, params, P) != KNNG_OK) return 0;
     return P.total;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Binds a context to its inputs and workspace, lays the rows out and checks
+// X (one synchronisation). dev_slots == nullptr: phase events and pinned
+// counter slots; else the allocation-free form (counter slots in device
+// memory, no events).
+knng_status ctx_init(knng_ctx* c, const Plan& P, const float* dX, int64_t N, int32_t d, const knng_params* params,
+                     void* d_ws, void* stream, uint64_t* dev_slots) {
+    c->plan = P;
+    c->p = *params;
+    c->N = N;
+    c->d = d;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->dX = dX;
+    c->ws = d_ws;
+    c->v = carve(P, N, d, params->K, d_ws);
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    c->stats.path = P.path;
+    c->stats.precision = P.bf16 ? KNNG_BF16_SCREEN : KNNG_FP32;
+    c->stats.dpad = P.dp;
+    if (dev_slots) {
+        c->noalloc = true;
+        c->dslot = dev_slots;
+    } else {
+        for (auto& e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(KNNG_EDEVICE, "hipEventCreate failed");
+        if (!slot_take(&c->hslot, &c->dslot))
+            return fail(KNNG_EDEVICE, "pinned counter slots: hipHostMalloc failed");
+    }
+    c->v.stop = c->v.flag + kStopFlag;
+    launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
+    launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
+    launch_fill_u32(c->v.pcnt, 0u, N, c->stream);
+    launch_fill_u32(c->v.stop, 0u, 1, c->stream);
+    if (P.path == KNNG_PATH_VALU) {
+        launch_pad_rows(dX, c->v, c->stream);
+    } else {
+        launch_prep(dX, c->v, P.split, c->stream);
+    }
+    if (P.bf16) launch_make_bf16(c->v, c->stream);
+    if (hipGetLastError() != hipSuccess || read_counters(c) != KNNG_OK) return fail(KNNG_EDEVICE, "row padding failed");
+    if (c->hc[kCntNonFinite]) return fail(KNNG_EINVAL, "X holds a NaN or an infinity");
+    if (P.path != KNNG_PATH_VALU && !P.bf16) {
+        // FP32 Gram sums are exact only for integers with squared norms <= 2^23
+        c->v.acc = (c->hc[kCntSplit] & kLayoutInexact) ? 1 : 0;
+        c->stats.accurate = c->v.acc;
+    }
+    if (P.split) {
+        const uint64_t used = c->hc[kCntSplit];
+        c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
+        c->stats.planes = c->v.planes;
+        if (c->v.planes > 1) launch_prep_rest(dX, c->v, c->stream);
+        if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
+            c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)
+    }
+    c->stats.path = c->plan.path;
+    return KNNG_OK;
+}
+
+// Returns what ctx_init took: pinned slots (after the stream has drained)
+// and events.
+void ctx_release(knng_ctx* c) {
+    if (c->hslot) {
+        (void)hipStreamSynchronize(c->stream);   // no kernel of this context writes the slots any more
+        slot_give(c->hslot, c->dslot);
+        c->hslot = nullptr;
+    }
+    for (auto& e : c->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
 
 knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, const knng_params* params,
                         void* d_ws, size_t ws_bytes, void* stream) {
@@ -540,61 +719,11 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d, c
     }
     knng_ctx* c = new (std::nothrow) knng_ctx();
     if (!c) return fail(KNNG_ENOMEM, "host allocation of the context failed");
-    c->plan = P;
-    c->p = *params;
-    c->N = N;
-    c->d = d;
-    c->stream = static_cast<hipStream_t>(stream);
-    c->dX = dX;
-    c->ws = d_ws;
-    c->v = carve(P, N, d, params->K, d_ws);
-    std::memset(&c->stats, 0, sizeof(c->stats));
-    c->stats.path = P.path;
-    c->stats.precision = P.bf16 ? KNNG_BF16_SCREEN : KNNG_FP32;
-    c->stats.dpad = P.dp;
-    for (auto& e : c->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            knng_destroy(c);
-            return fail(KNNG_EDEVICE, "hipEventCreate failed");
-        }
-    }
-    if (!slot_take(&c->hslot, &c->dslot)) {
+    s = ctx_init(c, P, dX, N, d, params, d_ws, stream, nullptr);
+    if (s != KNNG_OK) {
         knng_destroy(c);
-        return fail(KNNG_EDEVICE, "pinned counter slots: hipHostMalloc failed");
+        return s;
     }
-    c->v.stop = c->v.flag + kStopFlag;
-    launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
-    launch_fill_u32(c->v.nn, 0u, N, c->stream);   // no owner has a sample before its first iteration
-    launch_fill_u32(c->v.pcnt, 0u, N, c->stream);
-    launch_fill_u32(c->v.stop, 0u, 1, c->stream);
-    if (P.path == KNNG_PATH_VALU) {
-        launch_pad_rows(dX, c->v, c->stream);
-    } else {
-        launch_prep(dX, c->v, P.split, c->stream);
-    }
-    if (P.bf16) launch_make_bf16(c->v, c->stream);
-    if (hipGetLastError() != hipSuccess || read_counters(c) != KNNG_OK) {
-        knng_destroy(c);
-        return fail(KNNG_EDEVICE, "row padding failed");
-    }
-    if (c->hc[kCntNonFinite]) {
-        knng_destroy(c);
-        return fail(KNNG_EINVAL, "X holds a NaN or an infinity");
-    }
-    if (P.path != KNNG_PATH_VALU && !P.bf16) {
-        // FP32 Gram sums are exact only for integers with squared norms <= 2^23
-        c->v.acc = (c->hc[kCntSplit] & kLayoutInexact) ? 1 : 0;
-        c->stats.accurate = c->v.acc;
-    }
-    if (P.split) {
-        const uint64_t used = c->hc[kCntSplit];
-        c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
-        c->stats.planes = c->v.planes;
-        if (c->v.planes > 1) launch_prep_rest(dX, c->v, c->stream);
-        if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
-            c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)
-    }
-    c->stats.path = c->plan.path;
     *out = c;
     return KNNG_OK;
 }
@@ -668,12 +797,7 @@ knng_status knng_get_stats(const knng_ctx* c, knng_stats* stats) {
 
 void knng_destroy(knng_ctx* c) {
     if (!c) return;
-    if (c->hslot) {
-        (void)hipStreamSynchronize(c->stream);   // no kernel of this context writes the slots any more
-        slot_give(c->hslot, c->dslot);
-    }
-    for (auto& e : c->ev)
-        if (e) (void)hipEventDestroy(e);
+    ctx_release(c);
     delete c;
 }
 
@@ -683,61 +807,36 @@ knng_status knng_build(const float* dX, int64_t N, int32_t d, const knng_params*
     knng_ctx* c = nullptr;
     knng_status s = knng_create(&c, dX, N, d, params, d_ws, ws_bytes, stream);
     if (s != KNNG_OK) return s;
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        knng_destroy(c);
-        return fail(KNNG_EDEVICE, "hipEventCreate failed");
-    }
-    auto cleanup = [&]() {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipEventDestroy(e2);
-        knng_destroy(c);
-    };
-    (void)hipEventRecord(e0, c->stream);
-    s = knng_init_graph(c);
-    if (s != KNNG_OK) { cleanup(); return s; }
-    (void)hipEventRecord(e1, c->stream);
-    const double thr = (double)params->delta * (double)N * (double)params->K;
-    const int T = std::min(params->max_iters, KNNG_MAX_ITERS);
-    bool conv = false;
-    // One iteration ahead: iteration t + 1 is enqueued before the host reads
-    // iteration t's counters, and returns at once on the device if t met the
-    // stop rule (the same test, c_t < delta N K, on both sides). Not across
-    // the permutation after iteration 1.
-    if (T > 0 && (s = enqueue_iteration(c, 1, thr)) != KNNG_OK) { cleanup(); return s; }
-    for (int t = 1; t <= T; ++t) {
-        const bool ahead = t < T && !permute_after(c, t);
-        if (ahead && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) { cleanup(); return s; }
-        int64_t e = 0, ch = 0;
-        s = finish_iteration(c, t, &e, &ch);
-        if (s == KNNG_OK && permute_after(c, t)) s = do_permute(c);
-        if (s != KNNG_OK) { cleanup(); return s; }
-        if ((double)ch < thr) { conv = true; break; }
-        if (!ahead && t < T && (s = enqueue_iteration(c, t + 1, thr)) != KNNG_OK) { cleanup(); return s; }
-    }
-    launch_finalize(c->v, d_ids, d_dists, nullptr, c->stream);
-    (void)hipEventRecord(e2, c->stream);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
-        cleanup();
-        return fail(KNNG_EDEVICE, "finalize failed");
-    }
-    c->stats.converged = conv ? 1 : 0;
-    c->stats.init_ms = ms_between(e0, e1);
-    c->stats.total_ms = ms_between(e0, e2);
-    float fin = 0.f;
-    if (hipEventElapsedTime(&fin, e0, e2) == hipSuccess) {
-        float acc = c->stats.init_ms + c->stats.reorder_ms;
-        for (int i = 0; i < c->stats.iters; ++i) acc += c->stats.iter_ms[i];
-        c->stats.finalize_ms = fin - acc > 0.f ? fin - acc : 0.f;
-    }
-    if (stats) *stats = c->stats;
-    cleanup();
-    return (conv || params->max_iters == 0) ? KNNG_OK : KNNG_ENOTCONV;
+    s = run_build(c, params, d_ids, d_dists, stats);
+    knng_destroy(c);
+    return s;
 }
 
+knng_status knng_build_noalloc(const float* dX, int64_t N, int32_t d, const knng_params* params, int32_t* d_ids,
+                               float* d_dists, void* stream, knng_stats* stats) {
+    g_err.clear();
+    if (!dX) return fail(KNNG_EINVAL, "dX is NULL");
+    if (!d_ids || !d_dists) return fail(KNNG_EINVAL, "outputs are NULL");
+    Plan P{};
+    knng_status s = make_plan(N, d, params, P);
+    if (s != KNNG_OK) return s;
+    const size_t need = P.total + kSlotBytes;   // workspace, then the counter slots
+    if (need > kScratchBytes) {
+        char buf[192];
+        snprintf(buf, sizeof buf,
+                 "allocation-free build needs %zu bytes of scratch; the static scratch holds %zu "
+                 "(use knng_build with a workspace)", need, kScratchBytes);
+        return fail(KNNG_ENOMEM, buf);
+    }
+    char* base = nullptr;
+    s = scratch_base(&base);
+    if (s != KNNG_OK) return s;
+    knng_ctx c{};   // on the stack: nothing is allocated
+    s = ctx_init(&c, P, dX, N, d, params, base, stream, reinterpret_cast<uint64_t*>(base + P.total));
+    if (s == KNNG_OK) s = run_build(&c, params, d_ids, d_dists, stats);
+    ctx_release(&c);
+    return s;
+}
 
 }  // extern "C"
 // ====================================================================== batched form

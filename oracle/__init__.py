@@ -62,6 +62,7 @@ def _load():
     lib.orc_sample.argtypes = [P, P, i64, i32, i32, u64, i32, P, P, P, P, P, i32]
     lib.orc_join_merge.argtypes = [P, i64, i32, i32, i32, P, P, P, P, P, P, P, P, P]
     lib.orc_iterate.argtypes = [P, i64, i32, i32, i32, u64, i32, P, P, P, P, P, i32]
+    lib.orc_iterate_blocks.argtypes = [P, i64, i32, i32, i32, u64, i32, i32, P, P, P, P, P, i32]
     lib.orc_dist_sum.argtypes = [P, i64, i32]
     lib.orc_dist_sum.restype = f64
     lib.orc_build.argtypes = [P, i64, i32, i32, f64, f64, i32, u64, P, P, P, P, P, P, i32]
@@ -72,7 +73,7 @@ def _load():
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     lib.orc_set_num_threads.restype = None
-    for name in ("orc_init", "orc_sample", "orc_join_merge", "orc_iterate", "orc_build",
+    for name in ("orc_init", "orc_sample", "orc_join_merge", "orc_iterate", "orc_iterate_blocks", "orc_build",
                  "orc_bruteforce", "orc_bruteforce_rows", "orc_list_dists", "orc_greedy_order"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -215,16 +216,23 @@ def join_merge(X, state: State, smp: Sample, K: int, C: int) -> tuple[State, int
 
 
 def iterate(X, state: State, K: int, C: int, seed: int,
-            sampling: str = "weighted") -> tuple[State, int, int]:
-    """One synchronous iteration t = state.t + 1. Returns (new state, e_t, c_t)."""
+            sampling: str = "weighted", blocks: int = 1) -> tuple[State, int, int]:
+    """One iteration t = state.t + 1: synchronous (blocks = 1), or block-
+    asynchronous over ``blocks`` blocks of consecutive owner ids (each block
+    samples from the graph the earlier blocks left). Returns (new state, e_t, c_t)."""
     X = _f32(X)
     N, d = X.shape
     s = state.copy()
     e = ctypes.c_int64(0)
     c = ctypes.c_int64(0)
-    _check(_load().orc_iterate(_ptr(X), N, d, K, C, seed, s.t + 1, _ptr(s.ids), _ptr(s.dists),
-                               _ptr(s.flags), ctypes.byref(e), ctypes.byref(c), _mode(sampling)),
-           "iterate")
+    if blocks > 1:
+        _check(_load().orc_iterate_blocks(_ptr(X), N, d, K, C, seed, s.t + 1, int(blocks), _ptr(s.ids),
+                                          _ptr(s.dists), _ptr(s.flags), ctypes.byref(e), ctypes.byref(c),
+                                          _mode(sampling)), "iterate_blocks")
+    else:
+        _check(_load().orc_iterate(_ptr(X), N, d, K, C, seed, s.t + 1, _ptr(s.ids), _ptr(s.dists),
+                                   _ptr(s.flags), ctypes.byref(e), ctypes.byref(c), _mode(sampling)),
+               "iterate")
     s.t += 1
     return s, int(e.value), int(c.value)
 
@@ -242,8 +250,9 @@ class BuildResult:
 
 
 def build_graph(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
-                keep_states: bool = False, sampling: str = "weighted") -> BuildResult:
-    """Whole build. With keep_states, every G_t (t = 0..iters) is kept."""
+                keep_states: bool = False, sampling: str = "weighted", blocks: int = 1) -> BuildResult:
+    """Whole build (synchronous, or block-asynchronous with ``blocks`` > 1).
+    With keep_states, every G_t (t = 0..iters) is kept."""
     X = _f32(X)
     N, d = X.shape
     C = cap(K, rho)
@@ -251,7 +260,7 @@ def build_graph(X, K: int, rho: float, delta: float, max_iters: int, seed: int,
     states = [st.copy()] if keep_states else []
     ev, ch, ds = [], [], []
     for t in range(1, max_iters + 1):
-        st, e, c = iterate(X, st, K, C, seed, sampling)
+        st, e, c = iterate(X, st, K, C, seed, sampling, blocks)
         ev.append(e)
         ch.append(c)
         ds.append(float(_load().orc_dist_sum(_ptr(st.dists), N, K)))

@@ -408,6 +408,55 @@ int orc_iterate(const float *X, int64_t N, int32_t d, int32_t K, int32_t C,
     return rc;
 }
 
+/* Block-asynchronous iteration t. The paper updates the graph in place
+ * (Sec. 3.1 tracks neighbourhood sizes upon every update), so a node sampled
+ * later in an iteration sees what earlier nodes changed. Reading (order-
+ * dependent, so it is fixed here): the owners are taken in B blocks of
+ * consecutive ids, block b = [floor(N b / B), floor(N (b + 1) / B)), in
+ * order; block b samples from the graph as blocks 0..b-1 of this iteration
+ * left it (lists, flags and the reverse lists they imply), only its owners
+ * take samples, flip and join, and their proposals are merged into every
+ * list before block b + 1 samples. B = 1 is the synchronous iteration and
+ * B = N the node-by-node order. e_t and c_t are summed over the blocks (an
+ * id that enters and is pushed out later in the iteration counts once). */
+int orc_iterate_blocks(const float *X, int64_t N, int32_t d, int32_t K, int32_t C,
+                       uint64_t seed, int32_t t, int32_t B, int32_t *ids, double *dists, uint8_t *flags,
+                       int64_t *evals_out, int64_t *changes_out, int32_t mode)
+{
+    if (B < 1 || (int64_t)B > N) return -1;
+    int32_t *cnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N * C));
+    int32_t *cold = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N * C));
+    int32_t *nnew = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *nold = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    uint8_t *f2 = (uint8_t *)malloc((size_t)(N * K));
+    int rc = -2;
+    int64_t e_sum = 0, c_sum = 0;
+    if (cnew && cold && nnew && nold && f2) {
+        rc = 0;
+        for (int32_t b = 0; b < B && rc == 0; ++b) {
+            const int64_t lo = N * (int64_t)b / B, hi = N * (int64_t)(b + 1) / B;
+            rc = orc_sample(ids, flags, N, K, C, seed, t, cnew, nnew, cold, nold, f2, mode);
+            if (rc != 0) break;
+            for (int64_t u = 0; u < N; ++u) {
+                if (u >= lo && u < hi) {
+                    memcpy(flags + u * K, f2 + u * K, (size_t)K);
+                } else {
+                    nnew[u] = 0;
+                    nold[u] = 0;
+                }
+            }
+            int64_t e = 0, c = 0;
+            rc = orc_join_merge(X, N, d, K, C, cnew, nnew, cold, nold, ids, dists, flags, &e, &c);
+            e_sum += e;
+            c_sum += c;
+        }
+    }
+    free(cnew); free(cold); free(nnew); free(nold); free(f2);
+    if (evals_out) *evals_out = e_sum;
+    if (changes_out) *changes_out = c_sum;
+    return rc;
+}
+
 /* Sum of all list distances, in a fixed order (the monotonicity invariant). */
 double orc_dist_sum(const double *dists, int64_t N, int32_t K)
 {

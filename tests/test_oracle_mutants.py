@@ -45,6 +45,10 @@ MUTANTS = {
     "entered_ids_flagged_old": ("if (f == 2) { f = ORC_NEW; ++c; }", "if (f == 2) { f = ORC_OLD; ++c; }"),
     "turbo_counts_whole_pool": ("nf[pool[i].flag == ORC_NEW ? 0 : 1] += 1;", "{ nf[0] += 1; nf[1] += 1; }"),
     "turbo_coin_skipped": ("if (mode == ORC_TURBO &&", "if (0 &&"),
+    "block_takes_all_later_owners": ("const int64_t lo = N * (int64_t)b / B, hi = N * (int64_t)(b + 1) / B;",
+                                     "const int64_t lo = N * (int64_t)b / B, hi = N;"),
+    "block_flips_dropped": ("memcpy(flags + u * K, f2 + u * K, (size_t)K);", ";"),
+    "block_outside_owners_join": ("nnew[u] = 0;", ";"),
     "turbo_coin_uses_k": ("* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)C << 32))",
                           "* nf[pool[i].flag == ORC_NEW ? 0 : 1] >= ((uint64_t)K << 32))"),
 }

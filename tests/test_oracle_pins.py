@@ -595,3 +595,63 @@ def test_thread_count_independence(oracle_lib):
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env,
                                             cwd=os.path.dirname(HERE)))
     assert outs[0] == outs[1]
+
+
+def _blocks_by_definition(X, st, K, C, seed, t, B):
+    """The block-asynchronous iteration composed from its definition: block b
+    of consecutive owner ids samples from the graph the earlier blocks left
+    (the oracle's sampler, pinned above), only its owners keep their samples
+    and flips, and its join + merge is the pair-by-pair step written out
+    above."""
+    N = X.shape[0]
+    cur = st.copy()
+    e_sum = c_sum = 0
+    for b in range(B):
+        lo, hi = N * b // B, N * (b + 1) // B
+        smp = oracle.sample(cur, K, C, seed, t)
+        for u in range(N):
+            if not lo <= u < hi:
+                smp.cnew[u] = smp.cnew[u][:0]
+                smp.cold[u] = smp.cold[u][:0]
+                smp.flags[u] = cur.flags[u]
+        ids, dists, flags, e, c = _join_merge_by_definition(X, cur, smp, K)
+        cur = oracle.State(ids, dists, flags, cur.t)
+        e_sum += e
+        c_sum += c
+    return cur, e_sum, c_sum
+
+
+@pytest.mark.parametrize("N,K,rho,seed,t,B", [(40, 5, 1.0, 1, 1, 4), (60, 6, 0.5, 2, 2, 3), (30, 4, 1.0, 4, 1, 30)])
+def test_block_async_matches_definition(oracle_lib, N, K, rho, seed, t, B):
+    """The block-asynchronous iteration (the paper's in-place update at block
+    granularity, B = N: node by node) equals its definition composed block by
+    block, on random states with exact integer distances."""
+    X = synth.integer_points(N, 3, 4, seed)
+    st = _sorted_random_state(X, K, seed)
+    st.t = t - 1
+    C = oracle.cap(K, rho)
+    got, e, c = oracle.iterate(X, st, K, C, seed, blocks=B)
+    ref, e_ref, c_ref = _blocks_by_definition(X, st, K, C, seed, t, B)
+    assert e == e_ref and c == c_ref
+    assert np.array_equal(got.ids, ref.ids)
+    assert np.array_equal(got.dists, ref.dists)
+    assert np.array_equal(got.flags, ref.flags)
+
+
+def test_block_async_one_block_is_synchronous_and_more_blocks_differ(oracle_lib):
+    """B = 1 is the synchronous iteration bit for bit; with several blocks the
+    later blocks see the earlier ones' updates, so the trajectory changes, and
+    the built graph stays valid and as good (recall against brute force)."""
+    X, p = synth.workload("gauss2k_d8", N=800)
+    K, C = 10, oracle.cap(10, 1.0)
+    s0 = oracle.init(X, K, 0)
+    a, ea, ca = oracle.iterate(X, s0, K, C, 0)
+    b, eb, cb = oracle.iterate(X, s0, K, C, 0, blocks=1)
+    assert np.array_equal(a.ids, b.ids) and np.array_equal(a.flags, b.flags) and (ea, ca) == (eb, cb)
+    g, eg, cg = oracle.iterate(X, s0, K, C, 0, blocks=8)
+    assert not np.array_equal(g.ids, a.ids)
+    r = oracle.build_graph(X, K, 1.0, 0.001, 20, 0, blocks=8)
+    s = oracle.build_graph(X, K, 1.0, 0.001, 20, 0)
+    _, ed = oracle.bruteforce(X, K)
+    assert oracle.recall(X, r.ids, ed) >= min(0.98, oracle.recall(X, s.ids, ed) - 0.01)
+    assert (np.diff(r.dists, axis=1) >= 0).all()

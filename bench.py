@@ -120,7 +120,7 @@ def recall_of(X, ids, tau, rows, rel=1e-5):
     return good / (len(rows) * ids.shape[1])
 
 
-def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted", threads=0):
+def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted", threads=0, blocks=0):
     """FP64 oracle on the host: init + iterations 1, 2, ... of the same workload
     (same sampling rule) until ~budget_s of CPU work; evals/s over the
     iterations run."""
@@ -136,7 +136,7 @@ def cpu_baseline(Xnp, w, budget_s=20.0, sampling="weighted", threads=0):
     thr = w["delta"] * Xnp.shape[0] * w["K"]
     stopped = False
     while time.perf_counter() - t0 < budget_s and iters < w["max_iters"]:
-        st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"], sampling)
+        st, e, c = oracle.iterate(Xnp, st, w["K"], C, w["seed"], sampling, max(1, blocks))
         ev += e
         iters += 1
         if c < thr:   # the build's own stop rule (Sec. 2: changes below delta*N*K)
@@ -175,7 +175,7 @@ def member_counts_and_graphs(X, w, args, iters, keep_graphs):
     asked, the graph G_t."""
     import paper_2112_06630_amd as knng
     ctx = knng.Context(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
-                       path=args.path, precision=args.precision, sampling=args.sampling)
+                       path=args.path, precision=args.precision, sampling=args.sampling, blocks=args.blocks)
     ctx.init()
     members, graphs = [], []
     for _ in range(iters):
@@ -372,6 +372,8 @@ def main():
                     help="selection-step rule (Sec. 3.1): bounded heaps or turbosampling")
     ap.add_argument("--recall-rows", type=int, default=100000,
                     help="query rows for recall (all rows when N is smaller; a seeded sample otherwise)")
+    ap.add_argument("--blocks", type=int, default=0,
+                    help="block-asynchronous iterations over this many blocks of owners (0: synchronous)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU oracle baseline (0: all host cores)")
@@ -486,13 +488,13 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
     dev = torch.device("cuda:0")
     X = torch.from_numpy(Xnp).to(dev)
     p = knng.make_params(w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
-                         path=args.path, precision=args.precision, sampling=args.sampling)
+                         path=args.path, precision=args.precision, sampling=args.sampling, blocks=args.blocks)
     ws = torch.empty(knng.workspace_bytes(w["N"], w["d"], p), dtype=torch.uint8, device=dev)
     ids = torch.empty((w["N"], w["K"]), dtype=torch.int32, device=dev)
     dists = torch.empty((w["N"], w["K"]), dtype=torch.float32, device=dev)
     run = lambda: knng.build(X, w["K"], w["rho"], w["delta"], w["max_iters"], w["seed"], int(args.reorder),
                              path=args.path, workspace=ws, out=(ids, dists), precision=args.precision,
-                             sampling=args.sampling)
+                             sampling=args.sampling, blocks=args.blocks)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -556,7 +558,8 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) / 1e3) / 1e9
     del src, dst
-    cpu = cpu_baseline(Xnp, w, sampling=args.sampling, threads=args.cpu_threads) if with_cpu else None
+    cpu = cpu_baseline(Xnp, w, sampling=args.sampling, threads=args.cpu_threads, blocks=args.blocks) \
+        if with_cpu else None
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
     if kernel == "k_join_split":
@@ -576,7 +579,7 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
                    "delta": w["delta"], "max_iters": w["max_iters"], "seed": w["seed"],
                    "reorder": int(args.reorder),
                    "path": {knng.PATH_MFMA: "mfma", knng.PATH_MFMA_BF16X3: "bf16x3"}.get(s0["path"], "valu"),
-                   "precision": args.precision, "sampling": args.sampling},
+                   "precision": args.precision, "sampling": args.sampling, "blocks": args.blocks},
         "iters": s0["iters"], "evals_per_build": evals, "recall": rec, "recall_plain": rec_plain,
         "ms_to_recall_0.99": t99,
         "recall_rows": None if no_recall else int(min(w["N"], recall_rows)),

@@ -131,6 +131,13 @@ typedef struct {
                            (Sec. 3.2 applies it after the first); 0: off; at most 64 */
     int32_t path;       /* knng_path */
     int32_t sampling;   /* knng_sampling (Sec. 3.1) */
+    int32_t blocks;     /* 0 or 1: synchronous iterations. B > 1 (B <= N): block-asynchronous
+                           iterations, the paper's in-place update (Sec. 3.1) at block
+                           granularity: the owners are taken in B blocks of consecutive
+                           original ids, in order; block b samples from the graph as blocks
+                           0..b-1 of the iteration left it, only its owners sample, flip and
+                           join, and their proposals are merged into every list before block
+                           b + 1 samples. Deterministic; e_t and c_t add up over the blocks. */
 } knng_params;
 
 #define KNNG_MAX_ITERS 64

@@ -45,7 +45,8 @@ class KnngError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("rho", ctypes.c_double), ("delta", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("path", ctypes.c_int32), ("sampling", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("path", ctypes.c_int32), ("sampling", ctypes.c_int32),
+                ("blocks", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -109,13 +110,13 @@ _PRECISIONS = {"fp32": PRECISION_FP32, "bf16": PRECISION_BF16_SCREEN}
 
 def make_params(K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
                 reorder: bool | int = False, path: str | int = "auto", precision: str | int = "fp32",
-                sampling: str | int = "weighted") -> Params:
+                sampling: str | int = "weighted", blocks: int = 0) -> Params:
     pth = _PATHS[path] if isinstance(path, str) else int(path)
     prc = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     smp = _SAMPLING[sampling] if isinstance(sampling, str) else int(sampling)
     # reorder: False/0 off, True/1 after iteration 1, an int t_p after iteration t_p
     return Params(int(K), float(rho), float(delta), int(max_iters), int(seed) & 0xFFFFFFFFFFFFFFFF, prc,
-                  int(reorder), pth, smp)
+                  int(reorder), pth, smp, int(blocks))
 
 
 def sample_cap(K: int, rho: float) -> int:
@@ -153,7 +154,8 @@ def _stats_dict(s: _Stats) -> dict:
 
 def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30, seed: int = 0,
           reorder: bool | int = False, path: str | int = "auto", workspace: torch.Tensor | None = None,
-          out: tuple | None = None, precision: str | int = "fp32", sampling: str | int = "weighted"):
+          out: tuple | None = None, precision: str | int = "fp32", sampling: str | int = "weighted",
+          blocks: int = 0):
     """K-NN graph of the rows of X (device float32 [N, d]).
 
     Returns (ids int32 [N, K], dists float32 [N, K] squared l2, stats dict);
@@ -162,7 +164,7 @@ def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_i
     """
     _check_x(X)
     N, d = X.shape
-    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling, blocks)
     ws = workspace_bytes(N, d, p)
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(ws, dtype=torch.uint8, device=X.device)
@@ -180,7 +182,8 @@ def build(X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_i
 
 def build_noalloc(X: torch.Tensor, K: int, ids: torch.Tensor, dists: torch.Tensor, rho: float = 1.0,
                   delta: float = 0.001, max_iters: int = 30, seed: int = 0, reorder: bool | int = False,
-                  path: str | int = "auto", precision: str | int = "fp32", sampling: str | int = "weighted") -> dict:
+                  path: str | int = "auto", precision: str | int = "fp32", sampling: str | int = "weighted",
+                  blocks: int = 0) -> dict:
     """knng_build_noalloc: the build with the library's static device scratch
     as workspace (nothing allocated). The caller passes the outputs ids
     (int32 [N, K]) and dists (float32 [N, K]); returns the stats dict (no
@@ -193,7 +196,7 @@ def build_noalloc(X: torch.Tensor, K: int, ids: torch.Tensor, dists: torch.Tenso
         raise ValueError("ids / dists must be int32 / float32 [N, K]")
     if not (ids.is_contiguous() and dists.is_contiguous()):
         raise ValueError("ids / dists must be contiguous")
-    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
+    p = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling, blocks)
     st = _Stats()
     _check(lib.knng_build_noalloc(ctypes.c_void_p(X.data_ptr()), N, d, ctypes.byref(p),
                                   ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(dists.data_ptr()),
@@ -213,12 +216,12 @@ class Context:
 
     def __init__(self, X: torch.Tensor, K: int, rho: float = 1.0, delta: float = 0.001, max_iters: int = 30,
                  seed: int = 0, reorder: bool | int = False, path: str | int = "auto", precision: str | int = "fp32",
-                 sampling: str | int = "weighted"):
+                 sampling: str | int = "weighted", blocks: int = 0):
         _check_x(X)
         self.X = X
         self.N, self.d = X.shape
         self.K = K
-        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling)
+        self.params = make_params(K, rho, delta, max_iters, seed, reorder, path, precision, sampling, blocks)
         self.C = sample_cap(K, rho)
         self.ws_bytes = workspace_bytes(self.N, self.d, self.params)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=X.device)

@@ -85,6 +85,7 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
     if (p->precision != KNNG_FP32 && p->precision != KNNG_BF16_SCREEN) return fail(KNNG_EINVAL, "unknown precision");
     if (p->path < KNNG_PATH_AUTO || p->path > KNNG_PATH_MFMA_BF16X3) return fail(KNNG_EINVAL, "unknown path");
     if (p->reorder < 0 || p->reorder > KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "reorder must be in [0, 64]");
+    if (p->blocks < 0 || (int64_t)p->blocks > N) return fail(KNNG_EINVAL, "blocks must be in [0, N]");
     if (p->sampling != KNNG_SAMPLING_WEIGHTED && p->sampling != KNNG_SAMPLING_TURBO)
         return fail(KNNG_EINVAL, "unknown sampling rule");
     if (N * (int64_t)p->K >= (1LL << 31)) return fail(KNNG_EINVAL, "N*K must be < 2^31");
@@ -427,34 +428,51 @@ hipEvent_t* phase_events(knng_ctx* c, int t) { return (t & 1) ? &c->ev[0] : &c->
 // Enqueues iteration t (sampling, join, merge). thr >= 0: the device records
 // whether the stop rule held (changes < thr) so that an iteration enqueued
 // ahead of the host's decision returns at once.
+// Block-asynchronous iterations (params.blocks = B > 1) enqueue B rounds of
+// the same steps: round b samples and joins only the owners with original
+// ids in [N b / B, N (b + 1) / B) from the graph the earlier rounds left, and
+// its merge updates every list before round b + 1 samples; the counters add
+// up over the rounds. Phase events: sampling from the first round's start,
+// the last round's join and merge.
 knng_status enqueue_iteration(knng_ctx* c, int t, double thr) {
     const Views& v = c->v;
     hipStream_t s = c->stream;
     hipEvent_t* E = phase_events(c, t);
     const uint64_t st = stream_state(c->p.seed, 2, (uint64_t)t);
-    // counters and proposal-bucket cursors are cleared by the previous merge
-    // (and at create); the atomic reverse path counts into rdeg and rcur
-    if (!v.rev_S) launch_fill_u32(v.rdeg, 0u, 2 * (int64_t)v.N, s);
-    // phase events: start of sampling (E0), start / end of the join (E1,
-    // E2), end of the merge (E3), stamped by the dispatches themselves
-    if (v.rev_S) {
-        launch_rev_partition(v, st, t, s, E[0]);
-    } else {
-        launch_rev_hist(v, s, E[0]);
-        launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
-        launch_rev_scatter(v, st, t, s);
+    const int B = c->p.blocks > 1 ? c->p.blocks : 1;
+    for (int b = 0; b < B; ++b) {
+        const bool first = b == 0, last = b == B - 1;
+        Views vb = v;
+        if (B > 1) {
+            vb.blk_on = 1;
+            vb.blk_lo = (int)((int64_t)v.N * b / B);
+            vb.blk_hi = (int)((int64_t)v.N * (b + 1) / B);
+        }
+        // counters and proposal-bucket cursors are cleared by the previous merge
+        // (and at create); the atomic reverse path counts into rdeg and rcur
+        if (!v.rev_S) launch_fill_u32(v.rdeg, 0u, 2 * (int64_t)v.N, s);
+        // phase events: start of sampling (E0), start / end of the join (E1,
+        // E2), end of the merge (E3), stamped by the dispatches themselves
+        hipEvent_t e0 = first ? E[0] : nullptr, e1 = last ? E[1] : nullptr, e2 = last ? E[2] : nullptr;
+        if (v.rev_S) {
+            launch_rev_partition(v, st, t, s, e0);
+        } else {
+            launch_rev_hist(v, s, e0);
+            launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
+            launch_rev_scatter(v, st, t, s);
+        }
+        launch_select(vb, st, t, s);
+        if (c->plan.bf16)
+            launch_join_bf16(vb, s, e1, e2);
+        else if (c->plan.path == KNNG_PATH_MFMA_BF16X3)
+            launch_join_split(vb, s, e1, e2);
+        else if (c->plan.path == KNNG_PATH_MFMA)
+            launch_join_mfma(vb, s, e1, e2);
+        else
+            launch_join_valu(vb, s, e1, e2);
+        launch_merge(v, s);
+        launch_finish_counters(v, s, last ? E[3] : nullptr, c->dslot + (size_t)t * kNumCounters, thr, last ? 1 : 0);
     }
-    launch_select(v, st, t, s);
-    if (c->plan.bf16)
-        launch_join_bf16(v, s, E[1], E[2]);
-    else if (c->plan.path == KNNG_PATH_MFMA_BF16X3)
-        launch_join_split(v, s, E[1], E[2]);
-    else if (c->plan.path == KNNG_PATH_MFMA)
-        launch_join_mfma(v, s, E[1], E[2]);
-    else
-        launch_join_valu(v, s, E[1], E[2]);
-    launch_merge(v, s);
-    launch_finish_counters(v, s, E[3], c->dslot + (size_t)t * kNumCounters, thr);
     HIP_TRY(hipGetLastError());
     return KNNG_OK;
 }
@@ -928,6 +946,7 @@ knng_status batch_validate(const knng_dataset* descs, int32_t n, const knng_para
     if (!descs || n < 1) return fail(KNNG_EINVAL, "no datasets");
     if (!p) return fail(KNNG_EINVAL, "params is NULL");
     if (p->reorder) return fail(KNNG_EINVAL, "the batched form runs without the permutation");
+    if (p->blocks > 1) return fail(KNNG_EINVAL, "the batched form runs synchronous iterations");
     if (p->precision != KNNG_FP32) return fail(KNNG_EINVAL, "the batched form runs in FP32");
     if (p->max_iters < 1) return fail(KNNG_EINVAL, "the batched form needs max_iters >= 1");
     for (int i = 0; i < n; ++i) {

@@ -50,6 +50,8 @@ struct Views {
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
     int permuted;       // 0 until the graph-ordered permutation ran: position = original id
+    int blk_on, blk_lo, blk_hi;   // block-asynchronous iteration: only owners with original
+                                  // ids in [blk_lo, blk_hi) sample and join (blk_on != 0)
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
     uint32_t* lpos;     // [N, K] position of the neighbour | kNewBit
     uint64_t* kth;      // [N] the list's K-th key (lkey[p, K-1]), written with the list: the joins'
@@ -160,7 +162,7 @@ void launch_merge(const Views& v, hipStream_t s);
 // (host-visible, may be null) receives a copy of all counters, which are then
 // cleared for the next iteration; thr >= 0 sets *v.stop when changes < thr or
 // a device invariant failed.
-void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr);
+void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr, int last = 1);
 constexpr int kStopFlag = 12;   // index of the stop word in the device flags
 void launch_finalize(const Views& v, int32_t* ids, float* dists, uint8_t* flags, hipStream_t s);
 void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t* counts, hipStream_t s);

@@ -1409,9 +1409,12 @@ __device__ __forceinline__ void select_pool_x2(const Views& v, uint64_t st0, int
     pool_finish<64>(v, ub, kb, ib, pb);
 }
 
-// Pool size of owner u (0: past N, or its dataset has finished).
+// Pool size of owner u (0: past N, its dataset has finished, or it is not an
+// owner of the current block of a block-asynchronous iteration: then it
+// samples nothing, flips nothing and joins nothing).
 __device__ __forceinline__ int pool_size(const Views& v, int u) {
     if (u >= v.N || (v.ds && !pos_active(v, u))) return 0;
+    if (v.blk_on && (v.orig[u] < v.blk_lo || v.orig[u] >= v.blk_hi)) return 0;   // not this block's owner
     return v.K + (int)(v.roff[u + 1] - v.roff[u]);
 }
 
@@ -2605,11 +2608,13 @@ __global__ __launch_bounds__(256, 8) void k_merge(Views v) {
 }
 
 // Counters of an iteration, by one workgroup of 1024 threads after the
-// merge kernels have written their partial sums: c_t, proposals and e_t summed;
-// all counters copied to the host-visible slot (may be null) and cleared for
-// the next iteration; thr >= 0 sets *v.stop when changes < thr or a device
-// invariant failed.
-__device__ void finish_counters_block(const Views& v, uint64_t* slot, double thr) {
+// merge kernels have written their partial sums: c_t, proposals and e_t added
+// up; after the iteration's last merge (last != 0; every block of a
+// block-asynchronous iteration but the last adds its sums and clears the hub
+// list only) all counters are copied to the host-visible slot (may be null)
+// and cleared for the next iteration, and thr >= 0 sets *v.stop when
+// changes < thr or a device invariant failed.
+__device__ void finish_counters_block(const Views& v, uint64_t* slot, double thr, int last) {
     __shared__ uint64_t s_a[16], s_b[16], s_c[16];
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const uint64_t* part = v.partial;
@@ -2638,15 +2643,19 @@ __device__ void finish_counters_block(const Views& v, uint64_t* slot, double thr
             sc += s_c[i];
         }
         uint64_t* cnt = v.counters;
-        cnt[kCntChanges] = sa;
-        cnt[kCntProposals] = sb;
-        cnt[kCntPairs2] = 2ull * sc;
+        cnt[kCntChanges] += sa;
+        cnt[kCntProposals] += sb;
+        cnt[kCntPairs2] += 2ull * sc;
+        if (!last) {
+            cnt[kCntHubs] = 0ull;   // the next block's merge lists its own hubs
+            return;
+        }
         if (slot) {
             for (int i = 0; i < kNumCounters; ++i) slot[i] = cnt[i];
             __threadfence_system();
         }
         if (thr >= 0.0 && v.stop) {
-            const bool met = (double)sa < thr || cnt[kCntError] != 0ull;
+            const bool met = (double)cnt[kCntChanges] < thr || cnt[kCntError] != 0ull;
             *v.stop = met ? 1u : 0u;
         }
         for (int i = 0; i < kNumCounters; ++i) cnt[i] = 0ull;
@@ -2699,13 +2708,13 @@ void launch_merge(const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_merge_hubs, dim3(kHubBlocks), dim3(1024), 0, s, v);
 }
 
-__global__ __launch_bounds__(1024) void k_finish_counters(Views v, uint64_t* slot, double thr) {
+__global__ __launch_bounds__(1024) void k_finish_counters(Views v, uint64_t* slot, double thr, int last) {
     if (stopped(v)) return;
-    finish_counters_block(v, slot, thr);
+    finish_counters_block(v, slot, thr, last);
 }
 
-void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr) {
-    launch_timed(k_finish_counters, dim3(1), dim3(1024), 0, s, nullptr, e1, v, slot, thr);
+void launch_finish_counters(const Views& v, hipStream_t s, hipEvent_t e1, uint64_t* slot, double thr, int last) {
+    launch_timed(k_finish_counters, dim3(1), dim3(1024), 0, s, nullptr, e1, v, slot, thr, last);
 }
 
 size_t partial_words() { return 3 * (size_t)(kMergeBlocks + kHubBlocks); }

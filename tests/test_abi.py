@@ -64,6 +64,8 @@ def _params(**kw):
     (100, 784, dict(path="mfma_i8"), "not available"),
     (100, 8, dict(sampling=2), "unknown sampling"),
     (100, 8, dict(reorder=-1), "reorder"),
+    (100, 8, dict(blocks=-1), "blocks"),
+    (100, 8, dict(blocks=101), "blocks"),
     (100, 8, dict(reorder=65), "reorder"),
 ])
 def test_workspace_query_rejects(N, d, kw, msg):
@@ -137,3 +139,31 @@ def test_header_path_values_match_binding():
     assert vals == {"KNNG_PATH_AUTO": knng.PATH_AUTO, "KNNG_PATH_VALU": knng.PATH_VALU,
                     "KNNG_PATH_MFMA": knng.PATH_MFMA, "KNNG_PATH_MFMA_I8": knng.PATH_MFMA_I8,
                     "KNNG_PATH_MFMA_BF16X3": knng.PATH_MFMA_BF16X3}
+
+
+def _header_struct_fields(name):
+    """(type, field) pairs of a `typedef struct { ... } name;` in knng.h."""
+    import re
+    text = open(HDR).read()
+    m = re.search(r"typedef struct \{([^{}]*)\} " + name + ";", text)
+    assert m, name
+    body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        toks = decl.replace("*", " * ").split()
+        field = toks[-1].split("[")[0]
+        out.append((" ".join(toks[:-1]), field))
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("knng_params", "Params"), ("knng_stats", "_Stats"),
+                                          ("knng_dataset", "_Dataset")])
+def test_binding_structs_follow_the_header(cname, pyname):
+    """The ctypes mirrors of the ABI structs have the header's fields, in order."""
+    import paper_2112_06630_amd as knng
+    hdr = [f for _, f in _header_struct_fields(cname)]
+    py = [f for f, _ in getattr(knng, pyname)._fields_]
+    assert hdr == py

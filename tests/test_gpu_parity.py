@@ -532,3 +532,59 @@ def test_bf16_screen_with_permutation(knng):
     a = knng.build(dev(X), 12, 0.5, 0.001, 20, 5, precision="bf16", reorder=False)
     b = knng.build(dev(X), 12, 0.5, 0.001, 20, 5, precision="bf16", reorder=True)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ----------------------------------------------------------------- block-asynchronous iteration
+
+@pytest.mark.parametrize("path,d", [("valu", 8), ("bf16x3", 72), ("mfma", 72)])
+@pytest.mark.parametrize("B,reorder", [(4, 0), (16, 0), (5, 2)])
+def test_block_async_integer_bitwise(knng, path, d, B, reorder):
+    """Block-asynchronous builds (blocks of consecutive owner ids in order,
+    each sampling from the graph the earlier blocks left) equal the oracle's
+    block mode bit for bit on integer data: graph, e_t, c_t and the iteration
+    count, also with the permutation running between iterations (blocks stay
+    defined on original ids)."""
+    X = synth.integer_points(1500, d, 9, 31)
+    ref = oracle.build_graph(X, 12, 0.8, 0.001, 15, 5, blocks=B)
+    ids, dists, st = knng.build(dev(X), 12, 0.8, 0.001, 15, 5, path=path, reorder=reorder, blocks=B)
+    assert st["iters"] == ref.iters
+    assert st["evals"] == ref.evals.tolist() and st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)
+    sync = oracle.build_graph(X, 12, 0.8, 0.001, 15, 5)
+    assert sync.evals.tolist() != ref.evals.tolist()   # the blocks do change the trajectory
+
+
+@pytest.mark.parametrize("sampling", ["weighted", "turbo"])
+def test_block_async_continuous_build(knng, sampling):
+    """Continuous data (the Gaussian mixture far from the origin, split form
+    with FP64 accumulation), block-asynchronous builds: inside one iteration
+    a near-tie that FP32 decides otherwise than FP64 in an early block changes
+    what the later blocks sample, so the GPU is compared with the oracle's
+    block-mode build over the trajectory: rows valid and sorted, stored
+    distances within the bound, the evaluation counts within 1% (200 in the
+    last, small iterations; the total within 0.5%), and the recall within
+    0.005 of the oracle's."""
+    X = synth.gaussian_mixture(3000, 96, 10, 10)
+    K, rho, seed, B = 16, 1.0, 10, 6
+    ref = oracle.build_graph(X, K, rho, 0.001, 30, seed, sampling=sampling, blocks=B)
+    ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, seed, path="bf16x3", sampling=sampling, blocks=B)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    D64, bound = fp32_bound(X, ids, 96, True, accurate=True)
+    assert (np.abs(dists.astype(np.float64) - D64) <= bound).all()
+    assert all(len(set(r.tolist())) == K for r in ids)
+    assert not (ids == np.arange(X.shape[0])[:, None]).any()
+    assert ((dists[:, 1:] > dists[:, :-1]) | ((dists[:, 1:] == dists[:, :-1]) & (ids[:, 1:] > ids[:, :-1]))).all()
+    n = min(len(st["evals"]), len(ref.evals))
+    assert abs(len(st["evals"]) - len(ref.evals)) <= 1
+    assert np.allclose(st["evals"][:n], ref.evals[:n], rtol=0.01, atol=200)
+    assert abs(sum(st["evals"]) - int(ref.evals.sum())) <= 0.005 * int(ref.evals.sum())
+    _, ed = oracle.bruteforce(X, K)
+    assert oracle.recall(X, ids, ed) >= oracle.recall(X, ref.ids, ed) - 0.005
+
+
+def test_block_async_one_block_is_synchronous(knng):
+    X, p = synth.workload("gauss2k_d8")
+    a = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], blocks=0)
+    b = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], blocks=1)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2]["evals"] == b[2]["evals"]

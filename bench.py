@@ -447,7 +447,8 @@ def join_roofline(knng, w, s0, stats, members, precision):
     join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
     dpad = s0["dpad"]
     alg = [m * (4 * dpad + 8) + 8 * pr for m, pr in zip(members, s0["proposals"])]
-    enc_row = {"k_join_split": 2 * dpad * max(1, s0["planes"]), "k_join_bf16": 2 * dpad}.get(kernel, 4 * dpad)
+    enc_row = {"k_join_split": (dpad if s0.get("u8") else 2 * dpad * max(1, s0["planes"])),
+               "k_join_bf16": 2 * dpad}.get(kernel, 4 * dpad)
     enc = [m * (enc_row + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
     flops = [e * 2 * w["d"] for e in s0["evals"]]
     sec = sum(join_ms) / 1e3
@@ -563,7 +564,7 @@ def measure(args, w, steps, warmup, recall_rows, with_cpu):
     if cpu is not None and args.precision != "fp32":
         cpu["sample"] += " (the oracle computes FP64 distances)"
     if kernel == "k_join_split":
-        dtype = "f32" if s0["planes"] == 3 else f"bf16x{s0['planes']}+f32"
+        dtype = "u8+f32" if s0.get("u8") else ("f32" if s0["planes"] == 3 else f"bf16x{s0['planes']}+f32")
     else:
         dtype = {"k_join_bf16": "bf16+f32"}.get(kernel, "f32")
 

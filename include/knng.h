@@ -154,7 +154,8 @@ typedef struct {
     int32_t accurate;                     /* matrix paths: 1 when FP32 sums of X are not exact (see
                                              knng_path), so dot products are summed in FP64 per
                                              32 dimensions; 0 where every FP32 sum is exact */
-    int32_t reserved;
+    int32_t u8;                           /* split form on 8-bit data (integers 0..255): 1 when the
+                                             join reads the rows as bytes */
     int64_t evals[KNNG_MAX_ITERS];        /* e_t: distance evaluations of iteration t */
     int64_t changes[KNNG_MAX_ITERS];      /* c_t: ids that entered a list */
     int64_t proposals[KNNG_MAX_ITERS];    /* proposals that passed the snapshot filter */

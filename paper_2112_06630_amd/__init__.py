@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("dpad", ctypes.c_int32), ("precision", ctypes.c_int32), ("planes", ctypes.c_int32),
-                ("accurate", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("accurate", ctypes.c_int32), ("u8", ctypes.c_int32),
                 ("evals", ctypes.c_int64 * MAX_ITERS), ("changes", ctypes.c_int64 * MAX_ITERS),
                 ("proposals", ctypes.c_int64 * MAX_ITERS), ("rescored", ctypes.c_int64 * MAX_ITERS),
                 ("iter_ms", ctypes.c_float * MAX_ITERS), ("sample_ms", ctypes.c_float * MAX_ITERS),
@@ -144,7 +144,7 @@ def _check_x(X: torch.Tensor):
 def _stats_dict(s: _Stats) -> dict:
     it = s.iters
     return dict(iters=it, converged=bool(s.converged), path=s.path, dpad=s.dpad, precision=s.precision,
-                planes=s.planes, accurate=s.accurate,
+                planes=s.planes, accurate=s.accurate, u8=s.u8,
                 evals=list(s.evals[:it]), changes=list(s.changes[:it]), proposals=list(s.proposals[:it]),
                 rescored=list(s.rescored[:it]),
                 iter_ms=list(s.iter_ms[:it]), sample_ms=list(s.sample_ms[:it]), join_ms=list(s.join_ms[:it]),

@@ -694,6 +694,9 @@ knng_status ctx_init(knng_ctx* c, const Plan& P, const float* dX, int64_t N, int
         const uint64_t used = c->hc[kCntSplit];
         c->v.planes = (used & 2u) ? 3 : (used & 1u) ? 2 : 1;
         c->stats.planes = c->v.planes;
+        // 8-bit data: integers in 0..255 with exact FP32 sums read as byte rows
+        c->v.u8 = c->v.planes == 1 && !c->v.acc && !(used & 16u) ? 1 : 0;
+        c->stats.u8 = c->v.u8;
         if (c->v.planes > 1) launch_prep_rest(dX, c->v, c->stream);
         if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
             c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)

@@ -22,7 +22,8 @@ enum Counter : int {
     kCntError = 3,       // nonzero: a device-side invariant failed
     kCntNonFinite = 4,   // nonzero: X holds a NaN or an infinity
     kCntSplit = 5,       // layout pass: bit 0 some x2 != 0, bit 1 some x3 != 0 (split-BF16 copies),
-                         // bit 2 some value is not an integer, bit 3 some squared norm exceeds 2^23
+                         // bit 2 some value is not an integer, bit 3 some squared norm exceeds 2^23,
+                         // bit 4 some value is outside 0..255
     kCntHubs = 6,        // targets whose proposal bucket is merged by a workgroup
     kCntRescored = 7,    // precision form: pairs that passed the BF16 screen and were rescored
     kNumCounters = 8
@@ -47,6 +48,8 @@ struct Views {
     float2* nb;         // [N] BF16 rows: {squared norm, norm of the rounding error bf16(x) - x}
     uint16_t* Xs;       // [3, N, dp] split-BF16 copies x = x1 + x2 + x3 (split form), else null
     int planes;         // split form: leading planes the join reads (1..3; the rest are all zero)
+    int u8;             // split form on 8-bit data (integers 0..255, FP32 sums exact): the join and
+                        // the initial distances read byte rows, Xs + N dp (the unused second plane)
     int32_t* orig;      // [N] position -> original id
     int32_t* posof;     // [N] original id -> position
     int permuted;       // 0 until the graph-ordered permutation ran: position = original id

@@ -364,6 +364,20 @@ __device__ __forceinline__ float chunk8_dot(const float4* __restrict__ a, const 
     return chunk_dot(a[2 * c + 1], b[2 * c + 1], s);
 }
 
+// byte rows: the same 8 products and sums in dimension order (every byte is
+// exact in BF16 and FP32, so the value equals the BF16-plane one bit for bit)
+__device__ __forceinline__ float chunk8_dot(const uint2* __restrict__ a, const uint2* __restrict__ b, int c,
+                                            float s) {
+    const uint2 x = a[c], y = b[c];
+    const uint32_t av[2] = {x.x, x.y}, bv[2] = {y.x, y.y};
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s = fmaf((float)((av[q] >> (8 * k)) & 0xffu), (float)((bv[q] >> (8 * k)) & 0xffu), s);
+    return s;
+}
+
 __device__ __forceinline__ float chunk8_dot(const uint4* __restrict__ a, const uint4* __restrict__ b, int c,
                                             float s) {
     const uint4 x = a[c], y = b[c];
@@ -474,7 +488,10 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     float Dg = 0.f;
     if (mode == kDistGram) {   // whole wave
         const bool plane = v.Xs && v.planes == 1;
-        if (v.acc && plane)
+        if (v.u8)
+            Dg = wave_gram_dists(reinterpret_cast<const uint2*>(v.Xs + (size_t)v.N * v.dp), v.dp >> 3, v.dp >> 3, u,
+                                 pid, K, v.nrm);
+        else if (v.acc && plane)
             Dg = wave_gram_dists64(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, v.dp >> 3, u, pid, K, v.nrm64);
         else if (v.acc)
             Dg = wave_gram_dists64(reinterpret_cast<const float4*>(v.Xp), v.dp >> 2, v.dp >> 3, u, pid, K, v.nrm64);
@@ -2082,6 +2099,17 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
             s3 = fma((double)q.w, (double)q.w, s3);
             if (q.x != rintf(q.x) || q.y != rintf(q.y) || q.z != rintf(q.z) || q.w != rintf(q.w)) used |= 4u;
             if (split) {
+                // byte rows (read instead of plane 1 when every value is an integer in 0..255)
+                const float e8[4] = {q.x, q.y, q.z, q.w};
+                uint32_t packed = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bool in = e8[c] >= 0.f && e8[c] <= 255.f;
+                    if (!in) used |= 16u;
+                    packed |= (in ? (uint32_t)e8[c] : 0u) << (8 * c);
+                }
+                *reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(v.Xs + (size_t)v.N * dp) + (size_t)r * dp + j) =
+                    packed;
                 const float e[4] = {q.x, q.y, q.z, q.w};
                 uint16_t b1[4];
 #pragma unroll
@@ -2110,9 +2138,9 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
         }
     }
     const uint64_t m1 = ballot((used & 1u) != 0), m2 = ballot((used & 2u) != 0), mb = ballot(bad);
-    const uint64_t m4 = ballot((used & 4u) != 0), m8 = ballot((used & 8u) != 0);
+    const uint64_t m4 = ballot((used & 4u) != 0), m8 = ballot((used & 8u) != 0), m16 = ballot((used & 16u) != 0);
     if (lane == 0) {
-        const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u) | (m4 ? 4u : 0u) | (m8 ? 8u : 0u);
+        const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u) | (m4 ? 4u : 0u) | (m8 ? 8u : 0u) | (m16 ? 16u : 0u);
         if (wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
         if (mb) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
     }
@@ -2172,9 +2200,20 @@ void launch_prep_rest(const float* X, const Views& v, hipStream_t s) {
 // FP32 over all steps as before. x.y = S64 + (R + Q) in FP64 is still the
 // same value with x and y exchanged, and the distance is formed from FP64
 // norms in FP64 and rounded once.
-template <int MaxCT, int Planes, bool Acc>
-__global__ __launch_bounds__(256, MaxCT <= 2 ? ((Acc && Planes == 3) ? 3 : 4) : (MaxCT <= 3 && !(Acc && Planes >= 2)) ? 3 : 2)
+// U8 (8-bit data, one plane, FP32 sums exact): the rows are read as bytes
+// (half the bytes of the BF16 plane) and widened to BF16 in registers, each
+// byte exactly; the tiles and their order are those of the plane form, so
+// every distance is bit-identical to it.
+__device__ __forceinline__ uint32_t u8x2_to_bf16x2(uint32_t w, int k) {
+    const uint32_t lo = __float_as_uint((float)((w >> (8 * k)) & 0xffu));
+    const uint32_t hi = __float_as_uint((float)((w >> (8 * k + 8)) & 0xffu));
+    return (lo >> 16) | (hi & 0xffff0000u);
+}
+
+template <int MaxCT, int Planes, bool Acc, bool U8 = false>
+__global__ __launch_bounds__(256, U8 ? (MaxCT <= 2 ? 6 : MaxCT <= 3 ? 5 : 3) : MaxCT <= 2 ? ((Acc && Planes == 3) ? 3 : 4) : (MaxCT <= 3 && !(Acc && Planes >= 2)) ? 3 : 2)
 void k_join_split(Views v) {
+    static_assert(!U8 || (Planes == 1 && !Acc), "byte rows carry one exact plane");
     if (stopped(v)) return;
     constexpr int kSplitTiles = 2 * MaxCT - 1;
     __shared__ uint64_t s_thr[kJoinWaves][64];
@@ -2213,9 +2252,14 @@ void k_join_split(Views v) {
         const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
         // lanes past the last member read member m-1; their outputs are never used
         const uint16_t* rp[MaxCT];
+        const uint8_t* rb[MaxCT];
+        const uint8_t* bytes = reinterpret_cast<const uint8_t*>(v.Xs + plane);
 #pragma unroll
-        for (int ct = 0; ct < MaxCT; ++ct)
-            rp[ct] = v.Xs + (size_t)s_pos[w][min(ct * 16 + c16, m - 1)] * dp + g * 8;
+        for (int ct = 0; ct < MaxCT; ++ct) {
+            const size_t row = (size_t)s_pos[w][min(ct * 16 + c16, m - 1)] * dp + g * 8;
+            rp[ct] = v.Xs + row;
+            rb[ct] = bytes + row;
+        }
         floatx4 aS[kSplitTiles], aR[kSplitTiles], aQ[kSplitTiles];
         double a64[Acc ? kSplitTiles : 1][4];
 #pragma unroll
@@ -2227,14 +2271,57 @@ void k_join_split(Views v) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) a64[t][r] = 0.0;
         }
-        for (int k0 = 0; k0 < dp; k0 += 32) {
+        int k0 = 0;
+        if constexpr (U8) {
+            // 64 dimensions per step: each lane loads 16 bytes (half the load
+            // instructions of 8-byte loads) and feeds two instructions; lane
+            // (c16, g) takes bytes [k0 + 16 g, k0 + 16 g + 16) of its row for
+            // both operands, so every instruction pairs the same dimensions
+            // (exact sums: the order of the partial products is free)
+            const uint8_t* rw[MaxCT];
+#pragma unroll
+            for (int ct = 0; ct < MaxCT; ++ct) rw[ct] = rb[ct] + g * 8;
+            for (; k0 + 64 <= dp; k0 += 64) {
+                bf16x8 lo[MaxCT], hi[MaxCT];
+#pragma unroll
+                for (int ct = 0; ct < MaxCT; ++ct) {
+                    uint4 b16 = make_uint4(0u, 0u, 0u, 0u);
+                    if (ct < CT) b16 = *reinterpret_cast<const uint4*>(rw[ct] + k0);
+                    lo[ct] = __builtin_bit_cast(bf16x8, make_uint4(u8x2_to_bf16x2(b16.x, 0), u8x2_to_bf16x2(b16.x, 2),
+                                                                   u8x2_to_bf16x2(b16.y, 0), u8x2_to_bf16x2(b16.y, 2)));
+                    hi[ct] = __builtin_bit_cast(bf16x8, make_uint4(u8x2_to_bf16x2(b16.z, 0), u8x2_to_bf16x2(b16.z, 2),
+                                                                   u8x2_to_bf16x2(b16.w, 0), u8x2_to_bf16x2(b16.w, 2)));
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int t = 0;
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                        for (int ct = rt; ct < MaxCT; ++ct, ++t) {
+                            if (!(rt < RT && ct < CT)) continue;
+                            aS[t] = h ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[rt], hi[ct], aS[t], 0, 0, 0)
+                                      : __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[rt], lo[ct], aS[t], 0, 0, 0);
+                        }
+                }
+            }
+        }
+        for (; k0 < dp; k0 += 32) {
             bf16x8 f[Planes][MaxCT];
 #pragma unroll
             for (int q = 0; q < Planes; ++q)
 #pragma unroll
                 for (int ct = 0; ct < MaxCT; ++ct) {
                     uint4 raw = make_uint4(0u, 0u, 0u, 0u);
-                    if (ct < CT) raw = *reinterpret_cast<const uint4*>(rp[ct] + q * plane + k0);
+                    if constexpr (U8) {
+                        if (ct < CT) {
+                            const uint2 b8 = *reinterpret_cast<const uint2*>(rb[ct] + k0);
+                            raw = make_uint4(u8x2_to_bf16x2(b8.x, 0), u8x2_to_bf16x2(b8.x, 2), u8x2_to_bf16x2(b8.y, 0),
+                                             u8x2_to_bf16x2(b8.y, 2));
+                        }
+                    } else {
+                        if (ct < CT) raw = *reinterpret_cast<const uint4*>(rp[ct] + q * plane + k0);
+                    }
                     f[q][ct] = __builtin_bit_cast(bf16x8, raw);
                 }
             // product kinds outer, tiles inner: consecutive instructions go to
@@ -2321,6 +2408,12 @@ void k_join_split(Views v) {
 template <int MaxCT, bool Acc>
 static void launch_join_split_ct(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
+    if constexpr (!Acc) {
+        if (v.u8) {
+            launch_timed(k_join_split<MaxCT, 1, false, true>, g, dim3(256), 0, s, e0, e1, v);
+            return;
+        }
+    }
     if (v.planes == 1)
         launch_timed(k_join_split<MaxCT, 1, Acc>, g, dim3(256), 0, s, e0, e1, v);
     else if (v.planes == 2)
@@ -3045,6 +3138,20 @@ __global__ void k_perm_rows_split(Views v) {
     }
 }
 
+__global__ void k_perm_rows_u8(Views v) {
+    const int dp8 = v.dp >> 3;   // 8-byte groups per byte row
+    const int64_t total = (int64_t)v.N * dp8;
+    const size_t plane = (size_t)v.N * v.dp;
+    const uint2* src = reinterpret_cast<const uint2*>(reinterpret_cast<const uint8_t*>(v.Xs + plane));
+    uint2* dst = reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(v.Xs2 + plane));
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(i / dp8), c = (int)(i - (int64_t)p * dp8);
+        const int np = v.newpos[p];
+        if (np < 0 || np >= v.N) continue;  // reported by k_perm_rows
+        dst[(size_t)np * dp8 + c] = src[(size_t)p * dp8 + c];
+    }
+}
+
 __global__ void k_perm_lists(Views v) {
     const int64_t NK = (int64_t)v.N * v.K;
     const double rk = 1.0 / v.K;
@@ -3100,6 +3207,8 @@ void launch_perm_finish(const Views& v, uint32_t levels, hipStream_t s) {
     if (v.Xs)
         hipLaunchKernelGGL(k_perm_rows_split, dim3(grid_for(3 * (int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256),
                            0, s, v);
+    if (v.u8)
+        hipLaunchKernelGGL(k_perm_rows_u8, dim3(grid_for((int64_t)v.N * (v.dp >> 3), 256, 16384)), dim3(256), 0, s, v);
 }
 
 void launch_perm_posof(const Views& v, hipStream_t s) {

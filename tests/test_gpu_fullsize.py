@@ -61,6 +61,7 @@ def test_image60k_bitwise(knng, image60k, path, reorder, want):
                                 path=path, reorder=reorder)
     assert st["path"] == want
     assert st["accurate"] == 0   # 0..255 integers, squared norms below 2^23: FP32 sums exact
+    assert st["u8"] == (1 if want == 4 else 0)   # the split form reads them as byte rows
     assert st["converged"]
     assert st["iters"] == ref.iters
     assert st["evals"] == ref.evals.tolist()

@@ -75,6 +75,7 @@ def test_image_like_subset_bitwise(knng, path, want):
     st = exact_build(knng, X, 20, 1.0, 0.001, 30, 1, path=path)
     assert st["path"] == want
     assert st["planes"] == (1 if want == 4 else 0)   # pixels are exact in BF16: one plane
+    assert st["u8"] == (1 if want == 4 else 0)       # ... read as bytes
 
 
 @pytest.mark.parametrize("bits,planes", [(8, 1), (12, 2), (16, 2), (24, 3)])
@@ -85,6 +86,17 @@ def test_split_plane_count(knng, bits, planes):
     X = rng.integers(0, 2 ** bits, (300, 64)).astype(np.float32)
     _, _, st = knng.build(dev(X), 8, max_iters=2, path="bf16x3")
     assert st["planes"] == planes
+
+
+@pytest.mark.parametrize("shift,want_u8", [(0, 1), (-1, 0), (56, 0)])
+def test_byte_rows_only_for_8bit_data(knng, shift, want_u8):
+    """Integers in 0..255 with exact FP32 sums are read as byte rows (half the
+    bytes of the BF16 plane, widened in registers); other exact integer data
+    (a negative value; 256, still one BF16 plane) keeps the plane. Both reproduce the
+    oracle bit for bit."""
+    X = (synth.integer_points(700, 64, 200, 9) + np.float32(shift)).astype(np.float32)
+    st = exact_build(knng, X, 10, 1.0, 0.001, 15, 9, path="bf16x3")
+    assert st["planes"] == 1 and st["accurate"] == 0 and st["u8"] == want_u8
 
 
 def test_split_two_planes_step_parity(knng):

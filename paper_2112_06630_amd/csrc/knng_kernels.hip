@@ -178,6 +178,15 @@ __device__ __forceinline__ void wave_bitonic_clean(uint64_t& k, uint32_t& v) {
 // when the previous iteration met the stop rule.
 __device__ __forceinline__ bool stopped(const Views& v) { return v.stop && *v.stop != 0u; }
 
+// Sets `bits` in a device-wide flag word. Every wave of a pass may report the
+// same bits; an atomic per wave on one address serialises at the cache (half
+// a millisecond for 50000 waves), so the word is read first and the atomic
+// issued only when a bit is still missing.
+__device__ __forceinline__ void flag_or(uint64_t* word, uint64_t bits) {
+    const uint64_t cur = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((cur & bits) != bits) atomicOr((unsigned long long*)word, (unsigned long long)bits);
+}
+
 // Batched form: position p belongs to dataset ds[p]; a single build has no
 // dataset table and every position is active.
 __device__ __forceinline__ bool pos_active(const Views& v, int p) { return !v.ds || v.active[v.ds[p]] != 0u; }
@@ -2059,7 +2068,7 @@ __global__ void k_make_split(Views v) {
     }
     const uint64_t m1 = ballot((used & 1u) != 0), m2 = ballot((used & 2u) != 0);
     const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u);
-    if (lane_id() == 0 && wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
+    if (lane_id() == 0 && wu) flag_or(&v.counters[kCntSplit], wu);
 }
 
 void launch_make_split(const Views& v, hipStream_t s) {
@@ -2141,8 +2150,8 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X, Views
     const uint64_t m4 = ballot((used & 4u) != 0), m8 = ballot((used & 8u) != 0), m16 = ballot((used & 16u) != 0);
     if (lane == 0) {
         const uint32_t wu = (m1 ? 1u : 0u) | (m2 ? 2u : 0u) | (m4 ? 4u : 0u) | (m8 ? 8u : 0u) | (m16 ? 16u : 0u);
-        if (wu) atomicOr((unsigned long long*)&v.counters[kCntSplit], (unsigned long long)wu);
-        if (mb) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
+        if (wu) flag_or(&v.counters[kCntSplit], wu);
+        if (mb) flag_or(&v.counters[kCntNonFinite], 1ull);
     }
 }
 
@@ -2876,16 +2885,17 @@ __global__ void k_batch_setup(Views v) {
             v.orig[p] = (int32_t)(p - b);
             v.posof[p] = (int32_t)(p - b);
         }
-        const int64_t cnt = (int64_t)(e - b) * v.dp;
+        // rows by waves, columns by lanes (no division per element)
         bool bad = false;
-        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
-            const int64_t r = q / v.dp;
-            const int c = (int)(q - r * v.dp);
-            const float x = c < d ? X[r * d + c] : 0.f;
-            bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
-            v.Xp[(size_t)b * v.dp + q] = x;
+        const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (uint32_t r = wv; r < e - b; r += nw) {
+            for (int c = lane; c < v.dp; c += 64) {
+                const float x = c < d ? X[(size_t)r * d + c] : 0.f;
+                bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
+                v.Xp[((size_t)b + r) * v.dp + c] = x;
+            }
         }
-        if (bad) atomicOr((unsigned long long*)&v.counters[kCntNonFinite], 1ull);
+        if (bad) flag_or(&v.counters[kCntNonFinite], 1ull);
         if (threadIdx.x == 0) {
             v.active[i] = 1u;
             v.ds_iters[i] = 0;

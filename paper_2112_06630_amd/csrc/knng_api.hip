@@ -1015,6 +1015,7 @@ knng_status batch_upload(knng_batch* b, hipStream_t s) {
         // sums are exact it gives the same values as FP32, so every dataset
         // matches its single build either way)
         v.acc = g.path != KNNG_PATH_VALU ? 1 : 0;
+        v.stop = v.flag + kStopFlag;   // set once every dataset of the group has stopped
         v.nds = nds;
         v.ds = reinterpret_cast<uint32_t*>(tb + L.ds);
         v.dsbase = reinterpret_cast<uint32_t*>(tb + L.dsbase);
@@ -1064,6 +1065,7 @@ void batch_group_setup(const BatchGroup& g, hipStream_t s) {
     const Views& v = g.v;
     launch_fill_u64(v.counters, 0ull, kNumCounters, s);
     launch_fill_u32(v.nn, 0u, v.N, s);
+    launch_fill_u32(v.stop, 0u, 1, s);
     launch_batch_setup(v, s);
     if (g.path != KNNG_PATH_VALU) launch_norms(v, s);
     if (g.path == KNNG_PATH_MFMA_BF16X3) launch_make_split(v, s);
@@ -1074,18 +1076,19 @@ void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hip
     const Views& v = g.v;
     // the hub list is per iteration (its count must not grow past N); the
     // other counters accumulate over the iterations (errors are read at the end)
-    launch_fill_u64(v.counters + kCntHubs, 0ull, 1, s);
-    launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s);
-    launch_fill_u32(v.chg, 0u, (int64_t)v.N, s);
+    // once the group has stopped every pass below returns at entry
+    launch_fill_u64(v.counters + kCntHubs, 0ull, 1, s, v.stop);
+    launch_fill_u32(v.rdeg, 0u, 4 * (int64_t)v.N, s, v.stop);
+    launch_fill_u32(v.chg, 0u, (int64_t)v.N, s, v.stop);
     if (v.rev_S) {
         launch_rev_partition(v, 0, t, s);
     } else {
         launch_rev_hist(v, s);
-        launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s);
+        launch_scan(v.rdeg, v.roff, v.N, v.scan_tmp, s, v.stop);
         launch_rev_scatter(v, 0, t, s);
     }
     launch_select(v, 0, t, s);
-    launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s);
+    launch_scan(v.cap, v.poff, v.N, v.scan_tmp, s, v.stop);
     if (g.path == KNNG_PATH_MFMA_BF16X3)
         launch_join_split(v, s);
     else if (g.path == KNNG_PATH_MFMA)
@@ -1093,7 +1096,7 @@ void batch_group_iteration(const BatchGroup& g, int t, const knng_params& p, hip
     else
         launch_join_valu(v, s);
     launch_merge(v, s);
-    launch_scan(v.chg, v.chgoff, v.N, v.scan_tmp, s);
+    launch_scan(v.chg, v.chgoff, v.N, v.scan_tmp, s, v.stop);
     launch_batch_step(v, t, p.max_iters, p.K, p.delta, s);
 }
 

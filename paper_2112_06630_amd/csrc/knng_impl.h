@@ -130,8 +130,8 @@ size_t partial_words();
 // kernels (launchers; all enqueue on `s`). Launchers that bound a timed phase
 // take optional events e0 / e1, stamped at the start / end of their first /
 // last kernel by the dispatch itself (no marker packets between kernels).
-void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
-void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s, const uint32_t* stop = nullptr);
+void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s, const uint32_t* stop = nullptr);
 void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
 void launch_norms(const Views& v, hipStream_t s);
 void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s);
@@ -149,7 +149,8 @@ void launch_rev_hist(const Views& v, hipStream_t s, hipEvent_t e0 = nullptr);
 void launch_batch_setup(const Views& v, hipStream_t s);
 void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s);
 void launch_batch_finalize(const Views& v, hipStream_t s);
-void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s);
+void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s,
+                 const uint32_t* stop = nullptr);
 void launch_rev_scatter(const Views& v, uint64_t st_sample, int t, hipStream_t s);
 // reverse buckets (roff, rev) by the counting sort; staging in the proposal buffer
 void launch_rev_partition(const Views& v, uint64_t st_sample, int t, hipStream_t s, hipEvent_t e0 = nullptr);

@@ -231,6 +231,33 @@ __device__ __forceinline__ float dist_direct(const float* __restrict__ a, const 
     return (s0 + s1) + (s2 + s3);
 }
 
+// Squared differences of one 32-dimension chunk: four partial sums
+// (components 0..3 of the eight 16-byte groups, in dimension order), added as
+// (s0 + s1) + (s2 + s3).
+__device__ __forceinline__ float chunk32_sq(const float4* __restrict__ pa, const float4* __restrict__ pb) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 x = pa[c], y = pb[c];
+        const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
+        s0 = fmaf(t0, t0, s0);
+        s1 = fmaf(t1, t1, s1);
+        s2 = fmaf(t2, t2, s2);
+        s3 = fmaf(t3, t3, s3);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+// The precision form's stored distance: the chunk sums added into FP64 in
+// chunk order and rounded to FP32 once (dp % 32 == 0). The rescore in the
+// join computes the same value from rows staged in LDS.
+__device__ __forceinline__ float dist_rescore(const float* __restrict__ a, const float* __restrict__ b, int dp) {
+    double tot = 0.0;
+    for (int k0 = 0; k0 < dp; k0 += 32)
+        tot += (double)chunk32_sq(reinterpret_cast<const float4*>(a + k0), reinterpret_cast<const float4*>(b + k0));
+    return (float)tot;
+}
+
 // q = a / b for 0 <= a < 2^31, 1 <= b, via a double reciprocal and one fix-up.
 __device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t b, double rcp) {
     uint32_t q = (uint32_t)((double)a * rcp);
@@ -275,24 +302,27 @@ static void launch_timed(void (*kernel)(P...), dim3 g, dim3 b, size_t lds, hipSt
 
 // ------------------------------------------------------------------ fills
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+// A non-null `stop` word that is set skips the pass (a stopped batch group).
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n, const uint32_t* stop) {
+    if (stop && *stop) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
-__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n, const uint32_t* stop) {
+    if (stop && *stop) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
-void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s, const uint32_t* stop) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n, stop);
 }
 
-void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
+void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s, const uint32_t* stop) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, s, p, v, n, stop);
 }
 
 // ------------------------------------------------------------------ layout (a0)
@@ -514,7 +544,9 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
         if (mode == kDistGram) {
             D = Dg;
         } else {
-            D = dist_direct(v.Xp + (size_t)u * v.dp, v.Xp + (size_t)pid * v.dp, v.dp);
+            const float* a = v.Xp + (size_t)u * v.dp;
+            const float* b = v.Xp + (size_t)pid * v.dp;
+            D = v.Xb ? dist_rescore(a, b, v.dp) : dist_direct(a, b, v.dp);
         }
         key = key_of(D, (uint32_t)v.orig[pid]);
     }
@@ -619,7 +651,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 __global__ __launch_bounds__(256) void k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                    int n, uint32_t* __restrict__ bsum) {
+                                                    int n, uint32_t* __restrict__ bsum, const uint32_t* stop) {
+    if (stop && *stop) return;
     __shared__ uint32_t s_w[4];
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)t * 4;
@@ -639,7 +672,8 @@ __global__ __launch_bounds__(256) void k_scan_local(const uint32_t* __restrict__
     if (t == 255) bsum[blockIdx.x] = woff + inc;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bsum, int nb) {
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bsum, int nb, const uint32_t* stop) {
+    if (stop && *stop) return;
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
@@ -661,17 +695,19 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bsum, 
     if (t == 0) bsum[nb] = s_carry;
 }
 
-__global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __restrict__ bsum, int nb) {
+__global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __restrict__ bsum, int nb,
+                           const uint32_t* stop) {
+    if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] += bsum[i / kScanBlock];
     if (i == 0) out[n] = bsum[nb];
 }
 
-void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s) {
+void launch_scan(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp, hipStream_t s, const uint32_t* stop) {
     const int nb = (n + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_local, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, in, out, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nb > 0 ? nb : 1);
-    hipLaunchKernelGGL(k_scan_add, dim3((n + 256) / 256), dim3(256), 0, s, out, n, tmp, nb > 0 ? nb : 1);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, in, out, n, tmp, stop);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nb > 0 ? nb : 1, stop);
+    hipLaunchKernelGGL(k_scan_add, dim3((n + 256) / 256), dim3(256), 0, s, out, n, tmp, nb > 0 ? nb : 1, stop);
 }
 
 // ------------------------------------------------------------------ reverse lists (a2)
@@ -1798,10 +1834,19 @@ void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
 // (||x~|| + ||y~||)^2, the test applied (in FP64, with the bound enlarged by
 // 2^-20 relative).
 //
-// Rescore. Sixteen lanes per surviving pair, each with four partial sums of
-// (x_j - y_j)^2 over its 16-byte groups, added by a fixed tree: an FP32
-// direct-form evaluation (64 partial sums of d/64 terms each, within the
-// direct form's error bound), deterministic and symmetric in (x, y).
+// Rescore. The owner's member rows (FP32, the original values) are staged in
+// LDS 32 dimensions at a time, so each member row is read once per owner, as
+// the join reads it; one lane per surviving pair adds the chunk's squared
+// differences into four partial sums (components 0..3 of its eight 16-byte
+// groups, in dimension order), adds (s0 + s1) + (s2 + s3) to an FP64 total in
+// chunk order, and rounds the total to FP32 once. The value depends on the
+// two rows alone, and swapping them only negates the differences: one key per
+// pair whichever owner evaluates it, deterministic.
+// Error (u = 2^-24, terms non-negative): a term (x_j - y_j)^2 carries at most
+// 2u, eight accumulations and two adds at most 10u more, the FP64 total and
+// its rounding at most 0.5u + d 2^-53, so |D' - D| <= 13u D at any d. The
+// screen adds 16u T to its margin, so that no pair whose rescored key passes
+// the filter is screened out.
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -1845,39 +1890,90 @@ void launch_make_bf16(const Views& v, hipStream_t s) {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// FP32 squared distance of two rows by a group of 16 lanes (lanes 16g..16g+15):
-// lane k of the group sums the components of the 16-byte groups c = k, k+16,
-// ... into four partial sums (one per component), adds them as
-// (s0 + s1) + (s2 + s3), and the 16 lane values are added by a fixed
-// butterfly (distances 1, 2, 4, 8). Deterministic and symmetric in (a, b);
-// dp % 4 == 0, rows 16-byte aligned. Every lane of the wave takes part in the
-// butterfly; a group with act == false sums nothing.
-__device__ __forceinline__ float dist_group16(const float* __restrict__ a, const float* __restrict__ b, int dp,
-                                              bool act) {
-    const int k = lane_id() & 15;
-    const float4* pa = reinterpret_cast<const float4*>(a);
-    const float4* pb = reinterpret_cast<const float4*>(b);
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    if (act) {
-#pragma unroll 2
-        for (int c = k; c < (dp >> 2); c += 16) {
-            const float4 x = pa[c], y = pb[c];
-            const float t0 = x.x - y.x, t1 = x.y - y.y, t2 = x.z - y.z, t3 = x.w - y.w;
-            s0 = fmaf(t0, t0, s0);
-            s1 = fmaf(t1, t1, s1);
-            s2 = fmaf(t2, t2, s2);
-            s3 = fmaf(t3, t3, s3);
-        }
-    }
-    float sum = (s0 + s1) + (s2 + s3);
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) sum += __uint_as_float(xor_lanes(__float_as_uint(sum), m));
-    return sum;
+constexpr int kRsChunk = 32;             // dimensions staged per pass (dp % 32 == 0 on this path)
+constexpr int kRsStride = kRsChunk + 4;  // floats per staged row: the 16-byte pad spreads rows over the banks
+
+// Most pairs one owner evaluates (new x new unordered, new x old): the bound
+// on its survivors.
+__host__ __device__ inline int bf_max_surv(int C) { return C * (C - 1) / 2 + C * C; }
+
+// Per-wave dynamic LDS of the precision-form join: staged rows [2C][kRsStride]
+// floats, FP64 rescore totals [S], survivors [S] as uint16.
+__host__ __device__ inline size_t bf_rows_bytes(int C) { return (size_t)2 * C * kRsStride * 4; }
+__host__ __device__ inline size_t bf_wave_bytes(int C) {
+    const size_t S = (size_t)bf_max_surv(C);
+    return bf_rows_bytes(C) + S * 8 + ((S * 2 + 15) & ~(size_t)15);
 }
 
-constexpr int kBfMaxSurv = 3 * 32 * 32 / 2;   // survivor pairs per owner <= e(u) <= C(C-1)/2 + C^2 < 1.5 C^2, C <= 32
+typedef float floatx32 __attribute__((ext_vector_type(32)));
 
-__global__ __launch_bounds__(256) void k_join_bf16(Views v) {
+// Rescore of one owner's survivors. Lane l stages 16 bytes of rows
+// l/8 + 8k (k < NG = ceil(m/8); rows past m repeat row m-1 in the loads and
+// are not stored). Two register buffers alternate over the chunks, so the
+// loads of the next two chunks are in flight while one is summed; the staged
+// values sit in vector register tuples (element 4k + c), which stay in
+// registers at any NG. Survivor q (i | j << 6 | directions << 12) is summed
+// by lane q mod 64 into s_tot[q].
+template <int NG>
+__device__ __forceinline__ void stage_load(floatx32& buf, const float* const (&src)[NG], int off) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const float4 x = *reinterpret_cast<const float4*>(src[k] + off);
+        buf[4 * k] = x.x;
+        buf[4 * k + 1] = x.y;
+        buf[4 * k + 2] = x.z;
+        buf[4 * k + 3] = x.w;
+    }
+}
+
+template <int NG>
+__device__ __forceinline__ void stage_store(const floatx32& buf, float* s_rows, int sr, int sc, int m) {
+#pragma unroll
+    for (int k = 0; k < NG; ++k)
+        if (sr + 8 * k < m)
+            *reinterpret_cast<float4*>(s_rows + (sr + 8 * k) * kRsStride + sc) =
+                make_float4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
+    wave_sync();
+}
+
+__device__ __forceinline__ void rescore_chunk(const uint16_t* s_surv, double* s_tot, uint32_t nsv,
+                                              const float* s_rows) {
+    for (uint32_t q = (uint32_t)lane_id(); q < nsv; q += 64) {
+        const uint32_t e = s_surv[q];
+        const float4* pa = reinterpret_cast<const float4*>(s_rows + (e & 63u) * kRsStride);
+        const float4* pb = reinterpret_cast<const float4*>(s_rows + ((e >> 6) & 63u) * kRsStride);
+        s_tot[q] += (double)chunk32_sq(pa, pb);
+    }
+    wave_sync();
+}
+
+template <int NG>
+__device__ __forceinline__ void rescore_staged(const Views& v, const uint32_t* pos, int m, const uint16_t* s_surv,
+                                               double* s_tot, uint32_t nsv, float* s_rows) {
+    const int lane = lane_id(), dp = v.dp;
+    const int sr = lane >> 3, sc = (lane & 7) * 4;
+    const float* src[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) src[k] = v.Xp + (size_t)pos[min(sr + 8 * k, m - 1)] * dp + sc;
+    // straight-line loads (the last chunks are loaded again past the end),
+    // so that only the loads of the chunk being stored are waited for
+    const int last = dp - kRsChunk;
+    floatx32 A, B;
+    stage_load<NG>(A, src, 0);
+    stage_load<NG>(B, src, min(kRsChunk, last));
+    for (uint32_t q = (uint32_t)lane; q < nsv; q += 64) s_tot[q] = 0.0;
+    for (int k0 = 0; k0 < dp; k0 += 2 * kRsChunk) {
+        stage_store<NG>(A, s_rows, sr, sc, m);
+        stage_load<NG>(A, src, min(k0 + 2 * kRsChunk, last));
+        rescore_chunk(s_surv, s_tot, nsv, s_rows);
+        const bool odd = k0 + kRsChunk < dp;
+        if (odd) stage_store<NG>(B, s_rows, sr, sc, m);
+        stage_load<NG>(B, src, min(k0 + 3 * kRsChunk, last));
+        if (odd) rescore_chunk(s_surv, s_tot, nsv, s_rows);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
     if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
@@ -1887,16 +1983,21 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     __shared__ double s_sn[kJoinWaves][64];  // sqrt of the BF16 squared norm
     __shared__ double s_st[kJoinWaves][64];  // sqrt of the snapshot threshold distance
     __shared__ uint32_t s_emit[kJoinWaves][3][64];
-    __shared__ uint32_t s_surv[kJoinWaves][kBfMaxSurv];   // survivors: i | j << 8 | directions << 16
-    __shared__ float s_sd[kJoinWaves][kBfMaxSurv];        // their rescored FP32 distances
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    const int lane = lane_id(), w = threadIdx.x >> 6, wpb = (int)(blockDim.x >> 6);
     const int C2 = 2 * v.C, dp = v.dp;
+    const int S = bf_max_surv(v.C);
+    unsigned char* wbase = s_dyn + (size_t)w * bf_wave_bytes(v.C);
+    float* s_rows = reinterpret_cast<float*>(wbase);
+    double* s_tot = reinterpret_cast<double*>(wbase + bf_rows_bytes(v.C));
+    uint16_t* s_surv = reinterpret_cast<uint16_t*>(wbase + bf_rows_bytes(v.C) + (size_t)S * 8);
     const int c16 = lane & 15, g = lane >> 4;
     EmitLds el{s_emit[w][0], s_emit[w][1], s_emit[w][2]};
     emit_clear(el, 64);
     uint64_t rescored = 0;
     const double cfp = (double)(dp + 3) * (1.0 / 16777216.0);
-    const XcdRange xr = xcd_range(v.N, kJoinWaves, w);
+    const double crs = 16.0 / 16777216.0;   // the rescore's relative error (at most 13u), with room
+    const XcdRange xr = xcd_range(v.N, wpb, w);
     for (int u = xr.next; u < xr.end; u += xr.step) {
         const uint32_t nn = v.nn[u];
         const int nnew = (int)(nn & 0xffffu), m = nnew + (int)(nn >> 16);
@@ -1965,52 +2066,48 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
                             const double fp = cfp * nbs * nbs;
                             const double Ti = (double)__uint_as_float((uint32_t)(s_thr[w][i] >> 32));
                             const double Tj = (double)__uint_as_float((uint32_t)(s_thr[w][j] >> 32));
-                            const double mi = (2.0 * eps * s_st[w][i] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
-                            const double mj = (2.0 * eps * s_st[w][j] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0);
+                            const double mi =
+                                (2.0 * eps * s_st[w][i] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0) + crs * Ti;
+                            const double mj =
+                                (2.0 * eps * s_st[w][j] + eps * eps + fp) * (1.0 + 1.0 / 1048576.0) + crs * Tj;
                             si = Dt - mi <= Ti;
                             sj = Dt - mj <= Tj;
                         }
                         const bool sv = si || sj;
                         const uint64_t mk = ballot(sv);
                         const uint32_t slot = nsv + mbcnt(mk);
-                        if (sv && slot < (uint32_t)kBfMaxSurv)
-                            s_surv[w][slot] = (uint32_t)i | ((uint32_t)j << 8) | (si ? 1u << 16 : 0u) |
-                                              (sj ? 1u << 17 : 0u);
+                        if (sv && slot < (uint32_t)S)
+                            s_surv[slot] = (uint16_t)((uint32_t)i | ((uint32_t)j << 6) | (si ? 1u << 12 : 0u) |
+                                                      (sj ? 1u << 13 : 0u));
                         nsv += (uint32_t)__popcll(mk);
                     }
                 }
         }
-        if (nsv > (uint32_t)kBfMaxSurv) {  // cannot happen: survivors <= e(u) <= 1.5 C^2
+        if (nsv > (uint32_t)S) {  // cannot happen: survivors <= e(u) <= S
             if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 128ull);
-            nsv = kBfMaxSurv;
+            nsv = (uint32_t)S;
         }
         wave_sync();
-        // rescore in FP32 from the original rows, 16 lanes per surviving pair
-        // (four pairs per pass; each load instruction covers 256 contiguous
-        // bytes of four rows)
-        for (uint32_t q0 = 0; q0 < nsv; q0 += 4) {
-            const uint32_t q = q0 + (uint32_t)(lane >> 4);
-            float D = 0.f;
-            const float* ra = v.Xp;
-            const float* rb = v.Xp;
-            if (q < nsv) {
-                const uint32_t e = s_surv[w][q];
-                ra = v.Xp + (size_t)s_pos[w][e & 255u] * dp;
-                rb = v.Xp + (size_t)s_pos[w][(e >> 8) & 255u] * dp;
-            }
-            D = dist_group16(ra, rb, dp, q < nsv);
-            if (q < nsv && (lane & 15) == 0) s_sd[w][q] = D;
+        // rescore from the FP32 rows staged 32 dimensions at a time
+        switch (__builtin_amdgcn_readfirstlane((m + 7) >> 3)) {
+            case 1: rescore_staged<1>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 2: rescore_staged<2>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 3: rescore_staged<3>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 4: rescore_staged<4>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 5: rescore_staged<5>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 6: rescore_staged<6>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 7: rescore_staged<7>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            default: rescore_staged<8>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
         }
         rescored += nsv;
-        wave_sync();
         // exact filter on the rescored keys: count, reserve, write
         for (int pass = 0; pass < 2; ++pass) {
             for (uint32_t q = (uint32_t)lane; q < nsv; q += 64) {
-                const uint32_t e = s_surv[w][q];
-                const int a = (int)(e & 255u), b = (int)((e >> 8) & 255u);
-                const uint64_t kb = (uint64_t)__float_as_uint(s_sd[w][q]) << 32;
+                const uint32_t e = s_surv[q];
+                const int a = (int)(e & 63u), b = (int)((e >> 6) & 63u);
+                const uint64_t kb = (uint64_t)__float_as_uint((float)s_tot[q]) << 32;
                 const uint64_t ka = kb | s_oid[w][b], kbb = kb | s_oid[w][a];
-                const bool da = (e >> 16) & 1u, db = (e >> 17) & 1u;
+                const bool da = (e >> 12) & 1u, db = (e >> 13) & 1u;
                 if (pass == 0) {
                     if (da && ka < s_thr[w][a]) emit_count(el, a);
                     if (db && kbb < s_thr[w][b]) emit_count(el, b);
@@ -2027,8 +2124,28 @@ __global__ __launch_bounds__(256) void k_join_bf16(Views v) {
     if (lane == 0 && rescored) atomicAdd((unsigned long long*)&v.counters[kCntRescored], (unsigned long long)rescored);
 }
 
+// Waves per workgroup: four where the device's LDS per workgroup holds them.
 void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    launch_timed(k_join_bf16, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), 0, s, e0, e1, v);
+    static const int lds_max = [] {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
+            lim = 65536;
+        return lim;
+    }();
+    static const size_t lds_static = [] {
+        hipFuncAttributes a{};
+        return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_join_bf16)) == hipSuccess
+                   ? (size_t)a.sharedSizeBytes
+                   : (size_t)kJoinWaves * 64 * 52;
+    }();
+    const size_t wb = bf_wave_bytes(v.C);
+    int wpb = kJoinWaves;
+    while (wpb > 1 && lds_static + (size_t)wpb * wb > (size_t)lds_max) wpb >>= 1;
+    const size_t lds = (size_t)wpb * wb;
+    if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_join_bf16),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    launch_timed(k_join_bf16, dim3(grid_for(v.N, wpb, 1 << 16)), dim3(64 * wpb), lds, s, e0, e1, v);
 }
 
 // ------------------------------------------------------------------ split-BF16 Gram form
@@ -2909,9 +3026,12 @@ void launch_batch_setup(const Views& v, hipStream_t s) {
 }
 
 // after iteration t: per-dataset e_t and c_t from the scans over its range,
-// then the stop rule c_t < delta*N_i*K, or t = T_max
-__global__ void k_batch_step(Views v, int t, int T_max, int K, double delta) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < v.nds; i += gridDim.x * blockDim.x) {
+// then the stop rule c_t < delta*N_i*K, or t = T_max. One workgroup: once no
+// dataset of the group is active it sets the group's stop word, and every
+// later iteration kernel of the group returns at entry.
+__global__ __launch_bounds__(1024) void k_batch_step(Views v, int t, int T_max, int K, double delta) {
+    int alive = 0;
+    for (int i = threadIdx.x; i < v.nds; i += blockDim.x) {
         if (!v.active[i]) continue;
         const uint32_t b = v.dsbase[i], e = v.dsbase[i + 1];
         const int64_t ev = (int64_t)(v.poff[e] - v.poff[b]);
@@ -2924,12 +3044,16 @@ __global__ void k_batch_step(Views v, int t, int T_max, int K, double delta) {
             v.active[i] = 0u;
         } else if (t >= T_max) {
             v.active[i] = 0u;
+        } else {
+            alive = 1;
         }
     }
+    alive = __syncthreads_or(alive);
+    if (threadIdx.x == 0 && v.stop) *v.stop = alive ? 0u : 1u;
 }
 
 void launch_batch_step(const Views& v, int t, int T_max, int K, double delta, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_step, dim3((v.nds + 255) / 256), dim3(256), 0, s, v, t, T_max, K, delta);
+    hipLaunchKernelGGL(k_batch_step, dim3(1), dim3(1024), 0, s, v, t, T_max, K, delta);
 }
 
 // per-dataset outputs: rows sorted by (distance, local id)

@@ -533,6 +533,11 @@ def test_bf16_screen_continuous_parity(knng):
     ids, dists, st = knng.build(dev(X), K, rho, 0.001, 30, 3, precision="bf16")
     res = check_rows(X, ids.cpu().numpy(), dists.cpu().numpy(), ref.ids, ref.dists, dpad=960, gram=False)
     assert res["exact_rows"] >= 3000 - 10
+    # stored values: 32-dimension chunk sums in FP32 added into FP64, rounded
+    # once: at most 13 u relative to the distance, whatever d
+    D64 = oracle.list_dists(X, ids.cpu().numpy())
+    err = np.abs(dists.cpu().numpy().astype(np.float64) - D64)
+    assert (err <= 13 * 2.0 ** -24 * D64).all(), float((err / np.maximum(D64, 1e-300)).max())
     ei, ed = oracle.bruteforce(X, K)
     assert oracle.recall(X, ids.cpu().numpy(), ed) >= 0.99
     late = [r / (2 * e) for r, e in zip(st["rescored"], st["evals"]) if e][-3:]

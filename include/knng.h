@@ -271,12 +271,18 @@ size_t knng_batch_workspace_bytes(const knng_dataset* descs, int32_t n, const kn
 
 /* Plan a batch: groups datasets by dimension and join path, uploads the
  * per-dataset tables (seeds, offsets, pointers) into the workspace and checks
- * every input is finite. `tuning` is NULL/"auto" (time both join paths per
- * dimension on the batch itself and keep the faster: the autotuner) or a
- * table such as "16:valu,64:mfma,128:mfma". params.K, rho, delta, max_iters
- * (>= 1) apply to every dataset; params.reorder must be 0, params.precision
- * KNNG_FP32. Synchronises `stream`. Results equal those of one knng_build per
- * dataset with the same join path. */
+ * every input is finite. `tuning` is NULL/"auto" (the autotuner: for every
+ * dimension, each join path the cap allows and two launch shapes of the select
+ * and join passes, one workgroup per four owners or eight workgroups per
+ * compute unit looping over the owners, each run as the whole build of that
+ * dimension's datasets on the batch itself; the fastest is kept) or a table
+ * such as "16:valu,64:mfma@2048,128:bf16x3" (path per d; "@n": at most n
+ * workgroups in the select and join passes). params.K, rho, delta, max_iters
+ * (>= 1) apply to every dataset; params.reorder must be 0, params.blocks at
+ * most 1, params.precision KNNG_FP32. Synchronises `stream`. Results equal
+ * those of one knng_build per dataset with the same join path, whatever the
+ * launch shape. Once every dataset of a dimension group has stopped, the
+ * group's later passes return at entry. */
 knng_status knng_batch_plan(knng_batch** out, const knng_dataset* descs, int32_t n, const knng_params* params,
                             void* d_ws, size_t ws_bytes, const char* tuning, void* stream);
 

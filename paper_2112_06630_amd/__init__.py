@@ -322,7 +322,8 @@ class Batch:
 
     ``Xs``: list of device float32 [N_i, d_i] tensors; ``seeds``: one seed per
     dataset. ``tuning``: None/"auto" runs the autotuner, or a table such as
-    "16:valu,64:mfma,128:mfma". Work is ordered on ``stream`` (a non-default
+    "16:valu,64:mfma@2048,128:mfma" (join path per d, optional workgroup cap
+    of the select and join passes). Work is ordered on ``stream`` (a non-default
     torch stream; one is created when not given).
     """
 

@@ -873,6 +873,7 @@ namespace {
 
 struct BatchGroup {
     int d = 0, dp = 0, path = 0;
+    int cap = 0;                // workgroup cap of the select and join passes (0: per owner group)
     std::vector<int> members;   // dataset indices in the caller's order
     int64_t N = 0;
     Plan plan{};
@@ -911,8 +912,12 @@ TableLayout table_layout(int64_t N, int nds, int T) {
     return L;
 }
 
-int parse_tuned_path(const std::string& table, int d) {
-    // "16:valu,64:mfma" -> path for d, 0 if absent
+// "16:valu,64:mfma@2048" -> {path, workgroup cap} for d; path 0 if d is absent
+struct Tuned {
+    int path = 0, cap = 0;
+};
+
+Tuned parse_tuned(const std::string& table, int d) {
     size_t pos = 0;
     while (pos < table.size()) {
         size_t end = table.find(',', pos);
@@ -920,14 +925,27 @@ int parse_tuned_path(const std::string& table, int d) {
         const std::string item = table.substr(pos, end - pos);
         const size_t c = item.find(':');
         if (c != std::string::npos && std::atoi(item.substr(0, c).c_str()) == d) {
-            const std::string v = item.substr(c + 1);
-            if (v == "valu") return KNNG_PATH_VALU;
-            if (v == "mfma") return KNNG_PATH_MFMA;
-            if (v == "bf16x3") return KNNG_PATH_MFMA_BF16X3;
+            std::string v = item.substr(c + 1);
+            Tuned t;
+            const size_t at = v.find('@');
+            if (at != std::string::npos) {
+                t.cap = std::max(0, std::atoi(v.substr(at + 1).c_str()));
+                v = v.substr(0, at);
+            }
+            if (v == "valu") t.path = KNNG_PATH_VALU;
+            if (v == "mfma") t.path = KNNG_PATH_MFMA;
+            if (v == "bf16x3") t.path = KNNG_PATH_MFMA_BF16X3;
+            if (t.path) return t;
         }
         pos = end + 1;
     }
-    return 0;
+    return Tuned{};
+}
+
+std::string tuned_entry(int d, int path, int cap) {
+    std::string e = std::to_string(d) + (path == KNNG_PATH_MFMA ? ":mfma" : path == KNNG_PATH_MFMA_BF16X3 ? ":bf16x3" : ":valu");
+    if (cap > 0) e += "@" + std::to_string(cap);
+    return e;
 }
 
 }  // namespace
@@ -968,7 +986,8 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
     const int C = sample_cap(p->K, p->rho);
     for (int i = 0; i < n; ++i) {
         const int d = descs[i].d;
-        int path = p->path != KNNG_PATH_AUTO ? p->path : parse_tuned_path(tuning, d);
+        const Tuned tu = parse_tuned(tuning, d);
+        int path = p->path != KNNG_PATH_AUTO ? p->path : tu.path;
         if (!path) path = (d >= kAutoMatrixMinD && 2 * C <= 64) ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
         const int dp = (int)(path != KNNG_PATH_VALU ? round_up(d, 32) : round_up(d, 4));
         BatchGroup* g = nullptr;
@@ -980,6 +999,7 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
             g->d = d;
             g->dp = dp;
             g->path = path;
+            g->cap = tu.cap;
         }
         g->members.push_back(i);
         g->N += descs[i].N;
@@ -1016,6 +1036,7 @@ knng_status batch_upload(knng_batch* b, hipStream_t s) {
         // matches its single build either way)
         v.acc = g.path != KNNG_PATH_VALU ? 1 : 0;
         v.stop = v.flag + kStopFlag;   // set once every dataset of the group has stopped
+        v.grid_cap = g.cap;
         v.nds = nds;
         v.ds = reinterpret_cast<uint32_t*>(tb + L.ds);
         v.dsbase = reinterpret_cast<uint32_t*>(tb + L.dsbase);
@@ -1108,8 +1129,13 @@ void batch_enqueue(knng_batch* b, hipStream_t s) {
     for (const auto& g : b->groups) launch_batch_finalize(g.v, s);
 }
 
-// Autotuner: for every d where both join paths are possible, time init plus
-// two iterations of the group with each path (HIP events) and keep the faster.
+// Autotuner: for every d, each candidate (join path, workgroup cap of the
+// select and join passes) runs the whole build of that dimension's datasets
+// (setup untimed; every iteration up to T, a stopped group's passes return at
+// entry) timed with HIP events, and the fastest is kept. Paths: the direct
+// form always, the matrix forms where 2C <= 64. Caps: one workgroup per four
+// owners (at most 65536), or eight workgroups per compute unit looping over
+// the owners, which costs less once most datasets have converged.
 knng_status batch_autotune(knng_batch* b, hipStream_t s) {
     std::string table;
     std::vector<int> ds_seen;
@@ -1117,30 +1143,35 @@ knng_status batch_autotune(knng_batch* b, hipStream_t s) {
         if (std::find(ds_seen.begin(), ds_seen.end(), D.d) == ds_seen.end()) ds_seen.push_back(D.d);
     std::sort(ds_seen.begin(), ds_seen.end());
     const int C = sample_cap(b->p.K, b->p.rho);
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int caps[2] = {0, 8 * std::max(cus, 1)};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     for (int d : ds_seen) {
-        int best_path = d >= kAutoMatrixMinD && 2 * C <= 64 ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU;
-        if (2 * C <= 64) {
-            float best_ms = 1e30f;
-            for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA, KNNG_PATH_MFMA_BF16X3}) {
+        int best_path = d >= kAutoMatrixMinD && 2 * C <= 64 ? KNNG_PATH_MFMA_BF16X3 : KNNG_PATH_VALU, best_cap = 0;
+        float best_ms = 1e30f;
+        for (int path : {KNNG_PATH_VALU, KNNG_PATH_MFMA, KNNG_PATH_MFMA_BF16X3}) {
+            if (path != KNNG_PATH_VALU && 2 * C > 64) continue;
+            for (int cap : caps) {
                 knng_batch tb;
                 tb.p = b->p;
                 tb.p.path = path;
-                tb.p.max_iters = 2;
                 for (const auto& D : b->descs)
                     if (D.d == d) tb.descs.push_back(D);
                 size_t total = 0;
                 if (batch_groups(tb.descs.data(), (int32_t)tb.descs.size(), &tb.p, "", tb.groups, total) != KNNG_OK)
                     continue;
                 if (total > b->ws_bytes) continue;
+                for (auto& g : tb.groups) g.cap = cap;
                 tb.ws = b->ws;
                 tb.ws_bytes = b->ws_bytes;
                 if (batch_upload(&tb, s) != KNNG_OK) continue;
                 for (const auto& g : tb.groups) batch_group_setup(g, s);
                 HIP_TRY(hipEventRecord(e0, s));
-                for (int t = 1; t <= 2; ++t)
+                for (int t = 1; t <= tb.p.max_iters; ++t)
                     for (const auto& g : tb.groups) batch_group_iteration(g, t, tb.p, s);
                 HIP_TRY(hipEventRecord(e1, s));
                 HIP_TRY(hipStreamSynchronize(s));
@@ -1148,12 +1179,12 @@ knng_status batch_autotune(knng_batch* b, hipStream_t s) {
                 if (ms >= 0.f && ms < best_ms) {
                     best_ms = ms;
                     best_path = path;
+                    best_cap = cap;
                 }
             }
         }
         if (!table.empty()) table += ",";
-        table += std::to_string(d) + (best_path == KNNG_PATH_MFMA ? ":mfma"
-                                      : best_path == KNNG_PATH_MFMA_BF16X3 ? ":bf16x3" : ":valu");
+        table += tuned_entry(d, best_path, best_cap);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

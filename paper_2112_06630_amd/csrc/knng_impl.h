@@ -55,6 +55,8 @@ struct Views {
     int permuted;       // 0 until the graph-ordered permutation ran: position = original id
     int blk_on, blk_lo, blk_hi;   // block-asynchronous iteration: only owners with original
                                   // ids in [blk_lo, blk_hi) sample and join (blk_on != 0)
+    int grid_cap;       // > 0: workgroups of the select and join passes (grid-stride loops over the
+                        // owners); 0: one workgroup per four owners, at most 65536
     uint64_t* lkey;     // [N, K] (f32 bits of D << 32) | original id, rows ascending
     uint32_t* lpos;     // [N, K] position of the neighbour | kNewBit
     uint64_t* kth;      // [N] the list's K-th key (lkey[p, K-1]), written with the list: the joins'

@@ -276,6 +276,8 @@ struct XcdRange {
 
 __device__ __forceinline__ XcdRange xcd_range(int n, int waves_per_block, int wave) {
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    // fewer workgroups than XCDs (a few dozen items): one grid-stride range
+    if (G < 8) return XcdRange{b * waves_per_block + wave, n, G * waves_per_block};
     const int x = b & 7, bi = b >> 3;
     const int nbx = (G - x + 7) >> 3;           // workgroups on this XCD
     const int per = (n + 7) >> 3;               // items per XCD range
@@ -289,6 +291,10 @@ static inline int grid_for(int64_t items, int per_block, int cap = 1 << 20) {
     if (g > cap) g = cap;
     return (int)g;
 }
+
+// Workgroup cap of the select and join passes (their loops stride over the
+// owners, so any grid covers them).
+static inline int pass_cap(const Views& v) { return v.grid_cap > 0 ? v.grid_cap : 1 << 16; }
 
 // Launch with optional start / stop events recorded by the dispatch packet.
 template <typename... P, typename... A>
@@ -846,7 +852,7 @@ __global__ __launch_bounds__(1024) void k_rev_bucket(Views v) {
 void launch_rev_partition(const Views& v, uint64_t st, int t, hipStream_t s, hipEvent_t e0) {
     const size_t lds_s = (size_t)v.rev_S * 4;
     launch_timed(k_rev_count, dim3(v.rev_B), dim3(1024), lds_s, s, e0, nullptr, v);
-    launch_scan(v.rev_h, v.rev_hs, v.rev_S * v.rev_B, v.rev_tmp, s);
+    launch_scan(v.rev_h, v.rev_hs, v.rev_S * v.rev_B, v.rev_tmp, s, v.stop);
     hipLaunchKernelGGL(k_rev_part, dim3(v.rev_B), dim3(1024), lds_s, s, v, st, t);
     hipLaunchKernelGGL(k_rev_bucket, dim3(v.rev_S), dim3(1024), ((size_t)4 << v.rev_shift), s, v);
 }
@@ -1528,7 +1534,7 @@ __global__ __launch_bounds__(256, 6) void k_select_small(Views v, uint64_t st0, 
 }
 
 void launch_select(const Views& v, uint64_t st, int t, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_small, dim3(grid_for((v.N + 1) / 2, kSelWaves, 1 << 16)), dim3(256), 0, s, v, st, t);
+    hipLaunchKernelGGL(k_select_small, dim3(grid_for((v.N + 1) / 2, kSelWaves, pass_cap(v))), dim3(256), 0, s, v, st, t);
     // The threshold search (inside k_select_small) needs a count in [2C, 64];
     // a member reached by both routes adds two entries of one weight, so the
     // count can step over a window narrower than 3 (2C = 64 leaves one
@@ -1658,7 +1664,7 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
 
 void launch_join_valu(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = join_valu_wave_bytes(v) * kJoinWaves;
-    launch_timed(k_join_valu, dim3(grid_for(v.N, kJoinWaves, 1 << 16)), dim3(256), lds, s, e0, e1, v);
+    launch_timed(k_join_valu, dim3(grid_for(v.N, kJoinWaves, pass_cap(v))), dim3(256), lds, s, e0, e1, v);
 }
 
 // High-d local join on FP32 MFMA (v_mfma_f32_16x16x4f32): per owner, the
@@ -1808,7 +1814,7 @@ __global__ __launch_bounds__(256) void k_join_mfma(Views v) {
 }
 
 void launch_join_mfma(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
+    const dim3 g(grid_for(v.N, kJoinWaves, pass_cap(v)));
     if (v.acc)
         launch_timed(k_join_mfma<true>, g, dim3(256), 0, s, e0, e1, v);
     else
@@ -2145,7 +2151,7 @@ void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
     const size_t lds = (size_t)wpb * wb;
     if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_join_bf16),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    launch_timed(k_join_bf16, dim3(grid_for(v.N, wpb, 1 << 16)), dim3(64 * wpb), lds, s, e0, e1, v);
+    launch_timed(k_join_bf16, dim3(grid_for(v.N, wpb, pass_cap(v))), dim3(64 * wpb), lds, s, e0, e1, v);
 }
 
 // ------------------------------------------------------------------ split-BF16 Gram form
@@ -2533,7 +2539,7 @@ void k_join_split(Views v) {
 
 template <int MaxCT, bool Acc>
 static void launch_join_split_ct(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 g(grid_for(v.N, kJoinWaves, 1 << 16));
+    const dim3 g(grid_for(v.N, kJoinWaves, pass_cap(v)));
     if constexpr (!Acc) {
         if (v.u8) {
             launch_timed(k_join_split<MaxCT, 1, false, true>, g, dim3(256), 0, s, e0, e1, v);

@@ -147,3 +147,49 @@ def test_batch_rejects_bad_input(knng):
         knng.Batch([dev(X)], [1], 10, tuning="16:valu")
     with pytest.raises(knng.KnngError):
         knng.Batch([dev(synth.integer_points(8, 16, 5, 1))], [1], 10, tuning="16:valu")  # K > N-1
+
+
+def test_batch_of_tiny_datasets(knng):
+    """Groups of a few dozen points (fewer join workgroups than XCDs) still
+    match their single builds."""
+    data = [(synth.integer_points(n, d, 7, 60 + n), 60 + n) for n, d in [(3, 16), (9, 16), (12, 64), (5, 64)]]
+    Xs = [dev(X) for X, _ in data]
+    seeds = [s for _, s in data]
+    b = knng.Batch(Xs, seeds, 2, 1.0, 0.001, 10, tuning="16:valu,64:bf16x3")
+    b.execute()
+    b.synchronize()
+    for i, (X, s) in enumerate(data):
+        ids, dists, _ = knng.build(Xs[i], 2, 1.0, 0.001, 10, s, path="valu" if X.shape[1] == 16 else "bf16x3")
+        assert torch.equal(b.ids[i], ids) and torch.equal(b.dists[i], dists), i
+        ref = oracle.build_graph(X, 2, 1.0, 0.001, 10, s)
+        assert np.array_equal(ids.cpu().numpy(), ref.ids), i
+    b.close()
+
+
+def test_batch_launch_shape_does_not_change_results(knng):
+    """The workgroup cap of the select and join passes ("@n" in the tuning
+    table) changes only how owners are spread over workgroups."""
+    data = small_batch(10, 21)
+    Xs = [dev(X) for X, _ in data]
+    seeds = [s for _, s in data]
+    out = []
+    for table in ["16:valu,64:bf16x3,128:mfma", "16:valu@64,64:bf16x3@7,128:mfma@300"]:
+        b = knng.Batch(Xs, seeds, 15, 1.0, 0.001, 30, tuning=table)
+        assert b.tuning == table
+        b.execute()
+        b.synchronize()
+        out.append(([t.clone() for t in b.ids], [t.clone() for t in b.dists], b.stats()))
+        b.close()
+    for i in range(len(data)):
+        assert torch.equal(out[0][0][i], out[1][0][i]) and torch.equal(out[0][1][i], out[1][1][i]), i
+    assert out[0][2]["evals"] == out[1][2]["evals"]
+
+
+def test_autotuner_table_is_valid(knng):
+    data = small_batch(6, 23)
+    b = knng.Batch([dev(X) for X, _ in data], [s for _, s in data], 15, 1.0, 0.001, 30)
+    for item in b.tuning.split(","):
+        d, rest = item.split(":")
+        path, _, cap = rest.partition("@")
+        assert path in ("valu", "mfma", "bf16x3") and (cap == "" or int(cap) > 0)
+    b.close()

@@ -605,3 +605,25 @@ def test_block_async_one_block_is_synchronous(knng):
     a = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], blocks=0)
     b = knng.build(dev(X), p["K"], p["rho"], p["delta"], p["max_iters"], p["seed"], blocks=1)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2]["evals"] == b[2]["evals"]
+
+
+# ----------------------------------------------------------------- inputs smaller than one workgroup per XCD
+
+@pytest.mark.parametrize("N", [2, 5, 13, 28, 33])
+@pytest.mark.parametrize("path,d", [("valu", 3), ("mfma", 40), ("bf16x3", 40)])
+def test_tiny_inputs_bitwise(knng, N, path, d):
+    """A few dozen points give fewer join workgroups than XCDs: every owner
+    must still be joined (graph, e_t and c_t equal the oracle's)."""
+    K = min(4, N - 1)
+    exact_build(knng, synth.integer_points(N, d, 7, 40 + N), K, 1.0, 0.001, 10, 40 + N, path=path)
+
+
+@pytest.mark.parametrize("N", [3, 20])
+def test_tiny_inputs_precision_form(knng, N):
+    X = synth.integer_points(N, 40, 7, 50 + N)
+    K = min(4, N - 1)
+    ref = oracle.build_graph(X, K, 1.0, 0.001, 10, 50 + N)
+    ids, dists, st = knng.build(dev(X), K, 1.0, 0.001, 10, 50 + N, precision="bf16")
+    assert st["evals"] == ref.evals.tolist() and st["changes"] == ref.changes.tolist()
+    assert np.array_equal(ids.cpu().numpy(), ref.ids)
+    assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)

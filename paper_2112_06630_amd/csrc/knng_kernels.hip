@@ -1979,7 +1979,11 @@ __device__ __forceinline__ void rescore_staged(const Views& v, const uint32_t* p
     }
 }
 
-__global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
+// MaxCT column tiles of 16 members (2C <= 16 MaxCT); NGmax = ceil(2C / 8)
+// row groups staged per lane in the rescore: both follow the sample cap, so
+// the register budget (and the waves resident) does too.
+template <int MaxCT, int NGmax>
+__global__ __launch_bounds__(256, MaxCT <= 2 ? 3 : 2) void k_join_bf16(Views v) {
     if (stopped(v)) return;
     __shared__ uint64_t s_thr[kJoinWaves][64];
     __shared__ uint32_t s_oid[kJoinWaves][64];
@@ -2027,28 +2031,28 @@ __global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
         }
         wave_sync();
         const int RT = (nnew + 15) >> 4, CT = (m + 15) >> 4;
-        const uint16_t* rp[kMfmaMaxCT];
-        bool rv[kMfmaMaxCT];
-        for (int ct = 0; ct < kMfmaMaxCT; ++ct) {
+        const uint16_t* rp[MaxCT];
+        bool rv[MaxCT];
+        for (int ct = 0; ct < MaxCT; ++ct) {
             const int j = ct * 16 + c16;
             rv[ct] = ct < CT && j < m;
             rp[ct] = v.Xb + (size_t)(rv[ct] ? s_pos[w][j] : 0u) * dp + g * 8;
         }
-        floatx4 acc[kMfmaMaxCT * (kMfmaMaxCT + 1) / 2];
-        for (int t = 0; t < kMfmaMaxCT * (kMfmaMaxCT + 1) / 2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        floatx4 acc[MaxCT * (MaxCT + 1) / 2];
+        for (int t = 0; t < MaxCT * (MaxCT + 1) / 2; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < dp; k0 += 32) {
-            bf16x8 f[kMfmaMaxCT];
+            bf16x8 f[MaxCT];
 #pragma unroll
-            for (int ct = 0; ct < kMfmaMaxCT; ++ct) {
+            for (int ct = 0; ct < MaxCT; ++ct) {
                 uint4 raw = make_uint4(0u, 0u, 0u, 0u);
                 if (rv[ct]) raw = *reinterpret_cast<const uint4*>(rp[ct] + k0);
                 f[ct] = __builtin_bit_cast(bf16x8, raw);
             }
             int t = 0;
 #pragma unroll
-            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+            for (int rt = 0; rt < MaxCT; ++rt)
 #pragma unroll
-                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t)
+                for (int ct = rt; ct < MaxCT; ++ct, ++t)
                     if (rt < RT && ct < CT)
                         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[rt], f[ct], acc[t], 0, 0, 0);
         }
@@ -2057,9 +2061,9 @@ __global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
         {
             int t = 0;
 #pragma unroll
-            for (int rt = 0; rt < kMfmaMaxCT; ++rt)
+            for (int rt = 0; rt < MaxCT; ++rt)
 #pragma unroll
-                for (int ct = rt; ct < kMfmaMaxCT; ++ct, ++t) {
+                for (int ct = rt; ct < MaxCT; ++ct, ++t) {
                     if (!(rt < RT && ct < CT)) continue;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -2095,15 +2099,15 @@ __global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
         }
         wave_sync();
         // rescore from the FP32 rows staged 32 dimensions at a time
-        switch (__builtin_amdgcn_readfirstlane((m + 7) >> 3)) {
+        switch (min(__builtin_amdgcn_readfirstlane((m + 7) >> 3), NGmax)) {
             case 1: rescore_staged<1>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 2: rescore_staged<2>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 3: rescore_staged<3>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 4: rescore_staged<4>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 5: rescore_staged<5>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 6: rescore_staged<6>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            case 7: rescore_staged<7>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
-            default: rescore_staged<8>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 2: rescore_staged<(NGmax < 2 ? NGmax : 2)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 3: rescore_staged<(NGmax < 3 ? NGmax : 3)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 4: rescore_staged<(NGmax < 4 ? NGmax : 4)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 5: rescore_staged<(NGmax < 5 ? NGmax : 5)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 6: rescore_staged<(NGmax < 6 ? NGmax : 6)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            case 7: rescore_staged<(NGmax < 7 ? NGmax : 7)>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
+            default: rescore_staged<NGmax>(v, s_pos[w], m, s_surv, s_tot, nsv, s_rows); break;
         }
         rescored += nsv;
         // exact filter on the rescored keys: count, reserve, write
@@ -2131,7 +2135,8 @@ __global__ __launch_bounds__(256, 2) void k_join_bf16(Views v) {
 }
 
 // Waves per workgroup: four where the device's LDS per workgroup holds them.
-void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+template <int MaxCT, int NGmax>
+static void launch_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     static const int lds_max = [] {
         int dev = 0, lim = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -2141,7 +2146,7 @@ void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
     }();
     static const size_t lds_static = [] {
         hipFuncAttributes a{};
-        return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_join_bf16)) == hipSuccess
+        return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_join_bf16<MaxCT, NGmax>)) == hipSuccess
                    ? (size_t)a.sharedSizeBytes
                    : (size_t)kJoinWaves * 64 * 52;
     }();
@@ -2149,9 +2154,25 @@ void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e
     int wpb = kJoinWaves;
     while (wpb > 1 && lds_static + (size_t)wpb * wb > (size_t)lds_max) wpb >>= 1;
     const size_t lds = (size_t)wpb * wb;
-    if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_join_bf16),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    launch_timed(k_join_bf16, dim3(grid_for(v.N, wpb, pass_cap(v))), dim3(64 * wpb), lds, s, e0, e1, v);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_join_bf16<MaxCT, NGmax>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    launch_timed(k_join_bf16<MaxCT, NGmax>, dim3(grid_for(v.N, wpb, pass_cap(v))), dim3(64 * wpb), lds, s, e0, e1,
+                 v);
+}
+
+void launch_join_bf16(const Views& v, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int C2 = 2 * v.C;
+    if (C2 <= 24)
+        launch_bf16<2, 3>(v, s, e0, e1);
+    else if (C2 <= 32)
+        launch_bf16<2, 4>(v, s, e0, e1);
+    else if (C2 <= 40)
+        launch_bf16<3, 5>(v, s, e0, e1);
+    else if (C2 <= 48)
+        launch_bf16<3, 6>(v, s, e0, e1);
+    else
+        launch_bf16<4, 8>(v, s, e0, e1);
 }
 
 // ------------------------------------------------------------------ split-BF16 Gram form

@@ -215,7 +215,7 @@ def bench_batch(args, w):
     ms_per_step = wall * 1e3 / args.steps
     st = b.stats()
     evals = int(sum(sum(e) for e in st["evals"]))
-    entries = dict(e.split(":") for e in b.tuning.split(","))
+    entries = {d: r.partition("@")[0] for d, r in (e.split(":") for e in b.tuning.split(","))}   # path per d
     # the same builds one dataset at a time (same join paths)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

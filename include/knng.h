@@ -217,11 +217,17 @@ knng_status knng_create(knng_ctx** out, const float* dX, int64_t N, int32_t d,
  * the hash, all flagged new, rows sorted by (distance, id). Sets t = 0. */
 knng_status knng_init_graph(knng_ctx* ctx);
 
-/* Load a graph state: d_ids[N*K] int32 original ids (row u = point u) and
- * d_flags[N*K] uint8 (1 = new, 0 = old); distances are recomputed on the
- * device and rows re-sorted by (distance, id). Sets the iteration counter to
- * t (the next iterate runs t+1). Only valid before any permutation. */
-knng_status knng_load_graph(knng_ctx* ctx, const int32_t* d_ids, const uint8_t* d_flags, int32_t t);
+/* Load a graph state: d_ids[N*K] int32 original ids (row u = point u),
+ * d_dists[N*K] float squared l2 or NULL, and d_flags[N*K] uint8 (1 = new,
+ * 0 = old); rows are re-sorted by (distance, id). With d_dists (a state from
+ * knng_export) the distances are kept bit for bit, so the build continues
+ * exactly as the exporting one would; with NULL they are recomputed on the
+ * device in the form init uses. A row with an id out of range, its own id, a
+ * repeated id, or a distance that is negative or not finite is rejected
+ * (KNNG_EINVAL, no graph loaded). Sets the iteration counter to t (the next
+ * iterate runs t+1). Only valid before any permutation of this context. */
+knng_status knng_load_graph(knng_ctx* ctx, const int32_t* d_ids, const float* d_dists, const uint8_t* d_flags,
+                            int32_t t);
 
 /* One synchronous iteration t+1: sample (Sec. 3.1), local join (Sec. 2,
  * Sec. 3.3), merge. Applies the permutation after iteration t_p when

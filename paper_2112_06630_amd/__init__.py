@@ -74,7 +74,7 @@ def _load() -> ctypes.CDLL:
     L.knng_build_noalloc.argtypes = [P, i64, i32, PP, P, P, P, ctypes.POINTER(_Stats)]
     L.knng_create.argtypes = [ctypes.POINTER(P), P, i64, i32, PP, P, sz, P]
     L.knng_init_graph.argtypes = [P]
-    L.knng_load_graph.argtypes = [P, P, P, i32]
+    L.knng_load_graph.argtypes = [P, P, P, P, i32]
     L.knng_iterate.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.knng_export.argtypes = [P, P, P, P]
     L.knng_export_samples.argtypes = [P, P, P, P]
@@ -245,10 +245,17 @@ class Context:
     def init(self):
         _check(lib.knng_init_graph(self._h))
 
-    def load(self, ids: torch.Tensor, flags: torch.Tensor, t: int):
+    def load(self, ids: torch.Tensor, flags: torch.Tensor, t: int, dists: torch.Tensor | None = None):
+        """Load a state; with ``dists`` (as exported) the keys are kept bit
+        for bit, without them the distances are recomputed."""
         ids = ids.to(device=self.X.device, dtype=torch.int32).contiguous()
         flags = flags.to(device=self.X.device, dtype=torch.uint8).contiguous()
-        _check(lib.knng_load_graph(self._h, ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(flags.data_ptr()), t))
+        dp = None
+        if dists is not None:
+            dists = dists.to(device=self.X.device, dtype=torch.float32).contiguous()
+            dp = ctypes.c_void_p(dists.data_ptr())
+        _check(lib.knng_load_graph(self._h, ctypes.c_void_p(ids.data_ptr()), dp, ctypes.c_void_p(flags.data_ptr()),
+                                   t))
         torch.cuda.current_stream(self.X.device).synchronize()
 
     def iterate(self) -> tuple[int, int]:

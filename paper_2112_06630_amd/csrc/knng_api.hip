@@ -760,14 +760,15 @@ knng_status knng_init_graph(knng_ctx* c) {
     return KNNG_OK;
 }
 
-knng_status knng_load_graph(knng_ctx* c, const int32_t* d_ids, const uint8_t* d_flags, int32_t t) {
+knng_status knng_load_graph(knng_ctx* c, const int32_t* d_ids, const float* d_dists, const uint8_t* d_flags,
+                            int32_t t) {
     if (!c) return fail(KNNG_EINVAL, "ctx is NULL");
     if (!d_ids || !d_flags) return fail(KNNG_EINVAL, "ids/flags are NULL");
     if (c->permuted) return fail(KNNG_EINVAL, "load after permutation is not supported");
     if (t < 0 || t >= KNNG_MAX_ITERS) return fail(KNNG_EINVAL, "t out of range");
     launch_fill_u64(c->v.counters, 0ull, kNumCounters, c->stream);
     launch_fill_u32(c->v.stop, 0u, 1, c->stream);
-    launch_load_rows(c->v, d_ids, d_flags, dist_mode(c), c->stream);
+    launch_load_rows(c->v, d_ids, d_dists, d_flags, dist_mode(c), c->stream);
     HIP_TRY(hipGetLastError());
     knng_status rs = read_counters(c);
     if (rs != KNNG_OK) return rs;

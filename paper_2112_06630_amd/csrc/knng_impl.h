@@ -137,7 +137,8 @@ void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s, const ui
 void launch_pad_rows(const float* X, const Views& v, hipStream_t s);
 void launch_norms(const Views& v, hipStream_t s);
 void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s);
-void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int mode, hipStream_t s);
+void launch_load_rows(const Views& v, const int32_t* ids, const float* dists, const uint8_t* flags, int mode,
+                      hipStream_t s);
 void launch_make_split(const Views& v, hipStream_t s);
 // one pass over X for the MFMA forms: padded rows, norms, identity positions,
 // finiteness check and (split != 0) the split-BF16 planes

@@ -526,12 +526,18 @@ __device__ __forceinline__ float wave_gram_dists64(const T* __restrict__ rows, i
 
 // Lanes < K hold one entry each (position `pid` of the neighbour, NEW flag in
 // pf). Computes D against row u, ranks the K keys and writes the sorted row.
-__device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, uint32_t pf, int mode) {
+// With `given` (a caller's state), the distances are taken as they are
+// (given[u K + lane]) instead of computed, so that a state exported and
+// loaded again keeps its keys bit for bit.
+__device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, uint32_t pf, int mode,
+                                           const float* given = nullptr) {
     const int lane = lane_id();
     const int K = v.K;
     uint64_t key = ~0ull;
     float Dg = 0.f;
-    if (mode == kDistGram) {   // whole wave
+    if (given) {
+        if (lane < K) Dg = given[(size_t)u * K + lane];
+    } else if (mode == kDistGram) {   // whole wave
         const bool plane = v.Xs && v.planes == 1;
         if (v.u8)
             Dg = wave_gram_dists(reinterpret_cast<const uint2*>(v.Xs + (size_t)v.N * v.dp), v.dp >> 3, v.dp >> 3, u,
@@ -547,7 +553,7 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     }
     if (lane < K) {
         float D;
-        if (mode == kDistGram) {
+        if (given || mode == kDistGram) {
             D = Dg;
         } else {
             const float* a = v.Xp + (size_t)u * v.dp;
@@ -615,16 +621,20 @@ void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s) {
 // Load a caller state: ids are original ids (positions equal ids before any
 // permutation); distances recomputed, rows re-sorted by key.
 __global__ __launch_bounds__(256) void k_load_rows(Views v, const int32_t* __restrict__ ids,
-                                                   const uint8_t* __restrict__ flags, int mode) {
+                                                   const float* __restrict__ dists, const uint8_t* __restrict__ flags,
+                                                   int mode) {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     for (int u = blockIdx.x * kRowWaves + w; u < v.N; u += gridDim.x * kRowWaves) {
         uint32_t pid = 0, pf = 0;
+        float D = 0.f;
         if (lane < v.K) {
             pid = (uint32_t)ids[(size_t)u * v.K + lane];
             pf = flags[(size_t)u * v.K + lane] ? kNewBit : 0u;
+            if (dists) D = dists[(size_t)u * v.K + lane];
         }
-        // a row must hold K distinct ids in [0, N), none equal to u
-        bool bad = lane < v.K && (pid >= (uint32_t)v.N || pid == (uint32_t)u);
+        // a row must hold K distinct ids in [0, N), none equal to u, and
+        // given distances must be finite and non-negative
+        bool bad = lane < v.K && (pid >= (uint32_t)v.N || pid == (uint32_t)u || !(D >= 0.f && D < INFINITY));
         for (int j = 0; j < v.K; ++j) {
             const uint32_t pj = rl32(pid, j);
             bad |= lane < v.K && j != lane && pj == pid;
@@ -633,12 +643,14 @@ __global__ __launch_bounds__(256) void k_load_rows(Views v, const int32_t* __res
             if (lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 4ull);
             continue;
         }
-        finish_row(v, u, pid, pf, mode);
+        finish_row(v, u, pid, pf, mode, dists);
     }
 }
 
-void launch_load_rows(const Views& v, const int32_t* ids, const uint8_t* flags, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_load_rows, dim3(grid_for(v.N, kRowWaves, 65536)), dim3(256), 0, s, v, ids, flags, mode);
+void launch_load_rows(const Views& v, const int32_t* ids, const float* dists, const uint8_t* flags, int mode,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_load_rows, dim3(grid_for(v.N, kRowWaves, 65536)), dim3(256), 0, s, v, ids, dists, flags,
+                       mode);
 }
 
 // ------------------------------------------------------------------ scan
@@ -1486,6 +1498,13 @@ __device__ __forceinline__ int pool_size(const Views& v, int u) {
     return v.K + (int)(v.roff[u + 1] - v.roff[u]);
 }
 
+// pool_size with the reverse offsets roff[u], roff[u + 1] already read
+__device__ __forceinline__ int pool_size_from(const Views& v, int u, uint32_t r0, uint32_t r1) {
+    if (u >= v.N || (v.ds && !pos_active(v, u))) return 0;
+    if (v.blk_on && (v.orig[u] < v.blk_lo || v.orig[u] >= v.blk_hi)) return 0;   // not this block's owner
+    return v.K + (int)(r1 - r0);
+}
+
 // Owners in pairs: two pools of at most 32 entries share one wave (one
 // 32-lane segment each: a 15-stage sort instead of 21); two pools of at most
 // 64 are sorted side by side in the wave's registers; otherwise each owner
@@ -1503,9 +1522,24 @@ __global__ __launch_bounds__(256, 6) void k_select_small(Views v, uint64_t st0, 
     const int N = v.N;
     const bool thr_inline = 2 * v.C <= 60;
     const int pairs = (N + 1) >> 1;
-    for (int pr = blockIdx.x * kSelWaves + w; pr < pairs; pr += gridDim.x * kSelWaves) {
+    // the next pair's reverse offsets are read while this pair is selected
+    const int step = gridDim.x * kSelWaves;
+    int pr = blockIdx.x * kSelWaves + w;
+    uint32_t q0 = 0, q1 = 0, q2 = 0;
+    if (pr < pairs) {
+        q0 = v.roff[2 * pr];
+        q1 = v.roff[2 * pr + 1];
+        q2 = v.roff[min(2 * pr + 2, N)];
+    }
+    for (; pr < pairs; pr += step) {
         const int u0 = 2 * pr, u1 = u0 + 1;
-        const int P0 = pool_size(v, u0), P1 = pool_size(v, u1);
+        const uint32_t r0 = q0, r1 = q1, r2 = q2;
+        if (pr + step < pairs) {
+            q0 = v.roff[2 * (pr + step)];
+            q1 = v.roff[2 * (pr + step) + 1];
+            q2 = v.roff[min(2 * (pr + step) + 2, N)];
+        }
+        const int P0 = pool_size_from(v, u0, r0, r1), P1 = pool_size_from(v, u1, r1, r2);
         if (lane == 0) {
             v.big[u0] = P0 > 64 && !thr_inline ? 1u : 0u;
             if (u1 < N) v.big[u1] = P1 > 64 && !thr_inline ? 1u : 0u;

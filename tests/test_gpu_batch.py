@@ -129,7 +129,8 @@ def test_batch_autotune_table(knng):
     Xs = [dev(X) for X, _ in data]
     b = knng.Batch(Xs, [s for _, s in data], 15, 1.0, 0.001, 30)
     table = b.tuning
-    entries = dict(e.split(":") for e in table.split(","))
+    # "d:path" or "d:path@cap" (workgroup cap of the select and join passes)
+    entries = {d: rest.partition("@")[0] for d, rest in (e.split(":") for e in table.split(","))}
     assert set(entries) == {str(X.shape[1]) for X, _ in data}
     assert set(entries.values()) <= {"valu", "mfma", "bf16x3"}
     b.execute()

@@ -231,7 +231,7 @@ def test_batch512_equals_sequential_builds(knng):
     Xs = [_dev(X) for X, _ in data]
     seeds = [s for _, s in data]
     b = knng.Batch(Xs, seeds, 15, 1.0, 0.001, 30)
-    entries = dict(e.split(":") for e in b.tuning.split(","))
+    entries = {d: r.partition("@")[0] for d, r in (e.split(":") for e in b.tuning.split(","))}
     b.capture()
     b.launch()
     b.synchronize()

@@ -627,3 +627,54 @@ def test_tiny_inputs_precision_form(knng, N):
     assert st["evals"] == ref.evals.tolist() and st["changes"] == ref.changes.tolist()
     assert np.array_equal(ids.cpu().numpy(), ref.ids)
     assert np.array_equal(dists.cpu().numpy().astype(np.float64), ref.dists)
+
+
+# ----------------------------------------------------------------- resume from an exported state
+
+@pytest.mark.parametrize("path,gen", [("bf16x3", "aniso"), ("valu", "gauss"), ("mfma", "gauss"),
+                                      ("bf16x3", "aniso_bf16")])
+def test_resume_from_export_is_bitwise(knng, path, gen):
+    """A state exported after t iterations and loaded with its distances into
+    a new context continues exactly as the exporting build (continuous data:
+    the keys are not recomputed): e_t, c_t and the final graph bit for bit."""
+    if gen.startswith("aniso"):
+        X = synth.anisotropic_clusters(1500, 200, 3, 12)
+    else:
+        X = synth.gaussian_mixture(1500, 16 if path == "valu" else 64, 12, 4)
+    prec = "bf16" if gen.endswith("bf16") else "fp32"
+    if prec == "bf16":
+        path = "auto"
+    K, rho, seed = 12, 0.8, 9
+    a = knng.Context(dev(X), K, rho, 0.001, 30, seed, path=path, precision=prec)
+    a.init()
+    for _ in range(3):
+        a.iterate()
+    g = a.export()
+    b = knng.Context(dev(X), K, rho, 0.001, 30, seed, path=path, precision=prec)
+    b.load(g.ids, g.flags, 3, dists=g.dists)
+    gb = b.export()
+    assert torch.equal(g.ids, gb.ids) and torch.equal(g.dists, gb.dists) and torch.equal(g.flags, gb.flags)
+    for _ in range(4):
+        assert a.iterate() == b.iterate()
+    ea, eb = a.export(), b.export()
+    assert torch.equal(ea.ids, eb.ids) and torch.equal(ea.dists, eb.dists) and torch.equal(ea.flags, eb.flags)
+    a.close()
+    b.close()
+
+
+def test_load_rejects_bad_distances(knng):
+    X = synth.gaussian_mixture(300, 8, 4, 1)
+    a = knng.Context(dev(X), 6, 1.0, 0.001, 10, 1, path="valu")
+    a.init()
+    g = a.export()
+    bad = g.dists.clone()
+    bad[5, 2] = -1.0
+    b = knng.Context(dev(X), 6, 1.0, 0.001, 10, 1, path="valu")
+    with pytest.raises(Exception):
+        b.load(g.ids, g.flags, 0, dists=bad)
+    bad[5, 2] = float("nan")
+    with pytest.raises(Exception):
+        b.load(g.ids, g.flags, 0, dists=bad)
+    b.load(g.ids, g.flags, 0, dists=g.dists)
+    a.close()
+    b.close()

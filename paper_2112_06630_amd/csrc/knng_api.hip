@@ -69,7 +69,9 @@ struct Plan {
     // byte offsets
     size_t o_Xp, o_nrm, o_nrm64, o_nrm64_2, o_orig, o_posof, o_lkey, o_lpos, o_kth, o_kth2, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
-        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp;
+        o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp,
+        o_rk, o_rk2;
+    int rowkey = 0;  // RowKey records (low-d direct form of a single build)
 };
 
 knng_status validate(int64_t N, int32_t d, const knng_params* p) {
@@ -99,7 +101,7 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
 constexpr int kAutoMatrixMinD = 48;
 constexpr int kAutoSplit3MinD = 192;
 
-knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
+knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool rowkey_ok = true) {
     knng_status s = validate(N, d, p);
     if (s != KNNG_OK) return s;
     const int K = p->K;
@@ -150,6 +152,8 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
     P.o_lkey = take(NK * 8);
     P.o_lpos = take(NK * 4);
     P.o_kth = take((size_t)N * 8);
+    P.rowkey = rowkey_ok && path == KNNG_PATH_VALU && P.dp == 4 ? 1 : 0;
+    if (P.rowkey) P.o_rk = take((size_t)N * sizeof(RowKey));
     P.o_cnt4 = take((size_t)N * 4 * 4);   // rdeg, rcur, cap, pcnt: one fill
     P.o_roff = take(((size_t)N + 1) * 4);
     P.o_rev = take(NK * 16);
@@ -187,6 +191,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P) {
         P.o_lkey2 = take(NK * 8);
         P.o_lpos2 = take(NK * 4);
         P.o_kth2 = take((size_t)N * 8);
+        if (P.rowkey) P.o_rk2 = take((size_t)N * sizeof(RowKey));
         P.o_Xp2 = take((size_t)N * P.dp * 4);
         P.o_nrm2 = take((size_t)N * 4);
         P.o_nrm64_2 = path != KNNG_PATH_VALU ? take((size_t)N * 8) : 0;
@@ -238,6 +243,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     v.lkey = reinterpret_cast<uint64_t*>(b + P.o_lkey);
     v.lpos = reinterpret_cast<uint32_t*>(b + P.o_lpos);
     v.kth = reinterpret_cast<uint64_t*>(b + P.o_kth);
+    if (P.rowkey) v.rk = reinterpret_cast<RowKey*>(b + P.o_rk);
     uint32_t* c4 = reinterpret_cast<uint32_t*>(b + P.o_cnt4);
     v.rdeg = c4;
     v.rcur = c4 + N;
@@ -275,6 +281,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
         v.lkey2 = reinterpret_cast<uint64_t*>(b + P.o_lkey2);
         v.lpos2 = reinterpret_cast<uint32_t*>(b + P.o_lpos2);
         v.kth2 = reinterpret_cast<uint64_t*>(b + P.o_kth2);
+        if (P.rowkey) v.rk2 = reinterpret_cast<RowKey*>(b + P.o_rk2);
         v.Xp2 = reinterpret_cast<float*>(b + P.o_Xp2);
         v.nrm2 = reinterpret_cast<float*>(b + P.o_nrm2);
         if (P.path != KNNG_PATH_VALU) v.nrm64_2 = reinterpret_cast<double*>(b + P.o_nrm64_2);
@@ -401,6 +408,7 @@ knng_status do_permute(knng_ctx* c) {
     std::swap(v.lkey, v.lkey2);
     std::swap(v.lpos, v.lpos2);
     std::swap(v.kth, v.kth2);
+    std::swap(v.rk, v.rk2);
     std::swap(v.Xb, v.Xb2);
     std::swap(v.nb, v.nb2);
     if (v.Xs) std::swap(v.Xs, v.Xs2);
@@ -1012,7 +1020,7 @@ knng_status batch_groups(const knng_dataset* descs, int32_t n, const knng_params
         gp.path = g.path;
         gp.reorder = 0;
         Plan P{};
-        knng_status s = make_plan(g.N, g.d, &gp, P);
+        knng_status s = make_plan(g.N, g.d, &gp, P, false);   // batch setup lays out Xp rows only
         if (s != KNNG_OK) return s;
         g.plan = P;
         g.off = total;

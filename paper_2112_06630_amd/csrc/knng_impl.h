@@ -37,6 +37,15 @@ enum DistMode : int {
 };
 
 // Views of the caller's workspace, carved by the host.
+// Low-d direct form (rows of 4 floats): a point's padded row and its list's
+// K-th key in one 32-byte record, so that the join's member gather (the row
+// and the snapshot key) touches one cache line instead of two.
+struct RowKey {
+    float4 x;
+    uint64_t kth;
+    uint64_t pad;
+};
+
 struct Views {
     int N, d, dp, K, C;
     int turbo;          // 1: turbosampling coin in the sampling step (Sec. 3.1)
@@ -61,6 +70,8 @@ struct Views {
     uint32_t* lpos;     // [N, K] position of the neighbour | kNewBit
     uint64_t* kth;      // [N] the list's K-th key (lkey[p, K-1]), written with the list: the joins'
                         // snapshot filter reads 8 bytes per member instead of a line of its list
+    RowKey* rk;         // [N] low-d direct form only (dp == 4, single builds): rows and K-th keys
+                        // together; the K-th keys are then kept here instead of in kth; else null
     uint32_t* rdeg;     // [N] reverse in-degree
     uint32_t* roff;     // [N + 1] reverse bucket offsets
     uint32_t* rcur;     // [N] reverse bucket cursors
@@ -113,6 +124,7 @@ struct Views {
     uint64_t* lkey2;    // [N, K] permuted copies (swapped with the originals)
     uint32_t* lpos2;    // [N, K]
     uint64_t* kth2;     // [N]
+    RowKey* rk2;        // [N]
     float* Xp2;         // [N, dp]
     float* nrm2;        // [N]
     double* nrm64_2;    // [N]

@@ -335,7 +335,8 @@ void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s, const ui
 
 // Rows padded to dp floats (zeros), identity permutation, finiteness check.
 __global__ void k_pad_rows(const float* __restrict__ X, int N, int d, int dp, float* __restrict__ Xp,
-                           int32_t* __restrict__ orig, int32_t* __restrict__ posof, uint64_t* counters) {
+                           int32_t* __restrict__ orig, int32_t* __restrict__ posof, uint64_t* counters,
+                           RowKey* __restrict__ rk) {
     const int64_t total = (int64_t)N * dp;
     bool bad = false;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -344,6 +345,7 @@ __global__ void k_pad_rows(const float* __restrict__ X, int N, int d, int dp, fl
         const float x = c < d ? X[r * d + c] : 0.f;
         bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
         Xp[i] = x;
+        if (rk) reinterpret_cast<float*>(&rk[r].x)[c] = x;   // dp == 4 here
         if (c == 0) {
             orig[r] = (int32_t)r;
             posof[r] = (int32_t)r;
@@ -354,7 +356,7 @@ __global__ void k_pad_rows(const float* __restrict__ X, int N, int d, int dp, fl
 
 void launch_pad_rows(const float* X, const Views& v, hipStream_t s) {
     hipLaunchKernelGGL(k_pad_rows, dim3(grid_for((int64_t)v.N * v.dp, 1024, 8192)), dim3(256), 0, s, X, v.N, v.d,
-                       v.dp, v.Xp, v.orig, v.posof, v.counters);
+                       v.dp, v.Xp, v.orig, v.posof, v.counters, v.rk);
 }
 
 // Squared norms of padded rows, one wave per row, in the order k_prep uses
@@ -567,7 +569,12 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     if (lane < K) {
         v.lkey[(size_t)u * K + rank] = key;
         v.lpos[(size_t)u * K + rank] = pid | pf;
-        if (rank == K - 1) v.kth[u] = key;
+        if (rank == K - 1) {   // the joins read the record when there is one
+            if (v.rk)
+                v.rk[u].kth = key;
+            else
+                v.kth[u] = key;
+        }
     }
 }
 
@@ -1659,19 +1666,32 @@ __global__ __launch_bounds__(256) void k_join_valu(Views v) {
             continue;
         }
         const uint2* cs = v.cand + (size_t)u * C2;
-        for (int i = lane; i < m; i += 64) {
-            const uint2 c = cs[i];
-            oid[i] = c.x;
-            opos[i] = c.y;
-            thr[i] = v.kth[c.y];
+        if (v.rk) {   // rows of 4 floats: the row and the K-th key from one record
+            for (int i = lane; i < m; i += 64) {
+                const uint2 c = cs[i];
+                const RowKey* rec = v.rk + c.y;
+                const float4 x = rec->x;
+                oid[i] = c.x;
+                opos[i] = c.y;
+                thr[i] = rec->kth;
+                reinterpret_cast<float4*>(rows)[i] = x;
+            }
+            wave_sync();
+        } else {
+            for (int i = lane; i < m; i += 64) {
+                const uint2 c = cs[i];
+                oid[i] = c.x;
+                opos[i] = c.y;
+                thr[i] = v.kth[c.y];
+            }
+            wave_sync();
+            for (int idx = lane; idx < m * dp4; idx += 64) {
+                const int r = (int)udiv((uint32_t)idx, (uint32_t)dp4, rdp4), c = idx - r * dp4;
+                reinterpret_cast<float4*>(rows)[idx] =
+                    reinterpret_cast<const float4*>(v.Xp + (size_t)opos[r] * dp)[c];
+            }
+            wave_sync();
         }
-        wave_sync();
-        for (int idx = lane; idx < m * dp4; idx += 64) {
-            const int r = (int)udiv((uint32_t)idx, (uint32_t)dp4, rdp4), c = idx - r * dp4;
-            reinterpret_cast<float4*>(rows)[idx] =
-                reinterpret_cast<const float4*>(v.Xp + (size_t)opos[r] * dp)[c];
-        }
-        wave_sync();
         const int ncell = nnew * m;
         const double rm = 1.0 / m;
         for (int pass = 0; pass < 2; ++pass) {
@@ -2830,7 +2850,12 @@ __device__ __forceinline__ uint64_t finish_merged_row(const Views& v, int p, uin
     if (lane < K) {
         v.lkey[row + lane] = key;
         v.lpos[row + lane] = pf;
-        if (lane == K - 1) v.kth[row / K] = key;
+        if (lane == K - 1) {   // the joins read the record when there is one
+            if (v.rk)
+                v.rk[row / K].kth = key;
+            else
+                v.kth[row / K] = key;
+        }
     }
     const uint64_t c = (uint64_t)__popcll(em);
     if (v.chg && lane == 0) v.chg[row / K] = (uint32_t)c;   // batched form: changes per target
@@ -3298,6 +3323,7 @@ __global__ void k_perm_rows(Views v) {
         if (fp32_rows_used(v))
             reinterpret_cast<float4*>(v.Xp2 + (size_t)q * v.dp)[c] =
                 reinterpret_cast<const float4*>(v.Xp + (size_t)p * v.dp)[c];
+        if (v.rk && c == 0) v.rk2[q].x = v.rk[p].x;
         if (c == 0) {
             v.orig2[q] = v.orig[p];
             v.nrm2[q] = v.nrm[p];
@@ -3362,7 +3388,12 @@ __global__ void k_perm_lists(Views v) {
         const size_t to = (size_t)q * v.K + k;
         v.lkey2[to] = v.lkey[e];
         v.lpos2[to] = (uint32_t)qn | (pf & kNewBit);
-        if (k == v.K - 1) v.kth2[q] = v.lkey[e];
+        if (k == v.K - 1) {
+            if (v.rk)
+                v.rk2[q].kth = v.lkey[e];
+            else
+                v.kth2[q] = v.lkey[e];
+        }
     }
 }
 

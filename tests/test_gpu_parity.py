@@ -451,12 +451,14 @@ def test_deterministic_repeat(knng):
 
 # ----------------------------------------------------------------- permutation (Sec. 3.2)
 
-@pytest.mark.parametrize("path", ["valu", "mfma", "bf16x3", pytest.param("mfma_i8", marks=I8_OFF)])
+@pytest.mark.parametrize("path", ["valu", "valu3", "mfma", "bf16x3", pytest.param("mfma_i8", marks=I8_OFF)])
 @pytest.mark.parametrize("tp", [1, 3])
 def test_permutation_is_result_invisible_integer(knng, path, tp):
     """Reordering changes storage only: ids, distances, e_t, c_t stay bitwise
-    equal, whether the permutation runs after iteration 1 or later."""
-    d = 8 if path == "valu" else 72
+    equal, whether the permutation runs after iteration 1 or later (d = 3:
+    rows and K-th keys in one record, moved together)."""
+    d = 8 if path == "valu" else 3 if path == "valu3" else 72
+    path = "valu" if path == "valu3" else path
     X = synth.integer_points(3000, d, 9, 21)
     a = knng.build(dev(X), 12, 0.8, 0.001, 15, 5, reorder=False, path=path)
     b = knng.build(dev(X), 12, 0.8, 0.001, 15, 5, reorder=tp, path=path)
@@ -553,7 +555,7 @@ def test_bf16_screen_with_permutation(knng):
 
 # ----------------------------------------------------------------- block-asynchronous iteration
 
-@pytest.mark.parametrize("path,d", [("valu", 8), ("bf16x3", 72), ("mfma", 72)])
+@pytest.mark.parametrize("path,d", [("valu", 8), ("valu", 3), ("bf16x3", 72), ("mfma", 72)])
 @pytest.mark.parametrize("B,reorder", [(4, 0), (16, 0), (5, 2)])
 def test_block_async_integer_bitwise(knng, path, d, B, reorder):
     """Block-asynchronous builds (blocks of consecutive owner ids in order,
@@ -631,8 +633,8 @@ def test_tiny_inputs_precision_form(knng, N):
 
 # ----------------------------------------------------------------- resume from an exported state
 
-@pytest.mark.parametrize("path,gen", [("bf16x3", "aniso"), ("valu", "gauss"), ("mfma", "gauss"),
-                                      ("bf16x3", "aniso_bf16")])
+@pytest.mark.parametrize("path,gen", [("bf16x3", "aniso"), ("valu", "gauss"), ("valu", "gauss3"),
+                                      ("mfma", "gauss"), ("bf16x3", "aniso_bf16")])
 def test_resume_from_export_is_bitwise(knng, path, gen):
     """A state exported after t iterations and loaded with its distances into
     a new context continues exactly as the exporting build (continuous data:
@@ -640,7 +642,7 @@ def test_resume_from_export_is_bitwise(knng, path, gen):
     if gen.startswith("aniso"):
         X = synth.anisotropic_clusters(1500, 200, 3, 12)
     else:
-        X = synth.gaussian_mixture(1500, 16 if path == "valu" else 64, 12, 4)
+        X = synth.gaussian_mixture(1500, 3 if gen == "gauss3" else 16 if path == "valu" else 64, 12, 4)
     prec = "bf16" if gen.endswith("bf16") else "fp32"
     if prec == "bf16":
         path = "auto"

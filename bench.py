@@ -426,6 +426,27 @@ def join_kernel_name(knng, s0, precision):
     return {knng.PATH_MFMA: "k_join_mfma", knng.PATH_MFMA_BF16X3: "k_join_split"}.get(s0["path"], "k_join_valu")
 
 
+def member_encoding(kernel, s0, dpad):
+    """(row bytes, all bytes) the join reads per member as the library stores
+    them: byte rows (8-bit data) or the split-BF16 planes it reads, with the
+    member's sample entry (8 B), snapshot K-th key (8 B) and squared norm (4 B,
+    8 B in FP64 on inexact data); the precision form's BF16 copy, its
+    staged FP32 row and the copy's two norms (8 B); the direct form's FP32
+    row with the sample entry and the K-th key, which share one 32-byte
+    record with a 4-float row."""
+    norm = 8 if s0.get("accurate") else 4
+    if kernel == "k_join_split":
+        row = dpad if s0.get("u8") else 2 * dpad * max(1, s0["planes"])
+        return row, row + 16 + norm
+    if kernel == "k_join_mfma":
+        return 4 * dpad, 4 * dpad + 16 + norm
+    if kernel == "k_join_bf16":
+        return 6 * dpad, 6 * dpad + 16 + 8
+    if dpad == 4:
+        return 16, 32 + 8
+    return 4 * dpad, 4 * dpad + 16
+
+
 def join_roofline(knng, w, s0, stats, members, precision):
     """Roofline of the local join from its event-timed launches.
 
@@ -433,12 +454,10 @@ def join_roofline(knng, w, s0, stats, members, precision):
     byte model: every member row gathered once per owner in FP32
     (4 * d_pad bytes, no reuse across owners), its sample entry read (8 B),
     and one 8-byte key written per emitted proposal. ``encoding`` prices the
-    rows as the kernel actually stores them (2 * d_pad bytes per split-BF16
-    plane read; the FP32 row otherwise) plus the 20 B of member metadata it
-    reads (sample entry 8, snapshot K-th key 8, norm 4): on data that is
-    exact in one BF16 plane this is about half the FP32 figure, and the
-    FP32-model fraction can then exceed 1 without the kernel moving more
-    than the memory system delivers. ``traffic`` is the counter-measured
+    rows as the kernel actually stores them, with the member metadata it
+    reads (member_encoding): on 8-bit data (byte rows) this is about a
+    quarter of the FP32 figure, and the FP32-model fraction can then exceed 1
+    without the kernel moving more than the memory system delivers. ``traffic`` is the counter-measured
     L2-to-memory traffic of the same kernel (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, scaled by a copy of known size), when the committed counter
     summary was taken on the current source."""
@@ -447,9 +466,8 @@ def join_roofline(knng, w, s0, stats, members, precision):
     join_ms = [float(np.median([s["join_ms"][i] for s in stats])) for i in range(s0["iters"])]
     dpad = s0["dpad"]
     alg = [m * (4 * dpad + 8) + 8 * pr for m, pr in zip(members, s0["proposals"])]
-    enc_row = {"k_join_split": (dpad if s0.get("u8") else 2 * dpad * max(1, s0["planes"])),
-               "k_join_bf16": 2 * dpad}.get(kernel, 4 * dpad)
-    enc = [m * (enc_row + 20) + 8 * pr for m, pr in zip(members, s0["proposals"])]
+    enc_row, enc_member = member_encoding(kernel, s0, dpad)
+    enc = [m * enc_member + 8 * pr for m, pr in zip(members, s0["proposals"])]
     flops = [e * 2 * w["d"] for e in s0["evals"]]
     sec = sum(join_ms) / 1e3
     ach = sum(alg) / sec / 1e9
@@ -463,7 +481,7 @@ def join_roofline(knng, w, s0, stats, members, precision):
             "avg_launch_ms": round(sum(join_ms) / n, 4), "launches": n,
             "bytes_per_launch": int(sum(alg) / n), "members_per_launch": int(sum(members) / n),
             "proposals_per_launch": int(sum(s0["proposals"]) / n),
-            "encoding": {"row_bytes": enc_row, "bytes_per_launch": int(sum(enc) / n),
+            "encoding": {"row_bytes": enc_row, "member_bytes": enc_member, "bytes_per_launch": int(sum(enc) / n),
                          "achieved": round(ach_enc, 1), "frac": round(ach_enc / PEAK_HBM_GBS, 4)},
             "mfma": {"achieved": round(ach_fl, 3), "peak": peak_fl, "unit": "TFLOP/s",
                      "frac": round(ach_fl / peak_fl, 4), "flops_per_launch": int(sum(flops) / n)}}
@@ -471,7 +489,7 @@ def join_roofline(knng, w, s0, stats, members, precision):
         roof["traffic_achieved"] = round(traffic * n / sec / 1e9, 1)
     if roof["frac"] > 1:
         roof["note"] = ("the FP32 row model exceeds the HBM peak: the kernel reads a lossless "
-                        f"{enc_row // dpad}-byte-per-dimension encoding of the rows (see encoding)")
+                        f"{enc_row / dpad:g}-byte-per-dimension encoding of the rows (see encoding)")
     return roof
 
 

@@ -55,10 +55,9 @@ typedef enum {
 } knng_precision;
 
 /*
- * Join paths. AUTO takes the VALU direct form when d < 48 or ceil(rho*K) > 32,
- * else (FP32 precision) the split-BF16 Gram form below, except that data
- * whose values need all three BF16 planes (counted at create) run on FP32
- * tiles (KNNG_PATH_MFMA) below d = 192, where those are faster.
+ * Join paths. AUTO takes the VALU direct form when d < 56 or ceil(rho*K) > 32,
+ * else (FP32 precision) the split-BF16 Gram form below (the measured
+ * crossover of the two on single-Gaussian data at n = 16384, K = 20).
  * KNNG_PATH_MFMA_I8 is reserved (an exact int8 form that was withdrawn):
  * requesting it fails with KNNG_EINVAL.
  */

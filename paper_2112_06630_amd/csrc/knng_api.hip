@@ -70,7 +70,7 @@ struct Plan {
     size_t o_Xp, o_nrm, o_nrm64, o_nrm64_2, o_orig, o_posof, o_lkey, o_lpos, o_kth, o_kth2, o_cnt4, o_roff, o_rev, o_cand, o_nn, o_big, o_hubs, o_poff,
         o_pkey, o_scan, o_counters, o_partial, o_Xb, o_nb, o_Xb2, o_nb2, o_comp, o_comp2, o_par, o_lvl, o_best, o_size, o_offs,
         o_cur, o_newpos, o_lkey2, o_lpos2, o_Xp2, o_nrm2, o_orig2, o_flag, o_Xs, o_Xs2, o_rev_h, o_rev_hs, o_rev_tmp,
-        o_rk, o_rk2;
+        o_rk, o_rk2, o_pdone;
     int rowkey = 0;  // RowKey records (low-d direct form of a single build)
 };
 
@@ -95,11 +95,10 @@ knng_status validate(int64_t N, int32_t d, const knng_params* p) {
 }
 
 // AUTO's join path, from the single-Gaussian sweeps (n = 16384, K = 20): the
-// direct form on the VALU up to d = 40, the matrix forms from d = 48; among
-// those, data that needs all three BF16 planes runs faster on FP32 tiles
-// below d = 192 (decided after the layout pass has counted the planes).
-constexpr int kAutoMatrixMinD = 48;
-constexpr int kAutoSplit3MinD = 192;
+// direct form on the VALU up to d = 48, the split-BF16 form from d = 56, for
+// one-plane and three-plane data alike (with FP64 step accumulation on
+// inexact data the FP32 tiles trail the split form at every d).
+constexpr int kAutoMatrixMinD = 56;
 
 knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool rowkey_ok = true) {
     knng_status s = validate(N, d, p);
@@ -180,6 +179,7 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     }
     if (p->reorder) {   // permutation scratch only when the permutation is on
         P.o_comp = take((size_t)N * 4);
+        P.o_pdone = take((size_t)N);
         P.o_comp2 = take((size_t)N * 4);
         P.o_par = take((size_t)N * 4);
         P.o_lvl = take((size_t)N * 4);
@@ -270,6 +270,7 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
     }
     if (P.reorder) {
         v.comp = reinterpret_cast<int32_t*>(b + P.o_comp);
+        v.pdone = reinterpret_cast<uint8_t*>(b + P.o_pdone);
         v.comp2 = reinterpret_cast<int32_t*>(b + P.o_comp2);
         v.par = reinterpret_cast<int32_t*>(b + P.o_par);
         v.lvl = reinterpret_cast<uint32_t*>(b + P.o_lvl);
@@ -706,8 +707,6 @@ knng_status ctx_init(knng_ctx* c, const Plan& P, const float* dX, int64_t N, int
         c->v.u8 = c->v.planes == 1 && !c->v.acc && !(used & 16u) ? 1 : 0;
         c->stats.u8 = c->v.u8;
         if (c->v.planes > 1) launch_prep_rest(dX, c->v, c->stream);
-        if (params->path == KNNG_PATH_AUTO && c->v.planes == 3 && d < kAutoSplit3MinD)
-            c->plan.path = KNNG_PATH_MFMA;   // FP32 rows and norms are in place (prep_rest, prep)
     }
     c->stats.path = c->plan.path;
     return KNNG_OK;

@@ -114,6 +114,7 @@ struct Views {
     // permutation scratch
     int32_t* comp;      // [N] component label (a position) of each point
     int32_t* comp2;     // [N] pointer-jumping scratch
+    uint8_t* pdone;     // [N] 1 once every scanned list edge of the point lies inside its component
     int32_t* par;       // [N] hook parent
     uint32_t* lvl;      // [N] hook level (kNoLevel: never hooked)
     uint64_t* best;     // [N] cheapest outgoing edge per component

@@ -3186,6 +3186,7 @@ __global__ void k_perm_init(Views v) {
         v.size[p] = 1u;
         v.cur[p] = 0u;
         v.best[p] = ~0ull;
+        v.pdone[p] = 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x < 4) v.flag[threadIdx.x] = 0u;
 }
@@ -3194,11 +3195,14 @@ __global__ void k_perm_init(Views v) {
 // Each component takes its cheapest incident edge (either end) among the
 // first kPermEdges list entries of its points; edge key (D, entry index).
 // One thread per point: the point's own component gets the minimum of its
-// edges in one update, the other ends one each.
+// edges in one update, the other ends one each. Components only merge, so a
+// point whose scanned edges all lie inside its component stays so at every
+// later level: it is marked and skipped from then on (it would add nothing).
 __global__ void k_perm_edges(Views v) {
     if (v.flag[0]) return;
     const int E = min(v.K, kPermEdges);
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < v.N; u += gridDim.x * blockDim.x) {
+        if (v.pdone[u]) continue;
         const int cu = v.comp[u];
         uint64_t mine = ~0ull;
         for (int k = 0; k < E; ++k) {
@@ -3209,6 +3213,7 @@ __global__ void k_perm_edges(Views v) {
             mine = key < mine ? key : mine;
             if (key < v.best[cv]) atomicMin((unsigned long long*)&v.best[cv], (unsigned long long)key);
         }
+        if (mine == ~0ull) v.pdone[u] = 1u;
         if (mine < v.best[cu]) atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)mine);
     }
 }

@@ -256,12 +256,11 @@ def test_integer_form_step_parity(knng):
 
 
 def test_auto_path_choice(knng):
-    """AUTO follows the crossovers of the single-Gaussian sweeps: the direct
-    form below d = 48; from 48 the split form, except that data needing all
-    three BF16 planes run on FP32 tiles below d = 192; integer pixel-like data
-    (one plane) keep the split form."""
-    for d, want in ((40, knng.PATH_VALU), (48, knng.PATH_MFMA), (160, knng.PATH_MFMA),
-                    (224, knng.PATH_MFMA_BF16X3)):
+    """AUTO follows the crossover of the single-Gaussian sweeps: the direct
+    form below d = 56, the split form from 56 (three planes on these values);
+    integer pixel-like data (one plane) take the split form too."""
+    for d, want in ((40, knng.PATH_VALU), (48, knng.PATH_VALU), (64, knng.PATH_MFMA_BF16X3),
+                    (160, knng.PATH_MFMA_BF16X3), (224, knng.PATH_MFMA_BF16X3)):
         X = synth.single_gaussian(600, d, 3)
         _, _, st = knng.build(dev(X), 10, 1.0, 0.001, 3, 3, path="auto")
         assert st["path"] == want, (d, st["path"])

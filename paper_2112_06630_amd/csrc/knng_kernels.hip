@@ -3195,26 +3195,33 @@ __global__ void k_perm_init(Views v) {
 // Each component takes its cheapest incident edge (either end) among the
 // first kPermEdges list entries of its points; edge key (D, entry index).
 // One thread per point: the point's own component gets the minimum of its
-// edges in one update, the other ends one each. Components only merge, so a
-// point whose scanned edges all lie inside its component stays so at every
-// later level: it is marked and skipped from then on (it would add nothing).
-__global__ void k_perm_edges(Views v) {
+// edges in one update, the other ends one each; an atomic is issued only
+// when it can lower the current value (unconditional atomics on the few
+// words of large components serialise: 3x slower, measured). Components only
+// merge, so a point whose scanned edges all lie inside its component stays
+// so at every later level: it is marked and skipped from then on (it would
+// add nothing). At level 0 every point is its own component, so the labels
+// are not read.
+__global__ void k_perm_edges(Views v, uint32_t level) {
     if (v.flag[0]) return;
     const int E = min(v.K, kPermEdges);
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < v.N; u += gridDim.x * blockDim.x) {
         if (v.pdone[u]) continue;
-        const int cu = v.comp[u];
+        const int cu = level ? v.comp[u] : u;
         uint64_t mine = ~0ull;
         for (int k = 0; k < E; ++k) {
             const uint32_t e = (uint32_t)u * (uint32_t)v.K + (uint32_t)k;
-            const int cv = v.comp[v.lpos[e] & kPosMask];
+            const int pv = (int)(v.lpos[e] & kPosMask);
+            const int cv = level ? v.comp[pv] : pv;
             if (cu == cv) continue;
             const uint64_t key = ((v.lkey[e] >> 32) << 32) | e;
             mine = key < mine ? key : mine;
             if (key < v.best[cv]) atomicMin((unsigned long long*)&v.best[cv], (unsigned long long)key);
         }
-        if (mine == ~0ull) v.pdone[u] = 1u;
-        if (mine < v.best[cu]) atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)mine);
+        if (mine == ~0ull)
+            v.pdone[u] = 1u;
+        else if (mine < v.best[cu])
+            atomicMin((unsigned long long*)&v.best[cu], (unsigned long long)mine);
     }
 }
 
@@ -3414,7 +3421,7 @@ void launch_perm_begin(const Views& v, hipStream_t s) {
 
 void launch_perm_level(const Views& v, uint32_t level, hipStream_t s) {
     const int g = grid_for(v.N, 256, 8192);
-    hipLaunchKernelGGL(k_perm_edges, dim3(grid_for(v.N, 256, 16384)), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_perm_edges, dim3(grid_for(v.N, 256, 16384)), dim3(256), 0, s, v, level);
     hipLaunchKernelGGL(k_perm_hook, dim3(g), dim3(256), 0, s, v, level);
     hipLaunchKernelGGL(k_perm_jump, dim3(g), dim3(256), 0, s, v, level);
     hipLaunchKernelGGL(k_perm_relabel, dim3(g), dim3(256), 0, s, v);

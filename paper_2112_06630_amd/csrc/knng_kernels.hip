@@ -3077,13 +3077,18 @@ void launch_export_samples(const Views& v, int32_t* dnew, int32_t* dold, int32_t
 // is read back, so the whole build can be captured in one graph.
 
 // one workgroup per dataset: dataset index, local ids, padded rows
+// Datasets along x, kBatchSetupSplit workgroups per dataset along y (a
+// dataset of thousands of rows is copied by that many workgroups, not one).
+constexpr int kBatchSetupSplit = 16;
+
 __global__ void k_batch_setup(Views v) {
+    const uint32_t ny = gridDim.y, y = blockIdx.y;
     for (int i = blockIdx.x; i < v.nds; i += gridDim.x) {
         const uint32_t b = v.dsbase[i], e = v.dsbase[i + 1];
         const int d = v.in_d[i];
         const float* X = v.in_X[i];
         uint32_t* dsw = const_cast<uint32_t*>(v.ds);
-        for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+        for (uint32_t p = b + y * blockDim.x + threadIdx.x; p < e; p += ny * blockDim.x) {
             dsw[p] = (uint32_t)i;
             v.orig[p] = (int32_t)(p - b);
             v.posof[p] = (int32_t)(p - b);
@@ -3091,7 +3096,7 @@ __global__ void k_batch_setup(Views v) {
         // rows by waves, columns by lanes (no division per element)
         bool bad = false;
         const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        for (uint32_t r = wv; r < e - b; r += nw) {
+        for (uint32_t r = y * nw + wv; r < e - b; r += ny * nw) {
             for (int c = lane; c < v.dp; c += 64) {
                 const float x = c < d ? X[(size_t)r * d + c] : 0.f;
                 bad |= (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u;
@@ -3099,7 +3104,7 @@ __global__ void k_batch_setup(Views v) {
             }
         }
         if (bad) flag_or(&v.counters[kCntNonFinite], 1ull);
-        if (threadIdx.x == 0) {
+        if (y == 0 && threadIdx.x == 0) {
             v.active[i] = 1u;
             v.ds_iters[i] = 0;
             v.ds_conv[i] = 0;
@@ -3108,7 +3113,7 @@ __global__ void k_batch_setup(Views v) {
 }
 
 void launch_batch_setup(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_setup, dim3(v.nds < 4096 ? v.nds : 4096), dim3(256), 0, s, v);
+    hipLaunchKernelGGL(k_batch_setup, dim3(v.nds < 4096 ? v.nds : 4096, kBatchSetupSplit), dim3(256), 0, s, v);
 }
 
 // after iteration t: per-dataset e_t and c_t from the scans over its range,

@@ -498,12 +498,36 @@ __device__ __forceinline__ double chunk8_dot64(const uint4* __restrict__ a, cons
     return s;
 }
 
+// Short rows (at most 16 chunks): the wave splits into 64/P groups of P
+// lanes (P = chunks rounded up to a power of two), one neighbour per group,
+// one chunk per lane, and each group sums by the same xor steps the
+// 64-lane tree takes once its upper steps have only added zeros: the same
+// FP64 value, with 64/P neighbours per pass instead of 4.
 template <typename T>
 __device__ __forceinline__ float wave_gram_dists64(const T* __restrict__ rows, int stride, int chunks, int u,
                                                    uint32_t pid, int K, const double* __restrict__ nrm64) {
     const int lane = lane_id();
     const T* a = rows + (size_t)u * stride;
     float mine = 0.f;
+    if (chunks <= 16) {
+        int P = 1;
+        while (P < chunks) P <<= 1;
+        const int Q = 64 / P, q = lane / P, c = lane & (P - 1);
+        for (int k0 = 0; k0 < K; k0 += Q) {
+            const uint32_t pb = (uint32_t)__shfl((int)pid, min(k0 + q, K - 1));   // whole wave
+            const T* b = rows + (size_t)pb * stride;
+            double s = 0.0;
+            if (c < chunks) s = chunk8_dot64(a, b, c, 0.0);
+            for (int o = P >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            const int j = lane - k0;   // lane k0 + j takes the sum of group j
+            const double t = __shfl(s, (j >= 0 && j < Q) ? j * P : 0);
+            if (j >= 0 && j < Q && lane < K) {
+                const float D = (float)((nrm64[u] + nrm64[pid]) - 2.0 * t);
+                mine = D > 0.f ? D : 0.f;
+            }
+        }
+        return mine;
+    }
     for (int k0 = 0; k0 < K; k0 += 4) {
         const T* b[4];
 #pragma unroll

@@ -75,8 +75,8 @@ __device__ __forceinline__ void wave_sync() {
 // Value of lane (lane ^ m). Distances inside a row of 16 lanes use DPP moves
 // in the vector ALU (quad permutations; row mirror i -> i^15 and half mirror
 // i -> i^7 within a row, composed: 4 = half mirror then quad reverse (i^7^3),
-// 8 = mirror then half mirror (i^15^7)); 16 and 32 go through the LDS
-// crossbar. m is a compile-time constant after the sorting loops unroll.
+// 8 = mirror then half mirror (i^15^7); 15 = the mirror alone); other
+// distances go through the LDS crossbar. m is a compile-time constant after the sorting loops unroll.
 __device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int m) {
     switch (m) {
         case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
@@ -89,6 +89,7 @@ __device__ __forceinline__ uint32_t xor_lanes(uint32_t x, int m) {
             const int y = __builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);          // row_mirror
             return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x141, 0xF, 0xF, false);             // row_half_mirror
         }
+        case 15: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);  // row_mirror
         default: return (uint32_t)__shfl_xor((int)x, m);
     }
 }
@@ -2936,6 +2937,227 @@ __global__ __launch_bounds__(256, 8) void k_merge(Views v) {
     }
 }
 
+// ---- merge with one 16-lane row per target (K <= 16)
+
+constexpr int kSegLanes = 16;
+
+// Value of lane (lane + r) mod 16 of the caller's 16-lane row (DPP row
+// rotation); r is a compile-time constant after unrolling.
+__device__ __forceinline__ uint32_t row_rot(uint32_t x, int r) {
+    switch (r) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x121, 0xF, 0xF, false);   // row_ror
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x122, 0xF, 0xF, false);
+        case 3: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x123, 0xF, 0xF, false);
+        case 4: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, false);
+        case 5: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x125, 0xF, 0xF, false);
+        case 6: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x126, 0xF, 0xF, false);
+        case 7: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x127, 0xF, 0xF, false);
+        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);
+        case 9: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x129, 0xF, 0xF, false);
+        case 10: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12A, 0xF, 0xF, false);
+        case 11: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12B, 0xF, 0xF, false);
+        case 12: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, false);
+        case 13: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12D, 0xF, 0xF, false);
+        case 14: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12E, 0xF, 0xF, false);
+        case 15: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12F, 0xF, 0xF, false);
+        default: return x;
+    }
+}
+
+// Ascending bitonic sort of 64-bit keys within segments of S lanes (equal
+// keys allowed).
+template <int S>
+__device__ __forceinline__ void seg_sort64(uint64_t& k) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= S; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t o = shfl_xor64(k, j);
+            const bool keep_min = (size == S || (lane & size) == 0) == ((lane & j) == 0);
+            k = keep_min ? (o < k ? o : k) : (k < o ? o : k);
+        }
+    }
+}
+
+// fold_sorted within each segment: the proposals q (ascending in the
+// segment), reversed, against the list lane by lane keep the S smallest keys
+// of both as a bitonic sequence, which the half-cleaners sort.
+template <int S>
+__device__ __forceinline__ void seg_fold(uint64_t q, uint64_t& key, uint32_t& pf) {
+    const uint64_t rk = shfl_xor64(q, S - 1);
+    if (rk < key) {
+        key = rk;
+        pf = kPosUnknown;
+    }
+#pragma unroll
+    for (int j = S >> 1; j > 0; j >>= 1) cmpx(key, pf, j, true);
+}
+
+// finish_merged_row for the segment of target p (act: the segment holds a
+// merged list): the same checks, positions, stores and count of entered
+// entries; returns that count in the segment's first lane, 0 elsewhere. The
+// check for an id held twice compares every lane of the segment with every
+// entered lane by rotation.
+__device__ __forceinline__ uint32_t finish_seg_row(const Views& v, int p, bool act, uint64_t key, uint32_t pf) {
+    constexpr int S = kSegLanes;
+    const int lane = lane_id(), sl = lane & (S - 1), g0 = lane & ~(S - 1), K = v.K;
+    const bool in = act && sl < K;
+    uint32_t base = 0u, npts = (uint32_t)v.N;
+    if (act && v.ds) {
+        const uint32_t ds = v.ds[p];
+        base = v.dsbase[ds];
+        npts = v.dsbase[ds + 1] - base;
+    }
+    const uint32_t id = (uint32_t)key;
+    const bool entered = in && pf == kPosUnknown;
+    const bool lost = in && id >= npts;
+    if (ballot(lost) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 512ull);
+    if (lost) pf = kNewBit;   // position 0: the build reports the error after this iteration
+    if (in && pf == kPosUnknown) pf = (v.ds ? base + id : v.permuted ? (uint32_t)v.posof[id] : id) | kNewBit;
+    const uint32_t tag = entered ? (id | 0x80000000u) : 0u;   // ids are below 2^31
+    bool twice = false;
+#pragma unroll
+    for (int r = 1; r < S; ++r) {
+        const uint32_t o = row_rot(tag, r);
+        twice |= in && (o >> 31) != 0u && (o & 0x7fffffffu) == id;
+    }
+    if (ballot(twice) && lane == 0) atomicOr((unsigned long long*)&v.counters[kCntError], 8ull);
+    if (in) {
+        const size_t row = (size_t)p * K;
+        v.lkey[row + sl] = key;
+        v.lpos[row + sl] = pf;
+        if (sl == K - 1) {
+            if (v.rk)
+                v.rk[p].kth = key;
+            else
+                v.kth[p] = key;
+        }
+    }
+    const uint32_t c = (uint32_t)__popcll((ballot(entered) >> g0) & ((1ull << S) - 1));
+    if (v.chg && act && sl == 0) v.chg[p] = c;   // batched form: changes per target
+    return act && sl == 0 ? c : 0u;
+}
+
+// k_merge with four targets per wave, one per 16-lane row (K <= 16): short
+// lists fill the wave and each target sorts its proposals 16 at a time within
+// its row (DPP moves, no LDS crossbar), so the vector work and the memory
+// latency of a wave are shared by four targets. The result is k_merge's: the K smallest distinct keys of
+// the list and of the proposals below the K-th key whose id is not in the
+// list as it was when the iteration began. Proposals are read, filtered and
+// folded S at a time; a chunk whose fold puts one key twice among the first
+// K is folded again from the list before it, with the chunk's keys that
+// repeat a neighbour or a list key (binary search in LDS) removed.
+__global__ __launch_bounds__(256, 8) void k_merge_seg(Views v) {
+    if (stopped(v)) return;
+    constexpr int S = kSegLanes, G = 64 / S;
+    constexpr uint64_t kSeg = (1ull << S) - 1;
+    __shared__ uint64_t s_k[kMergeWaves][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int sl = lane & (S - 1), g0 = lane & ~(S - 1), gi = lane / S;
+    const int K = v.K;
+    uint64_t changes = 0, props = 0, pairs = 0;   // per lane, summed over the wave at the end
+    for (int pb = (blockIdx.x * kMergeWaves + w) * G; pb < v.N; pb += gridDim.x * kMergeWaves * G) {
+        const int p = pb + gi;
+        uint32_t base = 0u, n = 0u;
+        if (p < v.N) {
+            base = bucket_lo(v, p);
+            n = min(v.pcnt[p], bucket_lo(v, p + 1) - base);
+            if (sl == 0) pairs += v.cap[p];   // e(u) of owner p: e_t without a scan
+        }
+        const bool hub = n > kHubProposals;   // its bucket cursor is cleared by k_merge_hubs
+        if (hub && sl == 0) {
+            const uint32_t slot = (uint32_t)atomicAdd((unsigned long long*)&v.counters[kCntHubs], 1ull);
+            v.hubs[slot] = (uint32_t)p;
+        }
+        const bool act = n > 0u && !hub;
+        if (ballot(act) == 0ull) continue;
+        if (act && sl == 0) v.pcnt[p] = 0u;   // bucket cursors start the next iteration at zero
+        const bool in = act && sl < K;
+        const size_t row = (size_t)p * K;
+        uint64_t key = in ? v.lkey[row + sl] : ~0ull;
+        uint32_t pf = in ? v.lpos[row + sl] : 0u;
+        // snapshot ids; 0x7fffffff in the lanes beyond K matches no id
+        const uint32_t snap = in ? (uint32_t)key : 0x7fffffffu;
+        uint64_t kth = shfl64(key, g0 + K - 1);
+        for (uint32_t c0 = 0;; c0 += S) {
+            if (ballot(act && c0 < n) == 0ull) break;
+            const uint64_t pk = act && c0 + (uint32_t)sl < n ? v.pkey[base + c0 + sl] : ~0ull;
+            // (a ^ b) - 1 has bit 31 set exactly when a == b (both below 2^31)
+            const uint32_t pid = (uint32_t)pk;
+            uint32_t hit = (snap ^ pid) - 1u;   // every lane of the row against every other, by rotation
+#pragma unroll
+            for (int r = 1; r < S; ++r) hit |= (row_rot(snap, r) ^ pid) - 1u;
+            const bool ok = pk < kth && (hit >> 31) == 0u;
+            if (ballot(ok) == 0ull) continue;
+            uint64_t q = ok ? pk : ~0ull;
+            seg_sort64<S>(q);
+            const uint64_t k0 = key;
+            const uint32_t f0 = pf;
+            seg_fold<S>(q, key, pf);
+            const uint64_t prevk = shfl64(key, sl > 0 ? lane - 1 : lane);
+            const uint64_t dm = ballot(sl > 0 && sl < K && key != ~0ull && prevk == key);
+            if (dm) {
+                const bool redo = ((dm >> g0) & kSeg) != 0ull;
+                uint64_t* sk = s_k[w];
+                sk[lane] = k0;
+                wave_sync();
+                int lo = 0;   // keys of the segment's list below q
+#pragma unroll
+                for (int st = S / 2; st > 0; st >>= 1) lo += sk[g0 + lo + st - 1] < q ? st : 0;
+                const uint64_t prevq = shfl64(q, sl > 0 ? lane - 1 : lane);
+                const bool keep = q != ~0ull && sk[g0 + lo] != q && !(sl > 0 && prevq == q);
+                const uint64_t km = ballot(keep);
+                wave_sync();
+                sk[lane] = ~0ull;
+                wave_sync();
+                if (keep) sk[g0 + __popcll(km & ((1ull << lane) - 1) & ~((1ull << g0) - 1))] = q;
+                wave_sync();
+                const uint64_t qd = sk[lane];
+                wave_sync();
+                uint64_t k2 = k0;
+                uint32_t f2 = f0;
+                seg_fold<S>(qd, k2, f2);
+                if (redo) {
+                    key = k2;
+                    pf = f2;
+                }
+            }
+            if (sl >= K) {
+                key = ~0ull;
+                pf = 0u;
+            }
+            kth = shfl64(key, g0 + K - 1);
+        }
+        changes += finish_seg_row(v, p, act, key, pf);
+        if (act && sl == 0) props += n;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        changes += shfl_xor64(changes, o);
+        props += shfl_xor64(props, o);
+        pairs += shfl_xor64(pairs, o);
+    }
+    // per-block partial sums (no same-address atomics); summed by k_finish_counters
+    __shared__ uint64_t s_red[kMergeWaves][3];
+    if (lane == 0) {
+        s_red[w][0] = changes;
+        s_red[w][1] = props;
+        s_red[w][2] = pairs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0, c = 0;
+        for (int i = 0; i < kMergeWaves; ++i) {
+            a += s_red[i][0];
+            b += s_red[i][1];
+            c += s_red[i][2];
+        }
+        v.partial[3 * blockIdx.x] = a;
+        v.partial[3 * blockIdx.x + 1] = b;
+        v.partial[3 * blockIdx.x + 2] = c;
+    }
+}
+
 // Counters of an iteration, by one workgroup of 1024 threads after the
 // merge kernels have written their partial sums: c_t, proposals and e_t added
 // up; after the iteration's last merge (last != 0; every block of a
@@ -3033,7 +3255,12 @@ __global__ __launch_bounds__(1024) void k_merge_hubs(Views v) {
 }
 
 void launch_merge(const Views& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge, dim3(kMergeBlocks), dim3(256), 0, s, v);
+    // rows of 16 lanes for short lists; at larger K one wave per target
+    // sorts more proposals at once, which measured faster there
+    if (v.K <= kSegLanes)
+        hipLaunchKernelGGL(k_merge_seg, dim3(kMergeBlocks), dim3(256), 0, s, v);
+    else
+        hipLaunchKernelGGL(k_merge, dim3(kMergeBlocks), dim3(256), 0, s, v);
     hipLaunchKernelGGL(k_merge_hubs, dim3(kHubBlocks), dim3(1024), 0, s, v);
 }
 

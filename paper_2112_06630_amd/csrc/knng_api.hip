@@ -199,16 +199,19 @@ knng_status make_plan(int64_t N, int32_t d, const knng_params* p, Plan& P, bool 
     }
     // counting-sort reverse bucketing: super-buckets of 2^shift positions, at
     // most kRevMaxS of them, blocks of E entries (at most 1024 blocks). The
-    // shift grows while a block's run into one super-bucket averages under 32
-    // entries (512 B: shorter runs are written as partial lines) and at
-    // least 256 super-buckets remain (one workgroup each in k_rev_bucket).
+    // shift grows while a block's run into one super-bucket averages under 8
+    // entries (128 B: shorter runs are written as partial lines) and at least
+    // 256 super-buckets remain (one workgroup each in k_rev_bucket). Smaller
+    // super-buckets keep the region each k_rev_bucket workgroup scatters into
+    // small enough for its lines to fill in L2 (at 4M points and K = 15:
+    // 2^9 positions, about 120 KB per workgroup, against 480 KB at 2^11).
     P.rev_S = 0;
     int64_t E = 4096;
     while ((int64_t)(NK + E - 1) / E > 1024) E *= 2;
     for (int sh = 8; sh <= kRevMaxShift; ++sh) {
         const int64_t S = (N + (1LL << sh) - 1) >> sh;
         const int64_t S2 = (N + (2LL << sh) - 1) >> (sh + 1);
-        if (sh < kRevMaxShift && E < 32 * S && S2 >= 256) continue;
+        if (sh < kRevMaxShift && E < 8 * S && S2 >= 256) continue;
         if (S <= kRevMaxS) {
             P.rev_shift = sh;
             P.rev_S = (int)S;

@@ -152,9 +152,9 @@ def _samples_equal(ctx, sm_arrays):
 def test_blobs4m_oracle_step(knng):
     """4M x 3 low-d blobs at full size, in the launch configuration the bench
     times (AUTO: direct form): one GPU iteration from the oracle's G_0 against
-    its G_1 -- sampled sets integer-exact (the counting-sort reverse lists at
-    their widest super-buckets), e_1 exact, ids equal except at ties within
-    1e-5 relative."""
+    its G_1 -- sampled sets integer-exact (the counting-sort reverse lists
+    over super-buckets of 2^9 positions, some 7800 of them), e_1 exact, ids
+    equal except at ties within 1e-5 relative."""
     X, p = synth.workload("blobs4m_d3")
     K, rho, seed = p["K"], p["rho"], p["seed"]
     C = oracle.cap(K, rho)

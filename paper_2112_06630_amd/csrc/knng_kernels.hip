@@ -112,6 +112,31 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Value of another lane of the caller's 16-lane row, r lanes away with
+// wrap-around (DPP row rotation): r = 1 .. 15 visit every other lane of the
+// row once. r is a compile-time constant after unrolling. Callers that need
+// to know which lane a value came from rotate the lane index alongside.
+__device__ __forceinline__ uint32_t row_rot(uint32_t x, int r) {
+    switch (r) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x121, 0xF, 0xF, false);   // row_ror
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x122, 0xF, 0xF, false);
+        case 3: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x123, 0xF, 0xF, false);
+        case 4: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, false);
+        case 5: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x125, 0xF, 0xF, false);
+        case 6: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x126, 0xF, 0xF, false);
+        case 7: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x127, 0xF, 0xF, false);
+        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);
+        case 9: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x129, 0xF, 0xF, false);
+        case 10: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12A, 0xF, 0xF, false);
+        case 11: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12B, 0xF, 0xF, false);
+        case 12: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, false);
+        case 13: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12D, 0xF, 0xF, false);
+        case 14: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12E, 0xF, 0xF, false);
+        case 15: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12F, 0xF, 0xF, false);
+        default: return x;
+    }
+}
+
 // One compare-exchange step of a bitonic network across the wave: lanes
 // lane and lane^j exchange; an ascending block keeps the smaller key in its
 // lower lane. Equal keys are left in place.
@@ -646,8 +671,86 @@ __global__ __launch_bounds__(256) void k_init(Views v, uint64_t st, int mode) {
     }
 }
 
+// k_init for lists of at most 16 entries with direct-form distances: four
+// points per wave, one per 16-lane row. Each row draws 16 ids at a time in
+// draw order (the first K distinct draws are the same as k_init's 64 at a
+// time), every lane then computes its entry's distance, and the entry's rank
+// in the row comes from comparing keys around the row by rotation.
+__global__ __launch_bounds__(256) void k_init_rows(Views v, uint64_t st) {
+    __shared__ uint32_t s_sel[kRowWaves][64];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int sl = lane & 15, g0 = lane & ~15;
+    const int K = v.K;
+    uint32_t* sel = &s_sel[w][g0];
+    for (int pb = (blockIdx.x * kRowWaves + w) * 4; pb < v.N; pb += gridDim.x * kRowWaves * 4) {
+        const int u = pb + (lane >> 4);
+        const bool valid = u < v.N;
+        // ids are local to the dataset (the whole build for a single one)
+        uint32_t base = 0, n = (uint32_t)v.N;
+        uint64_t sti = st;
+        if (valid && v.ds) {
+            const uint32_t i = v.ds[u];
+            base = v.dsbase[i];
+            n = v.dsbase[i + 1] - base;
+            sti = v.st_init[i];
+        }
+        const uint32_t ul = (uint32_t)u - base;
+        int have = valid ? 0 : K;
+        for (uint32_t b0 = 0; ballot(have < K) != 0ull; b0 += 16) {
+            const uint32_t j = b0 + (uint32_t)sl;
+            const uint64_t h = mix64(sti ^ (((uint64_t)ul << 32) | j));
+            uint32_t c = (uint32_t)(((h >> 32) * (uint64_t)(n - 1)) >> 32);
+            c += (c >= ul) ? 1u : 0u;
+            c += base;
+            bool novel = have < K;
+            for (int i = 0; i < have; ++i) novel &= (sel[i] != c);
+#pragma unroll
+            for (int r = 1; r < 16; ++r) {   // an equal draw in a lower lane of the row comes first
+                const uint32_t o = row_rot(c, r);
+                const uint32_t ol = row_rot((uint32_t)sl, r);
+                novel &= !(ol < (uint32_t)sl && o == c);
+            }
+            const uint64_t m = (ballot(novel) >> g0) & 0xffffull;
+            const int rk = __popcll(m & ((1ull << sl) - 1));
+            wave_sync();
+            if (novel && have + rk < K) sel[have + rk] = c;
+            wave_sync();
+            have = min(K, have + __popcll(m));
+        }
+        const bool in = valid && sl < K;
+        const uint32_t pid = in ? sel[sl] : 0u;
+        wave_sync();
+        uint64_t key = ~0ull;
+        if (in) {
+            const float* a = v.Xp + (size_t)u * v.dp;
+            const float* b = v.Xp + (size_t)pid * v.dp;
+            const float D = v.Xb ? dist_rescore(a, b, v.dp) : dist_direct(a, b, v.dp);
+            key = key_of(D, (uint32_t)v.orig[pid]);
+        }
+        int rank = 0;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            const uint32_t lo = row_rot((uint32_t)key, r), hi = row_rot((uint32_t)(key >> 32), r);
+            rank += ((((uint64_t)hi << 32) | lo) < key) ? 1 : 0;
+        }
+        if (in) {
+            v.lkey[(size_t)u * K + rank] = key;
+            v.lpos[(size_t)u * K + rank] = pid | kNewBit;
+            if (rank == K - 1) {   // the joins read the record when there is one
+                if (v.rk)
+                    v.rk[u].kth = key;
+                else
+                    v.kth[u] = key;
+            }
+        }
+    }
+}
+
 void launch_init(const Views& v, uint64_t st_init, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(grid_for(v.N, kRowWaves, 65536)), dim3(256), 0, s, v, st_init, mode);
+    if (mode == kDistDirect && v.K <= 16)
+        hipLaunchKernelGGL(k_init_rows, dim3(grid_for((v.N + 3) / 4, kRowWaves, 65536)), dim3(256), 0, s, v, st_init);
+    else
+        hipLaunchKernelGGL(k_init, dim3(grid_for(v.N, kRowWaves, 65536)), dim3(256), 0, s, v, st_init, mode);
 }
 
 // Load a caller state: ids are original ids (positions equal ids before any
@@ -2940,29 +3043,6 @@ __global__ __launch_bounds__(256, 8) void k_merge(Views v) {
 // ---- merge with one 16-lane row per target (K <= 16)
 
 constexpr int kSegLanes = 16;
-
-// Value of lane (lane + r) mod 16 of the caller's 16-lane row (DPP row
-// rotation); r is a compile-time constant after unrolling.
-__device__ __forceinline__ uint32_t row_rot(uint32_t x, int r) {
-    switch (r) {
-        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x121, 0xF, 0xF, false);   // row_ror
-        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x122, 0xF, 0xF, false);
-        case 3: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x123, 0xF, 0xF, false);
-        case 4: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, false);
-        case 5: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x125, 0xF, 0xF, false);
-        case 6: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x126, 0xF, 0xF, false);
-        case 7: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x127, 0xF, 0xF, false);
-        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);
-        case 9: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x129, 0xF, 0xF, false);
-        case 10: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12A, 0xF, 0xF, false);
-        case 11: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12B, 0xF, 0xF, false);
-        case 12: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, false);
-        case 13: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12D, 0xF, 0xF, false);
-        case 14: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12E, 0xF, 0xF, false);
-        case 15: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12F, 0xF, 0xF, false);
-        default: return x;
-    }
-}
 
 // Ascending bitonic sort of 64-bit keys within segments of S lanes (equal
 // keys allowed).

@@ -385,6 +385,23 @@ def test_max_K(knng, path, N, d, K, rho, hi, seed):
     exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 6, seed, path=path)
 
 
+@pytest.mark.parametrize("path,N,d,K,rho,hi,seed", [
+    ("valu", 500, 2, 3, 1.0, 6, 21),
+    ("valu", 500, 2, 2, 1.0, 6, 22),
+    ("valu", 600, 2, 16, 1.0, 5, 23),
+    ("valu", 600, 2, 17, 1.0, 5, 24),
+    ("valu", 700, 3, 16, 0.5, 4, 25),
+    ("bf16x3", 500, 40, 16, 1.0, 3, 26),
+])
+def test_merge_row_boundary(knng, path, N, d, K, rho, hi, seed):
+    """Lists of up to 16 entries are merged four to a wave, one per 16-lane
+    row; K = 2 and 3 leave most of a row empty, K = 16 fills it (no spare lane
+    for a repeated proposal), K = 17 takes one wave per target. Small integer
+    coordinates make many equal distances and many pairs proposed by several
+    owners."""
+    exact_build(knng, synth.integer_points(N, d, hi, seed), K, rho, 0.001, 8, seed, path=path)
+
+
 @pytest.mark.parametrize("T", [1, 2, 3])
 @pytest.mark.parametrize("path", ["valu", "bf16x3"])
 def test_iteration_cap(knng, T, path):

@@ -465,27 +465,30 @@ __device__ __forceinline__ float chunk8_dot(const uint4* __restrict__ a, const u
 
 // Gram-form distances of row u to the K rows pid (lane k < K holds pid of
 // neighbour k), the wave streaming each row: lane l takes the 8-dimension
-// chunks l, l + 64, ..., four rows at a time; each row's lane sums are added
-// by a fixed xor tree. Returns lane k's distance. T = float4 (FP32 rows,
+// chunks l, l + 64, ..., R rows at a time (byte rows: ten, so that K = 20
+// takes two passes with more rows in flight; the value of each row does not
+// depend on R); each row's lane sums are added by a fixed xor tree. Returns lane k's distance. T = float4 (FP32 rows,
 // `stride` = d_pad / 4) or uint4 (one-plane BF16 rows, exact products,
 // `stride` = d_pad / 8); `chunks` = d_pad / 8 either way.
-template <typename T>
+template <typename T, int R = 4>
 __device__ __forceinline__ float wave_gram_dists(const T* __restrict__ rows, int stride, int chunks, int u,
                                                  uint32_t pid, int K, const float* __restrict__ nrm) {
     const int lane = lane_id();
     const T* a = rows + (size_t)u * stride;
     float mine = 0.f;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const T* b[4];
+    for (int k0 = 0; k0 < K; k0 += R) {
+        const T* b[R];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * stride;
-        float s[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < R; ++q) b[q] = rows + (size_t)rl32(pid, min(k0 + q, K - 1)) * stride;
+        float s[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) s[q] = 0.f;
         for (int c = lane; c < chunks; c += 64) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s[q] = chunk8_dot(a, b[q], c, s[q]);
+            for (int q = 0; q < R; ++q) s[q] = chunk8_dot(a, b[q], c, s[q]);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < R; ++q) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o);
             if (lane == k0 + q) {
@@ -592,8 +595,8 @@ __device__ __forceinline__ void finish_row(const Views& v, int u, uint32_t pid, 
     } else if (mode == kDistGram) {   // whole wave
         const bool plane = v.Xs && v.planes == 1;
         if (v.u8)
-            Dg = wave_gram_dists(reinterpret_cast<const uint2*>(v.Xs + (size_t)v.N * v.dp), v.dp >> 3, v.dp >> 3, u,
-                                 pid, K, v.nrm);
+            Dg = wave_gram_dists<uint2, 10>(reinterpret_cast<const uint2*>(v.Xs + (size_t)v.N * v.dp), v.dp >> 3,
+                                            v.dp >> 3, u, pid, K, v.nrm);
         else if (v.acc && plane)
             Dg = wave_gram_dists64(reinterpret_cast<const uint4*>(v.Xs), v.dp >> 3, v.dp >> 3, u, pid, K, v.nrm64);
         else if (v.acc)

@@ -16,6 +16,8 @@
 #include <vector>
 #include <cstring>
 #include <mutex>
+#include <array>
+#include <cstddef>
 #include <string>
 
 #include "knng.h"
@@ -318,6 +320,8 @@ Views carve(const Plan& P, int64_t N, int32_t d, int K, void* ws) {
 
 }  // namespace
 
+constexpr int kNumEvents = 13;
+
 struct knng_ctx {
     Views v;
     Plan plan;
@@ -332,7 +336,8 @@ struct knng_ctx {
     int perm_levels;
     bool has_graph;
     knng_stats stats;
-    hipEvent_t ev[10];   // phase events of odd (0..3) and even (6..9) iterations; 4, 5: permutation
+    hipEvent_t ev[kNumEvents];   // phase events of odd (0..3) and even (6..9) iterations; 4, 5: permutation;
+                                 // 10..12: start, end of init, end of the build
     uint64_t hc[kNumCounters];
     uint64_t* hslot;     // pinned: the counters of iteration t at hslot[t * kNumCounters]
     uint64_t* dslot;     // the same memory as the device addresses it (allocation-free
@@ -374,6 +379,50 @@ bool slot_take(uint64_t** host, uint64_t** dev) {
 void slot_give(uint64_t* host, uint64_t* dev) {
     std::lock_guard<std::mutex> lk(g_slot_mu);
     g_slot_free.emplace_back(host, dev);
+}
+
+// Phase events, kept for reuse across contexts like the slots (per device:
+// an event records only on streams of the device it was created on).
+std::mutex g_ev_mu;
+std::vector<std::pair<int, std::array<hipEvent_t, kNumEvents>>> g_ev_free;   // {device, events}
+
+bool events_take(hipEvent_t (&ev)[kNumEvents]) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        for (size_t i = g_ev_free.size(); i-- > 0;) {
+            if (g_ev_free[i].first != dev) continue;
+            for (int k = 0; k < kNumEvents; ++k) ev[k] = g_ev_free[i].second[k];
+            g_ev_free.erase(g_ev_free.begin() + (std::ptrdiff_t)i);
+            return true;
+        }
+    }
+    for (auto& e : ev) e = nullptr;
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            for (auto& f : ev) f = nullptr;
+            return false;
+        }
+    }
+    return true;
+}
+
+void events_give(hipEvent_t (&ev)[kNumEvents]) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    } else {
+        std::array<hipEvent_t, kNumEvents> a;
+        for (int k = 0; k < kNumEvents; ++k) a[k] = ev[k];
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        g_ev_free.emplace_back(dev, a);
+    }
+    for (auto& e : ev) e = nullptr;
 }
 
 knng_status read_counters(knng_ctx* c) {
@@ -584,19 +633,10 @@ knng_status scratch_base(char** out) {
 // init, iterations until the stop rule or max_iters, write-out (the body of
 // both build entry points). Events only when the context has them.
 knng_status run_build(knng_ctx* c, const knng_params* params, int32_t* d_ids, float* d_dists, knng_stats* stats) {
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-    if (!c->noalloc &&
-        (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess)) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        return fail(KNNG_EDEVICE, "hipEventCreate failed");
-    }
-    auto done = [&](knng_status st) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        if (e2) (void)hipEventDestroy(e2);
-        return st;
-    };
+    hipEvent_t e0 = c->noalloc ? nullptr : c->ev[10];
+    hipEvent_t e1 = c->noalloc ? nullptr : c->ev[11];
+    hipEvent_t e2 = c->noalloc ? nullptr : c->ev[12];
+    auto done = [](knng_status st) { return st; };
     if (e0) (void)hipEventRecord(e0, c->stream);
     knng_status s = knng_init_graph(c);
     if (s != KNNG_OK) return done(s);
@@ -679,8 +719,7 @@ knng_status ctx_init(knng_ctx* c, const Plan& P, const float* dX, int64_t N, int
         c->noalloc = true;
         c->dslot = dev_slots;
     } else {
-        for (auto& e : c->ev)
-            if (hipEventCreate(&e) != hipSuccess) return fail(KNNG_EDEVICE, "hipEventCreate failed");
+        if (!events_take(c->ev)) return fail(KNNG_EDEVICE, "hipEventCreate failed");
         if (!slot_take(&c->hslot, &c->dslot))
             return fail(KNNG_EDEVICE, "pinned counter slots: hipHostMalloc failed");
     }
@@ -715,18 +754,15 @@ knng_status ctx_init(knng_ctx* c, const Plan& P, const float* dX, int64_t N, int
     return KNNG_OK;
 }
 
-// Returns what ctx_init took: pinned slots (after the stream has drained)
-// and events.
+// Returns what ctx_init took: pinned slots and events (after the stream has
+// drained), to the pools.
 void ctx_release(knng_ctx* c) {
+    if (c->hslot || c->ev[0]) (void)hipStreamSynchronize(c->stream);   // no kernel writes the slots or records the events any more
     if (c->hslot) {
-        (void)hipStreamSynchronize(c->stream);   // no kernel of this context writes the slots any more
         slot_give(c->hslot, c->dslot);
         c->hslot = nullptr;
     }
-    for (auto& e : c->ev) {
-        if (e) (void)hipEventDestroy(e);
-        e = nullptr;
-    }
+    if (c->ev[0]) events_give(c->ev);
 }
 
 }  // namespace
